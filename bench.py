@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the clause test on one MI355X, at the paper's scale.
+
+Workload (default): 4,000,000 clauses over 1,000,000 variables with the length
+mix 50% in [2,10], 40% in [11,50], 10% in [51,300]; 1024 assignment slots (16
+words) with an assigned fraction uniform in [0.3, 0.9] per slot; planted hits at
+rate 1e-5; between rounds 5% of the variables flip (T <-> F in every slot).
+
+One step = one round of the hot path: the round's delta (new values of the
+flipped variables, already resident in HBM) is packed into the bitplanes, then
+every live clause is tested against every active slot and the reports are
+compacted in HBM (count read back).  value = clauses x slots tested per second.
+
+The JSON line also carries the roofline of the test kernel (algorithmic bytes per
+launch over its HIP-event duration, against 8 TB/s) and the oracle's rate on the
+host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_test_paper_4Mx1024_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2012_03119_amd", "csrc", "test.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def make_workload(args):
+    from paper_2012_03119_amd import gen
+    if args.workload == "tiny":
+        return gen.tiny(args.seed), "plain test, tiny: 20k clauses x 2k vars, 64 assignments"
+    w = gen.paper(args.seed, n_clauses=args.clauses, n_vars=args.vars, n_slots=args.slots)
+    desc = (f"plain test, paper scale: {args.clauses} clauses x {args.vars} vars, {args.slots} assignments, "
+            f"length mix 50%[2,10] 40%[11,50] 10%[51,300], 5% variable flips per round")
+    return w, desc
+
+
+def stage_rounds(w, n_rounds, seed, torch):
+    """Per round, the flipped variables and their new values (var-major), on the GPU."""
+    from paper_2012_03119_amd import gen
+    vals = w.values.copy()
+    rounds = []
+    for flip in gen.flip_rounds(seed + 1000, w.n_vars, n_rounds + 1):
+        gen.apply_flips(vals, flip)
+        delta = np.ascontiguousarray(vals[:, flip - 1].T)
+        rounds.append((flip.astype(np.uint32), torch.from_numpy(delta).cuda()))
+    return rounds
+
+
+def cpu_baseline(w, seconds):
+    """The oracle, untuned, on the host cores, over a bounded sample of clauses."""
+    import oracle
+    vm = oracle.transpose(w.values)
+
+    def run(n):
+        lits = w.lits[: w.offsets[n]]
+        offs = w.offsets[: n + 1]
+        t0 = time.perf_counter()
+        oracle.masks(lits, offs, values_vm=vm)
+        return time.perf_counter() - t0
+
+    n = min(w.n_clauses, 2000)
+    t = run(n)
+    n2 = int(min(w.n_clauses, max(n, n * seconds / max(t, 1e-6))))
+    if n2 > n:
+        n, t = n2, run(n2)
+    rate = n * w.n_slots / t
+    return {"value": rate, "unit": "tests/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"first {n} of {w.n_clauses} clauses x {w.n_slots} assignments (round 0), "
+                      f"{t:.1f} s; var-major transpose of the values not timed"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["paper", "tiny"], default="paper")
+    ap.add_argument("--clauses", type=int, default=4_000_000)
+    ap.add_argument("--vars", type=int, default=1_000_000)
+    ap.add_argument("--slots", type=int, default=1024)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--hot-vars", type=int, default=0)
+    ap.add_argument("--no-early-exit", action="store_true")
+    ap.add_argument("--trigger", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration for profiles)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(the clause test shards by clause, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2012_03119_amd import gss
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {n} bytes 3 times")
+        return
+
+    t0 = time.perf_counter()
+    w, desc = make_workload(args)
+    log(f"workload ready in {time.perf_counter() - t0:.1f} s: {w.n_clauses} clauses, {len(w.lits)} literals")
+    need_rounds = args.warmup + args.steps if args.workload == "paper" else 0
+    rounds = stage_rounds(w, min(need_rounds, 19), args.seed, torch) if need_rounds else []
+
+    flags = 0
+    if args.no_early_exit:
+        flags |= gss.GSS_TEST_NO_EARLY_EXIT
+    if args.trigger:
+        flags |= gss.GSS_TEST_TRIGGER
+    ctx = gss.Context(w.n_vars, w.n_slots, hot_vars=args.hot_vars, report_capacity=1 << 20)
+    t0 = time.perf_counter()
+    ctx.add_clauses(w.lits, w.offsets)
+    log(f"clauses stored in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    ctx.set_assignments(0, w.values)
+    log(f"assignments packed in {time.perf_counter() - t0:.1f} s")
+
+    def step(i):
+        if rounds:
+            vs, delta = rounds[i % len(rounds)]
+            ctx.set_var_values(0, vs, delta)
+        return ctx.test(flags)
+
+    for i in range(args.warmup):
+        n_rep = step(i)
+    log(f"warmup done ({args.warmup} steps), {n_rep} reports per test")
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        n_rep = step(args.warmup + i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = ctx.stats()
+    ms_per_step = elapsed * 1e3 / args.steps
+    pairs = st["last_pairs"]
+    value = pairs / (elapsed / args.steps)
+    kernel_ms = st["total_kernel_ms"] / max(1, st["timed_launches"])
+
+    W = w.n_slots // 64
+    table_bytes = 2 * (w.n_vars + 1) * W * 8
+    alg_bytes = 4 * st["last_literals"] + 8 * st["live_clauses"] + table_bytes + 16 * st["last_reports"]
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_sha256_16") == kernel_hash() and tr.get("config") == desc:
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "gss::k_test", "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes,
+                "alg_bytes": "4 B per stored literal + 8 B per clause (length, id) + plane table once "
+                             "(2 rows x W words x 8 B per variable) + 16 B per report"}
+    log(f"{args.steps} steps: {ms_per_step:.3f} ms/step, test kernel {kernel_ms:.3f} ms, "
+        f"{value / 1e12:.2f} T tests/s, {achieved:.0f} GB/s algorithmic, {n_rep} reports")
+
+    out = {
+        "metric": "clause x assignment tests/sec", "value": value, "unit": "tests/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": desc, "clauses": w.n_clauses, "vars": w.n_vars, "assignments": w.n_slots,
+                   "seed": args.seed, "flags": flags, "hot_vars": args.hot_vars,
+                   "reports_per_test": n_rep, "gpu": torch.cuda.get_device_name(0)},
+        "roofline": roofline,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * gss.h -- C ABI of the MI355X clause-test library (libgss.so).
+ *
+ * The library keeps a database of clauses and a set of up to `max_slots` partial
+ * assignments resident in GPU memory and finds every (clause, assignment) pair in
+ * which the clause is falsified: each of its literals is F under the assignment.
+ * This is the test at the heart of GpuShareSat (Section 3.4 and its listing of the
+ * bitwise trigger test; Section 3.5 for running it on millions of clauses at
+ * once), restricted to the conflict half of Definition 1 (Section 3.3); the full
+ * trigger predicate is available as a flag.
+ *
+ * The calls follow the paper's description of the exchange (Section 3.6): solver
+ * threads export clauses (gss_add_clauses), send assignments (gss_set_assignments
+ * and the delta calls), the GPU tests every clause against every assignment it
+ * holds and reports the hits (gss_test, gss_fetch_reports), and clauses leave the
+ * GPU again (gss_remove_clauses, Section 3.7 on deleting GPU clauses).
+ *
+ * Conventions for every call:
+ *  - Return value: GSS_OK (0) or a negative gss_status.  No exception, abort or
+ *    longjmp crosses this interface.  After an error, gss_last_error() holds a
+ *    message.  Errors detected while validating arguments leave the context
+ *    unchanged (validate, then apply).  GSS_ERR_DEVICE means a HIP call failed;
+ *    the context may then be unusable and should be destroyed.
+ *  - Input arrays are owned by the caller and are not retained after the call
+ *    returns.  Unless a call says otherwise they are host memory.  Calls marked
+ *    "host or device" also accept device pointers (detected with
+ *    hipPointerGetAttributes); device inputs must stay valid until the call returns.
+ *  - A context is not thread-safe: one thread drives it, like the single GPU
+ *    manager thread of the paper's solver (Section 5).  Work is issued on the
+ *    context's stream; calls that return results synchronise that stream.
+ *  - Literals are DIMACS signed int32: variable v in 1..num_vars, -v its negation.
+ *  - Truth values are int8: +1 = T, -1 = F, 0 = U (Section 3.1).
+ *  - Assignment slots are numbered 0..max_slots-1; slot s is bit s%64 of word s/64.
+ */
+#ifndef GSS_H
+#define GSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gss_status;
+
+#define GSS_OK 0
+#define GSS_ERR_INVALID_ARG (-1)     /* null pointer, empty clause, bad value, bad range, bad flag */
+#define GSS_ERR_BAD_LITERAL (-2)     /* literal 0 or |literal| > num_vars */
+#define GSS_ERR_UNKNOWN_ID (-3)      /* clause id never issued, already removed, or repeated */
+#define GSS_ERR_CAPACITY (-4)        /* slot range, id space or HBM budget exhausted */
+#define GSS_ERR_REPORT_OVERFLOW (-5) /* more hits than report capacity; count is still exact */
+#define GSS_ERR_DEVICE (-6)          /* a HIP runtime call failed */
+#define GSS_ERR_STATE (-7)           /* call not valid now (e.g. fetch before any test) */
+
+typedef struct gss_ctx gss_ctx;
+
+/* One hit record: clause `clause_id` is falsified by slot 64*word + b for every
+ * set bit b of `mask` (Section 4.3 reports a clause to the owner of a group with
+ * the mask of hits inside the group; here a group is one 64-slot word).
+ * 16 bytes, naturally aligned. */
+typedef struct gss_report {
+    uint32_t clause_id;
+    uint32_t word;
+    uint64_t mask;
+} gss_report;
+
+/* Device allocator hooks: a caller that manages device memory (for instance a
+ * framework's caching allocator) can route every device allocation of the
+ * context through them.  Both NULL: the library uses hipMalloc/hipFree.
+ * dev_alloc returns NULL on failure. */
+typedef void *(*gss_dev_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*gss_dev_free_fn)(void *ptr, void *stream, void *user);
+
+typedef struct gss_config {
+    uint32_t num_vars;          /* variables 1..num_vars (>= 1) */
+    uint32_t max_slots;         /* assignment capacity: multiple of 64, 64..4096 (W = max_slots/64 words) */
+    uint64_t hbm_budget_bytes;  /* cap on the context's device memory; 0 = no cap */
+    uint64_t report_capacity;   /* initial report buffer entries (grown by gss_test unless GSS_TEST_NO_REGROW) */
+    void *stream;               /* borrowed hipStream_t; NULL = the context creates its own */
+    gss_dev_alloc_fn dev_alloc; /* optional, see above */
+    gss_dev_free_fn dev_free;
+    void *alloc_user;
+    uint32_t hot_vars;          /* LDS staging: rows of variables 1..hot_vars are kept in LDS (0 = off) */
+    uint32_t reserved;
+} gss_config;
+
+/* Creates a context on the current HIP device.  Planes start all-Undef and no slot
+ * is active.  *out receives the context (NULL on error; then use the return code). */
+gss_status gss_create(const gss_config *cfg, gss_ctx **out);
+
+/* Releases every device and host resource of the context.  NULL is accepted. */
+void gss_destroy(gss_ctx *ctx);
+
+/* Message describing the last error of this context ("" if none).  With ctx NULL,
+ * the last error of a failed gss_create on this thread. */
+const char *gss_last_error(const gss_ctx *ctx);
+
+/* Adds n clauses (Section 3.6: every learned clause is exported to the GPU).
+ * Clause i is lits[offsets[i] .. offsets[i+1]), host memory, offsets has n+1
+ * entries and is non-decreasing.  Each clause needs at least one literal
+ * (an empty clause is GSS_ERR_INVALID_ARG) and at most 65536.  Repeated literals
+ * and tautologies are accepted and kept as given (literal order is not kept).
+ * out_ids[i] (host, n entries) receives the clause's id: ids are issued
+ * sequentially from 0 and never reused within a context.
+ * Errors: INVALID_ARG, BAD_LITERAL, CAPACITY (id space or HBM budget), DEVICE. */
+gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const uint64_t *offsets, uint32_t n,
+                           uint32_t *out_ids);
+
+/* Removes n clauses by id (Section 3.7: the GPU deletes clauses as well).  Every
+ * id must be live and appear once, else GSS_ERR_UNKNOWN_ID and nothing is
+ * removed.  Storage is reclaimed by compaction when a length class holds more
+ * than a quarter dead slots. */
+gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint32_t n);
+
+/* Number of live clauses, the next id to be issued, and the context's device bytes. */
+gss_status gss_store_info(const gss_ctx *ctx, uint64_t *live_clauses, uint64_t *next_id, uint64_t *device_bytes);
+
+/* Sets assignments into slots first_slot .. first_slot+n_slots-1 and marks them
+ * active (Section 3.6: the parent assignment of a conflict is sent to the GPU).
+ * values: slot-major int8 [n_slots][num_vars] (entry [s][v-1] is the value of
+ * variable v in slot first_slot+s), host or device memory.  Values outside
+ * {-1, 0, +1}: INVALID_ARG.  Range beyond max_slots: CAPACITY. */
+gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, const int8_t *values);
+
+/* Delta update: new values of n_vars variables in slots first_slot ..
+ * first_slot+n_slots-1; other variables and slots are unchanged.  vars: host
+ * array of distinct variable numbers (1..num_vars).  values: var-major int8
+ * [n_vars][n_slots], host or device.  The slots must already be active. */
+gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, uint32_t n_vars,
+                              const uint32_t *vars, const int8_t *values);
+
+/* Makes slots first_slot .. first_slot+n_slots-1 inactive and all-Undef.  Tests
+ * report nothing for inactive slots (Section 3.5 tests up to a fixed number of
+ * assignments per run; a freed slot can take the next assignment). */
+gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots);
+
+/* Flags of gss_test. */
+#define GSS_TEST_FALSIFIED 0u         /* default: every literal F */
+#define GSS_TEST_TRIGGER 1u           /* Definition 1: no literal T and at most one not F */
+#define GSS_TEST_NO_EARLY_EXIT 2u     /* read every literal (no wavefront early exit) */
+#define GSS_TEST_SORTED 4u            /* order reports by (clause_id, word) */
+#define GSS_TEST_DENSE 8u             /* write one mask row per clause id (see gss_fetch_masks); no reports */
+#define GSS_TEST_NO_REGROW 16u        /* on overflow return GSS_ERR_REPORT_OVERFLOW instead of growing */
+#define GSS_TEST_NO_HOT 32u           /* do not stage hot-variable rows in LDS */
+
+/* Tests every live clause against every active slot (Section 3.6: a GPU run tests
+ * all clauses against all assignments not yet tested and reports every hit).
+ * *out_n_reports receives the number of gss_report records (one per clause and
+ * 64-slot word with at least one hit; 0 with GSS_TEST_DENSE).  If the report
+ * buffer is too small it is grown within the HBM budget and the test repeated,
+ * unless GSS_TEST_NO_REGROW: then GSS_ERR_REPORT_OVERFLOW is returned, the first
+ * report_capacity records are kept and *out_n_reports holds the exact count.
+ * Record order is unspecified unless GSS_TEST_SORTED. */
+gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_reports);
+
+/* Copies the records of the last gss_test into out (host or device, room for cap
+ * records).  *out_n receives the number copied: min(cap, records available).
+ * GSS_ERR_STATE before the first test. */
+gss_status gss_fetch_reports(gss_ctx *ctx, gss_report *out, uint64_t cap, uint64_t *out_n);
+
+/* After a gss_test with GSS_TEST_DENSE: copies the mask rows of n clause ids into
+ * out (host or device, uint64 [n][W], W = max_slots/64).  Removed ids give zero
+ * rows; ids never issued are GSS_ERR_UNKNOWN_ID. */
+gss_status gss_fetch_masks(gss_ctx *ctx, const uint32_t *ids, uint32_t n, uint64_t *out);
+
+/* Counters and timings of the context. */
+typedef struct gss_stats {
+    uint64_t tests_run;         /* gss_test calls that launched kernels */
+    uint64_t last_pairs;        /* live clauses x active slots of the last test */
+    uint64_t last_reports;      /* records of the last test */
+    uint64_t last_literals;     /* literals stored for the live clauses (sum of lengths) */
+    uint64_t live_clauses;
+    uint64_t active_slots;
+    uint64_t device_bytes;
+    uint64_t compactions;
+    uint64_t regrows;           /* report-buffer regrowths */
+    uint64_t kernel_launches;   /* test kernel launches (reruns included) */
+    double last_kernel_ms;      /* duration of the last test kernel, from HIP events on the context stream */
+    double total_kernel_ms;     /* sum over test kernel launches since the last reset */
+    uint64_t timed_launches;    /* launches summed in total_kernel_ms */
+} gss_stats;
+
+gss_status gss_get_stats(const gss_ctx *ctx, gss_stats *out);
+gss_status gss_reset_stats(gss_ctx *ctx);
+
+/* hipStream_t the context issues work on (borrowed or owned). */
+gss_status gss_get_stream(const gss_ctx *ctx, void **stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSS_H */

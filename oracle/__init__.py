@@ -68,12 +68,19 @@ def _load():
         p = ctypes.c_void_p
         i64 = ctypes.c_int64
         lib.oracle_transpose.argtypes = [i64, i64, p, p]
+        lib.oracle_max_threads.argtypes = []
+        lib.oracle_max_threads.restype = ctypes.c_int
         for name in ("oracle_falsified", "oracle_trigger"):
             fn = getattr(lib, name)
             fn.argtypes = [i64, p, p, i64, i64, p, p, p]
             fn.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def max_threads() -> int:
+    """Threads the C oracle runs on (OpenMP)."""
+    return int(_load().oracle_max_threads())
 
 
 def _ptr(a: np.ndarray):

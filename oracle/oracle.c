@@ -33,6 +33,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define TV_T ((int8_t)1)
 #define TV_F ((int8_t)-1)
@@ -162,4 +165,14 @@ int oracle_trigger(int64_t n_clauses, const int64_t *offsets, const int32_t *lit
         }
     }
     return 0;
+}
+
+/* Number of threads the loops above use (OpenMP), for reporting. */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,0 +1,277 @@
+// Context lifetime, device memory accounting, errors and statistics of libgss.
+#include "gss_internal.h"
+
+#include <cstring>
+#include <new>
+
+namespace gss {
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t value) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t value) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+static unsigned fill_grid(uint64_t n) {
+    uint64_t g = (n + 255) / 256;
+    return (unsigned)(g < 8192 ? (g ? g : 1) : 8192);
+}
+
+void launch_fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t value) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(256), 0, c.stream, p, n, value);
+    GSS_HIP(hipGetLastError());
+}
+
+void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(n)), dim3(256), 0, c.stream, p, n, value);
+    GSS_HIP(hipGetLastError());
+}
+
+// Sets *bad when any byte is outside {-1, 0, +1}.
+__global__ void k_check_values(const int8_t *v, uint64_t n, unsigned int *bad) {
+    unsigned found = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        int8_t x = v[i];
+        found |= (x < -1 || x > 1);
+    }
+    if (found) atomicOr(bad, 1u);
+}
+
+void check_values_device(Ctx &c, const int8_t *values, uint64_t n) {
+    if (!n) return;
+    unsigned int *flag = c.hsmall;
+    unsigned int *dflag = c.dsmall;
+    launch_fill_u32(c, dflag, 1, 0);
+    hipLaunchKernelGGL(k_check_values, dim3(fill_grid(n)), dim3(256), 0, c.stream, values, n, dflag);
+    GSS_HIP(hipGetLastError());
+    GSS_HIP(hipMemcpyAsync(flag, dflag, sizeof(unsigned int), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    GSS_REQUIRE(*flag == 0, GSS_ERR_INVALID_ARG, "truth values must be -1, 0 or +1");
+}
+
+bool is_device_pointer(const void *p) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();  // plain pageable host memory
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// ---------------------------------------------------------------------------
+// memory
+// ---------------------------------------------------------------------------
+
+void *Ctx::dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    GSS_REQUIRE(cfg.hbm_budget_bytes == 0 || device_bytes + bytes <= cfg.hbm_budget_bytes, GSS_ERR_CAPACITY,
+                "HBM budget exhausted (" + std::to_string(device_bytes + bytes) + " > " +
+                    std::to_string(cfg.hbm_budget_bytes) + " bytes)");
+    void *p = nullptr;
+    if (cfg.dev_alloc) {
+        p = cfg.dev_alloc(bytes, stream, cfg.alloc_user);
+        GSS_REQUIRE(p != nullptr, GSS_ERR_DEVICE, "device allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        GSS_HIP(hipMalloc(&p, bytes));
+    }
+    allocs[p] = bytes;
+    device_bytes += bytes;
+    return p;
+}
+
+void Ctx::dfree(void *p) {
+    if (!p) return;
+    auto it = allocs.find(p);
+    if (it == allocs.end()) return;
+    device_bytes -= it->second;
+    allocs.erase(it);
+    if (cfg.dev_free)
+        cfg.dev_free(p, stream, cfg.alloc_user);
+    else
+        (void)hipFree(p);
+}
+
+void *Ctx::device_stage(size_t bytes) {
+    if (bytes > dstage_bytes) {
+        // the old buffer may still be read by queued work
+        sync();
+        dfree(dstage);
+        dstage = nullptr;
+        dstage_bytes = 0;
+        size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+        dstage = dalloc(want);
+        dstage_bytes = want;
+    }
+    return dstage;
+}
+
+void *Ctx::host_stage(size_t bytes) {
+    if (bytes > hstage_bytes) {
+        sync();
+        if (hstage) (void)hipHostFree(hstage);
+        hstage = nullptr;
+        hstage_bytes = 0;
+        size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+        GSS_HIP(hipHostMalloc(&hstage, want, hipHostMallocDefault));
+        hstage_bytes = want;
+    }
+    return hstage;
+}
+
+void Ctx::sync() { GSS_HIP(hipStreamSynchronize(stream)); }
+
+}  // namespace gss
+
+using namespace gss;
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_create_error;
+
+static void destroy_ctx(Ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &b : c->buckets) {
+        c->dfree(b.lits);
+        c->dfree(b.len);
+        c->dfree(b.ids);
+    }
+    c->dfree(c->planes);
+    c->dfree(c->active);
+    c->dfree(c->reports);
+    c->dfree(c->counter);
+    c->dfree(c->dense);
+    c->dfree(c->dstage);
+    if (c->hstage) (void)hipHostFree(c->hstage);
+    if (c->h_counter) (void)hipHostFree(c->h_counter);
+    c->dfree(c->dsmall);
+    c->dfree(c->d_desc);
+    if (c->hsmall_desc) (void)hipHostFree(c->hsmall_desc);
+    if (c->hsmall) (void)hipHostFree(c->hsmall);
+    if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+    if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
+    if (out) *out = nullptr;
+    g_create_error.clear();
+    if (!cfg || !out) {
+        g_create_error = "null argument";
+        return GSS_ERR_INVALID_ARG;
+    }
+    if (cfg->num_vars < 1 || cfg->num_vars > (1u << 30)) {
+        g_create_error = "num_vars must be in 1..2^30";
+        return GSS_ERR_INVALID_ARG;
+    }
+    if (cfg->max_slots < 64 || cfg->max_slots > 4096 || cfg->max_slots % 64 != 0) {
+        g_create_error = "max_slots must be a multiple of 64 in 64..4096";
+        return GSS_ERR_INVALID_ARG;
+    }
+    if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) {
+        g_create_error = "dev_alloc and dev_free must be given together";
+        return GSS_ERR_INVALID_ARG;
+    }
+    Ctx *c = nullptr;
+    try {
+        c = new Ctx();
+        c->cfg = *cfg;
+        GSS_HIP(hipGetDevice(&c->device));
+        GSS_HIP(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+        if (cfg->stream) {
+            c->stream = (hipStream_t)cfg->stream;
+        } else {
+            GSS_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        c->W = cfg->max_slots / 64;
+        c->LPC = 1;
+        while (c->LPC < c->W) c->LPC <<= 1;
+        c->T = 64 / c->LPC;
+        // LDS staging: rows of variables 0..hot_vars, at most 64 KiB per workgroup
+        uint64_t max_rows = 65536 / (8ull * c->W);
+        uint64_t rows = cfg->hot_vars ? 2ull * ((uint64_t)cfg->hot_vars + 1) : 0;
+        if (rows > max_rows) rows = max_rows & ~1ull;
+        if (rows > 2ull * ((uint64_t)cfg->num_vars + 1)) rows = 2ull * ((uint64_t)cfg->num_vars + 1);
+        c->hot_rows = (uint32_t)rows;
+        for (int b = 0; b < kMaxBuckets; ++b) c->buckets[b].stride_log2 = (uint32_t)b;
+
+        const uint64_t n_rows = 2ull * ((uint64_t)cfg->num_vars + 1);
+        c->planes = (uint64_t *)c->dalloc(n_rows * c->W * sizeof(uint64_t));
+        launch_fill_u64(*c, c->planes, n_rows * c->W, 0);
+        launch_fill_u64(*c, c->planes, c->W, ~0ull);  // row 0: always F
+        c->active = (uint64_t *)c->dalloc(c->W * sizeof(uint64_t));
+        launch_fill_u64(*c, c->active, c->W, 0);
+        c->h_active.assign(c->W, 0);
+
+        c->report_cap = cfg->report_capacity ? cfg->report_capacity : (1u << 16);
+        c->reports = (gss_report *)c->dalloc(c->report_cap * sizeof(gss_report));
+        c->counter = (unsigned long long *)c->dalloc(sizeof(unsigned long long));
+        GSS_HIP(hipHostMalloc(&c->h_counter, sizeof(unsigned long long), hipHostMallocDefault));
+        c->dsmall = (uint32_t *)c->dalloc(256);
+        c->d_desc = c->dalloc(kMaxBuckets * sizeof(BucketDesc));
+        GSS_HIP(hipHostMalloc(&c->hsmall_desc, kMaxBuckets * sizeof(BucketDesc), hipHostMallocDefault));
+        GSS_HIP(hipHostMalloc(&c->hsmall, 256, hipHostMallocDefault));
+        GSS_HIP(hipEventCreate(&c->ev_start));
+        GSS_HIP(hipEventCreate(&c->ev_stop));
+        c->sync();
+    } catch (const Error &e) {
+        g_create_error = e.what();
+        destroy_ctx(c);
+        return e.code;
+    } catch (const std::exception &e) {
+        g_create_error = e.what();
+        destroy_ctx(c);
+        return GSS_ERR_DEVICE;
+    }
+    *out = reinterpret_cast<gss_ctx *>(c);
+    return GSS_OK;
+}
+
+extern "C" void gss_destroy(gss_ctx *ctx) { destroy_ctx(reinterpret_cast<Ctx *>(ctx)); }
+
+extern "C" const char *gss_last_error(const gss_ctx *ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return reinterpret_cast<const Ctx *>(ctx)->last_error.c_str();
+}
+
+extern "C" gss_status gss_get_stats(const gss_ctx *ctx, gss_stats *out) {
+    const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+    if (!c || !out) return GSS_ERR_INVALID_ARG;
+    *out = c->stats;
+    out->live_clauses = c->live;
+    out->device_bytes = c->device_bytes;
+    uint64_t act = 0;
+    for (uint64_t w : c->h_active) act += __builtin_popcountll(w);
+    out->active_slots = act;
+    return GSS_OK;
+}
+
+extern "C" gss_status gss_reset_stats(gss_ctx *ctx) {
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c) return GSS_ERR_INVALID_ARG;
+    c->stats = gss_stats{};
+    return GSS_OK;
+}
+
+extern "C" gss_status gss_get_stream(const gss_ctx *ctx, void **stream) {
+    const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+    if (!c || !stream) return GSS_ERR_INVALID_ARG;
+    *stream = (void *)c->stream;
+    return GSS_OK;
+}
+

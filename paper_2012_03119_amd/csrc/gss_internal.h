@@ -1,0 +1,195 @@
+// Internal declarations of libgss: the context, the clause store, the assignment
+// planes and the launchers of the device kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gss.h"
+
+namespace gss {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+struct Error : std::runtime_error {
+    gss_status code;
+    Error(gss_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define GSS_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw ::gss::Error(GSS_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GSS_REQUIRE(cond, code, msg)            \
+    do {                                        \
+        if (!(cond))                            \
+            throw ::gss::Error((code), (msg));  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// encodings shared by host and device code of the library
+// ---------------------------------------------------------------------------
+
+// A literal is stored as code = 2*v + neg (v >= 1; neg = 1 for -v).  Plane row
+// `code` holds, per slot, whether that literal is F: row 2v has the slots where
+// v = F, row 2v+1 the slots where v = T.  Variable 0 is reserved: row 0 is all
+// ones (a literal that is always F) and row 1 all zeros (never F).
+__host__ __device__ inline uint32_t lit_code(int32_t lit) {
+    return lit > 0 ? 2u * (uint32_t)lit : 2u * (uint32_t)(-lit) + 1u;
+}
+
+constexpr int kMaxBuckets = 17;              // length classes 1, 2, 4, ..., 65536
+constexpr uint32_t kMaxClauseLen = 65536;
+constexpr uint32_t kDeadId = 0xFFFFFFFFu;
+constexpr uint64_t kNoLoc = ~0ull;
+
+// length class: smallest c with 2^c >= len
+inline int length_class(uint32_t len) {
+    int c = 0;
+    while ((1u << c) < len) ++c;
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// device-side descriptors
+// ---------------------------------------------------------------------------
+
+// One length class of the clause store as the test kernel sees it.  Tiles hold T
+// clauses (T = 64 / lanes-per-clause); tile t stores its literal codes
+// literal-major: lits[(t * S + k) * T + j] is literal k of clause j of the tile.
+struct BucketDesc {
+    const uint32_t *lits;
+    const uint32_t *len;   // per slot; 0 = empty or removed
+    const uint32_t *ids;   // per slot
+    uint32_t stride_log2;  // S = 1 << stride_log2 literal rows per tile
+    uint32_t tile_begin;   // global index of the bucket's first tile
+};
+
+struct TestArgs {
+    BucketDesc b[kMaxBuckets];
+    uint32_t n_buckets;
+    uint32_t n_tiles;
+    const uint64_t *planes;   // [2 * (num_vars + 1)][W]
+    const uint64_t *active;   // [W]
+    uint32_t W;
+    uint32_t hot_rows;        // rows [0, hot_rows) are staged in LDS (0 = off)
+    gss_report *reports;
+    unsigned long long *counter;
+    unsigned long long cap;
+    uint64_t *dense;          // GSS_TEST_DENSE: [n_ids][W]
+};
+
+// ---------------------------------------------------------------------------
+// host-side state
+// ---------------------------------------------------------------------------
+
+struct Bucket {
+    uint32_t stride_log2 = 0;
+    uint64_t n_slots = 0;    // slots in use, live or removed (the append tail)
+    uint64_t n_dead = 0;
+    uint64_t cap_slots = 0;  // allocated slots, a multiple of T
+    uint64_t n_lits = 0;     // literals of the live clauses
+    uint32_t *lits = nullptr;
+    uint32_t *len = nullptr;
+    uint32_t *ids = nullptr;
+    std::vector<uint32_t> h_ids;  // mirror of ids (kDeadId = removed)
+    std::vector<uint32_t> h_len;  // mirror of len
+};
+
+struct Ctx {
+    gss_config cfg{};
+    int device = 0;
+    int n_cu = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t W = 0;     // 64-slot words per plane row
+    uint32_t LPC = 0;   // lanes per clause in the test kernel (power of two >= W)
+    uint32_t T = 0;     // clauses per tile = 64 / LPC
+    uint32_t hot_rows = 0;
+
+    uint64_t device_bytes = 0;
+    std::unordered_map<void *, size_t> allocs;
+
+    uint64_t *planes = nullptr;
+    uint64_t *active = nullptr;
+    std::vector<uint64_t> h_active;
+    std::vector<uint64_t> var_seen;  // scratch bitmap for argument checks (kept all-zero)
+
+    Bucket buckets[kMaxBuckets];
+    std::vector<uint64_t> id_loc;  // per id: bucket << 40 | slot, or kNoLoc
+    uint64_t live = 0;
+
+    gss_report *reports = nullptr;
+    uint64_t report_cap = 0;
+    unsigned long long *counter = nullptr;   // device
+    unsigned long long *h_counter = nullptr; // pinned host
+    uint32_t *dsmall = nullptr;              // 256 B device scratch for flags
+    uint32_t *hsmall = nullptr;              // 256 B pinned host
+    void *d_desc = nullptr;                  // device copy of the test kernel's bucket descriptors
+    void *hsmall_desc = nullptr;             // pinned host staging of the same
+    uint64_t n_reports = 0;
+    bool tested = false;
+    uint32_t last_flags = 0;
+
+    uint64_t *dense = nullptr;
+    uint64_t dense_rows = 0;
+
+    // staging for uploads (device) and pinned host staging
+    void *dstage = nullptr;
+    size_t dstage_bytes = 0;
+    void *hstage = nullptr;
+    size_t hstage_bytes = 0;
+
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    gss_stats stats{};
+    std::string last_error;
+
+    // device memory within the budget
+    void *dalloc(size_t bytes);
+    void dfree(void *p);
+    void *device_stage(size_t bytes);
+    void *host_stage(size_t bytes);
+    void sync();
+};
+
+// kernels / launchers (defined in the .hip files)
+void launch_fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t value);
+void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value);
+bool is_device_pointer(const void *p);
+void check_values_device(Ctx &c, const int8_t *values, uint64_t n);
+
+// Wrapper of every ABI entry point taking a context: converts exceptions into
+// status codes and records the message for gss_last_error.
+#define GSS_API_BEGIN(ctxp)                                  \
+    ::gss::Ctx *c_ = reinterpret_cast<::gss::Ctx *>(ctxp);   \
+    if (!c_) return GSS_ERR_INVALID_ARG;                     \
+    try {                                                    \
+        c_->last_error.clear();
+#define GSS_API_END                                          \
+    }                                                        \
+    catch (const ::gss::Error &e) {                          \
+        c_->last_error = e.what();                           \
+        return e.code;                                       \
+    }                                                        \
+    catch (const std::bad_alloc &) {                         \
+        c_->last_error = "host out of memory";               \
+        return GSS_ERR_CAPACITY;                             \
+    }                                                        \
+    catch (const std::exception &e) {                        \
+        c_->last_error = e.what();                           \
+        return GSS_ERR_DEVICE;                               \
+    }                                                        \
+    return GSS_OK;
+
+}  // namespace gss

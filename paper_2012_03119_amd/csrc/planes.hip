@@ -1,0 +1,231 @@
+// Assignment bitplanes (Section 3.4): N assignments of a variable as two N-bit
+// words.  The paper keeps (isTrue, isSet); this library keeps, per literal code,
+// the word of slots where that literal is F:
+//   row 2v   = slots where v = F   (isSet & ~isTrue)
+//   row 2v+1 = slots where v = T   (isSet &  isTrue)
+// so a clause's falsified mask is the AND of one gathered row per literal, and
+// the Undef slots of v are the complement of (row 2v | row 2v+1).  The value of
+// the isTrue bit for an Undef slot, which the paper leaves open, never enters.
+//
+// One 64-bit word holds 64 slots, one per lane of a wavefront: the pack kernels
+// build each word with two wavefront ballots.
+#include "gss_internal.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace gss {
+
+// Packs the slots of word w from a slot-major staging block.  One wavefront per
+// 64 variables; lane b reads slot 64*w + b.  Staging row r holds slot s_lo + r,
+// `pitch` bytes per row (a multiple of 64), byte v-1 = value of variable v.
+__global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t W, uint32_t w, uint32_t num_vars,
+                                                  const int8_t *stage, uint64_t pitch, uint32_t s_lo, uint32_t s_hi) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t v0 = 1 + 64 * blockIdx.x;
+    const uint32_t slot = 64 * w + lane;
+    const bool in = slot >= s_lo && slot < s_hi;
+    uint4 q[4] = {};
+    if (in) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(stage + (uint64_t)(slot - s_lo) * pitch + (v0 - 1));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] = src[i];
+    }
+    const uint32_t r[16] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w,
+                            q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
+    const uint64_t sm = __ballot(in);
+    uint64_t f = 0, t = 0;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+        const uint32_t byte = (r[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        const uint64_t bf = __ballot(byte == 0xFFu);  // -1: F
+        const uint64_t bt = __ballot(byte == 0x01u);  // +1: T
+        if (lane == (uint32_t)j) {
+            f = bf;
+            t = bt;
+        }
+    }
+    const uint32_t v = v0 + lane;
+    if (v <= num_vars) {
+        const uint64_t r0 = (uint64_t)(2 * v) * W + w, r1 = r0 + W;
+        if (sm != ~0ull) {
+            f = (planes[r0] & ~sm) | (f & sm);
+            t = (planes[r1] & ~sm) | (t & sm);
+        }
+        planes[r0] = f;
+        planes[r1] = t;
+    }
+}
+
+// Delta update: new values of listed variables over a slot range.  One wavefront
+// per variable; lane b covers slot 64*w + b of each word w in the range, and the
+// finished words are written by lanes 0..(words-1).  vals is var-major
+// [n_vars][n_slots].
+__global__ __launch_bounds__(64) void k_set_vars(uint64_t *planes, uint32_t W, const uint32_t *vars, uint32_t n_vars,
+                                                 const int8_t *vals, uint32_t first, uint32_t n_slots) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t w_lo = first / 64, w_hi = (first + n_slots - 1) / 64;
+    for (uint32_t i = blockIdx.x; i < n_vars; i += gridDim.x) {
+        const uint32_t v = vars[i];
+        uint64_t my_f = 0, my_t = 0, my_sm = 0;
+        for (uint32_t w = w_lo; w <= w_hi; ++w) {
+            const uint32_t slot = 64 * w + lane;
+            const bool in = slot >= first && slot < first + n_slots;
+            const int8_t x = in ? vals[(uint64_t)i * n_slots + (slot - first)] : (int8_t)0;
+            const uint64_t bf = __ballot(x == -1);
+            const uint64_t bt = __ballot(x == 1);
+            const uint64_t sm = __ballot(in);
+            if (lane == w - w_lo) {
+                my_f = bf;
+                my_t = bt;
+                my_sm = sm;
+            }
+        }
+        if (lane <= w_hi - w_lo) {
+            const uint32_t w = w_lo + lane;
+            const uint64_t r0 = (uint64_t)(2 * v) * W + w, r1 = r0 + W;
+            uint64_t f = my_f, t = my_t;
+            if (my_sm != ~0ull) {
+                f = (planes[r0] & ~my_sm) | (f & my_sm);
+                t = (planes[r1] & ~my_sm) | (t & my_sm);
+            }
+            planes[r0] = f;
+            planes[r1] = t;
+        }
+    }
+}
+
+// Clears slots [first, first+n) in every row of real variables (rows >= 2).
+__global__ void k_clear_slots(uint64_t *planes, uint32_t W, uint64_t n_rows, uint32_t first, uint32_t n_slots) {
+    const uint32_t w_lo = first / 64, w_hi = (first + n_slots - 1) / 64, nw = w_hi - w_lo + 1;
+    const uint64_t total = (n_rows - 2) * nw;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t row = 2 + x / nw;
+        const uint32_t w = w_lo + (uint32_t)(x % nw);
+        const uint32_t a = std::max(first, 64 * w), b = std::min(first + n_slots, 64 * w + 64);
+        const uint64_t sm = (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1) << (a - 64 * w));
+        planes[row * W + w] &= ~sm;
+    }
+}
+
+static uint64_t slot_mask(uint32_t first, uint32_t n, uint32_t w) {
+    const uint32_t a = std::max(first, 64 * w), b = std::min(first + n, 64 * w + 64);
+    if (b <= a) return 0;
+    return (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1) << (a - 64 * w));
+}
+
+static void upload_active(Ctx &c) {
+    uint64_t *h = (uint64_t *)c.host_stage(c.W * 8);
+    std::memcpy(h, c.h_active.data(), c.W * 8);
+    GSS_HIP(hipMemcpyAsync(c.active, h, c.W * 8, hipMemcpyHostToDevice, c.stream));
+    c.sync();
+}
+
+static void check_values_host(const int8_t *v, uint64_t n) {
+    uint8_t bad = 0;
+    for (uint64_t i = 0; i < n; ++i) bad |= (uint8_t)((uint8_t)(v[i] + 1) > 2);
+    GSS_REQUIRE(!bad, GSS_ERR_INVALID_ARG, "truth values must be -1, 0 or +1");
+}
+
+}  // namespace gss
+
+using namespace gss;
+
+extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, const int8_t *values) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    if (n_slots == 0) return GSS_OK;
+    GSS_REQUIRE(values != nullptr, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE((uint64_t)first_slot + n_slots <= c.cfg.max_slots, GSS_ERR_CAPACITY, "slot range beyond max_slots");
+    const uint64_t V = c.cfg.num_vars;
+    const bool dev = is_device_pointer(values);
+    if (dev)
+        check_values_device(c, values, (uint64_t)n_slots * V);
+    else
+        check_values_host(values, (uint64_t)n_slots * V);
+
+    const uint64_t pitch = (V + 63) / 64 * 64;
+    const uint32_t last = first_slot + n_slots;
+    int8_t *stage = (int8_t *)c.device_stage(64 * pitch);
+    for (uint32_t w = first_slot / 64; w <= (last - 1) / 64; ++w) {
+        const uint32_t s_lo = std::max(first_slot, 64 * w), s_hi = std::min(last, 64 * w + 64);
+        const int8_t *src = values + (uint64_t)(s_lo - first_slot) * V;
+        GSS_HIP(hipMemcpy2DAsync(stage, pitch, src, V, V, s_hi - s_lo,
+                                 dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.stream));
+        hipLaunchKernelGGL(k_pack_word, dim3((unsigned)((V + 63) / 64)), dim3(64), 0, c.stream, c.planes, c.W, w,
+                           (uint32_t)V, stage, pitch, s_lo, s_hi);
+        GSS_HIP(hipGetLastError());
+        c.h_active[w] |= slot_mask(first_slot, n_slots, w);
+    }
+    upload_active(c);  // synchronises: the staging block is free again
+    GSS_API_END
+}
+
+extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, uint32_t n_vars,
+                                         const uint32_t *vars, const int8_t *values) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    if (n_slots == 0 || n_vars == 0) return GSS_OK;
+    GSS_REQUIRE(vars && values, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE((uint64_t)first_slot + n_slots <= c.cfg.max_slots, GSS_ERR_CAPACITY, "slot range beyond max_slots");
+    for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w) {
+        const uint64_t sm = slot_mask(first_slot, n_slots, w);
+        GSS_REQUIRE((c.h_active[w] & sm) == sm, GSS_ERR_INVALID_ARG, "slot range includes inactive slots");
+    }
+    {
+        // range and distinctness, O(n) with a bitmap that is cleared again afterwards
+        std::vector<uint64_t> &seen = c.var_seen;
+        if (seen.size() < (uint64_t)c.cfg.num_vars / 64 + 1) seen.assign((uint64_t)c.cfg.num_vars / 64 + 1, 0);
+        uint32_t bad = 0;  // 1: out of range, 2: repeated
+        uint32_t i = 0;
+        for (; i < n_vars; ++i) {
+            const uint32_t v = vars[i];
+            if (v < 1 || v > c.cfg.num_vars) { bad = 1; break; }
+            uint64_t &word = seen[v >> 6];
+            const uint64_t bit = 1ull << (v & 63);
+            if (word & bit) { bad = 2; break; }
+            word |= bit;
+        }
+        for (uint32_t k = 0; k < i; ++k) seen[vars[k] >> 6] = 0;
+        GSS_REQUIRE(bad != 1, GSS_ERR_BAD_LITERAL, "variable out of range");
+        GSS_REQUIRE(bad != 2, GSS_ERR_INVALID_ARG, "variable listed twice");
+    }
+    const uint64_t nv = (uint64_t)n_vars * n_slots;
+    const bool dev = is_device_pointer(values);
+    if (dev)
+        check_values_device(c, values, nv);
+    else
+        check_values_host(values, nv);
+
+    const size_t vars_bytes = ((size_t)n_vars * 4 + 255) / 256 * 256;
+    char *d = (char *)c.device_stage(vars_bytes + (dev ? 0 : nv));
+    GSS_HIP(hipMemcpyAsync(d, vars, (size_t)n_vars * 4, hipMemcpyHostToDevice, c.stream));
+    const int8_t *dvals = values;
+    if (!dev) {
+        GSS_HIP(hipMemcpyAsync(d + vars_bytes, values, nv, hipMemcpyHostToDevice, c.stream));
+        dvals = (const int8_t *)(d + vars_bytes);
+    }
+    const unsigned grid = std::min<uint32_t>(n_vars, 65536);
+    hipLaunchKernelGGL(k_set_vars, dim3(grid), dim3(64), 0, c.stream, c.planes, c.W, (const uint32_t *)d, n_vars,
+                       dvals, first_slot, n_slots);
+    GSS_HIP(hipGetLastError());
+    c.sync();
+    GSS_API_END
+}
+
+extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    if (n_slots == 0) return GSS_OK;
+    GSS_REQUIRE((uint64_t)first_slot + n_slots <= c.cfg.max_slots, GSS_ERR_CAPACITY, "slot range beyond max_slots");
+    const uint64_t n_rows = 2ull * ((uint64_t)c.cfg.num_vars + 1);
+    const uint64_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
+    const uint64_t total = (n_rows - 2) * nw;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
+    hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(256), 0, c.stream, c.planes, c.W, n_rows, first_slot, n_slots);
+    GSS_HIP(hipGetLastError());
+    for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w)
+        c.h_active[w] &= ~slot_mask(first_slot, n_slots, w);
+    upload_active(c);
+    GSS_API_END
+}

@@ -1,0 +1,378 @@
+// The clause store: length-bucketed SoA tiles of literal codes, with insertion,
+// deletion and compaction.
+//
+// Layout (per length class b, stride S = 2^b literal rows): slots are grouped in
+// tiles of T clauses (T = 64 / lanes-per-clause of the test kernel) and a tile
+// stores its codes literal-major, lits[(tile * S + k) * T + j] = literal k of
+// clause j, so the T clauses of one wavefront read their k-th literals from one
+// contiguous run.  Literals of a clause are kept sorted by code (variable order):
+// the order does not change the result, and it concentrates the first literals of
+// long clauses -- the ones the early exit actually reads -- on low variable rows.
+#include "gss_internal.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace gss {
+
+// ---------------------------------------------------------------------------
+// device kernels
+// ---------------------------------------------------------------------------
+
+// Appends one segment of new clauses to a bucket: thread per literal.  Clause i
+// of the segment goes to slot slot0 + i; its codes are codes[coff[i] .. coff[i+1]).
+__global__ void k_append_lits(uint32_t *lits, uint32_t stride_log2, uint32_t T, uint64_t slot0,
+                              const uint32_t *codes, const uint64_t *coff, uint32_t n_clauses, uint64_t n_lits) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n_lits; x += (uint64_t)gridDim.x * blockDim.x) {
+        // clause owning literal x: last i with coff[i] <= x
+        uint32_t lo = 0, hi = n_clauses;  // coff[lo] <= x < coff[hi]
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (coff[mid] <= x) lo = mid; else hi = mid;
+        }
+        uint64_t k = x - coff[lo];
+        uint64_t slot = slot0 + lo;
+        uint64_t tile = slot / T, j = slot % T;
+        lits[((tile << stride_log2) + k) * T + j] = codes[x];
+    }
+}
+
+__global__ void k_append_meta(uint32_t *len, uint32_t *ids, uint64_t slot0, const uint64_t *coff,
+                              const uint32_t *new_ids, uint32_t n_clauses) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_clauses; i += gridDim.x * blockDim.x) {
+        len[slot0 + i] = (uint32_t)(coff[i + 1] - coff[i]);
+        ids[slot0 + i] = new_ids[i];
+    }
+}
+
+// Marks slots removed.
+__global__ void k_tombstone(uint32_t *len, uint32_t *ids, const uint64_t *slots, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        len[slots[i]] = 0;
+        ids[slots[i]] = kDeadId;
+    }
+}
+
+// Compaction: new slot s takes the clause of old slot old_slot[s]; thread per
+// (new slot, literal row).
+__global__ void k_compact_lits(uint32_t *dst, const uint32_t *src, uint32_t stride_log2, uint32_t T,
+                               const uint64_t *old_slot, uint64_t n_new) {
+    const uint64_t S = 1ull << stride_log2;
+    const uint64_t total = n_new * S;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t s = x >> stride_log2, k = x & (S - 1);
+        uint64_t o = old_slot[s];
+        dst[(((s / T) << stride_log2) + k) * T + s % T] = src[(((o / T) << stride_log2) + k) * T + o % T];
+    }
+}
+
+__global__ void k_compact_meta(uint32_t *dlen, uint32_t *dids, const uint32_t *slen, const uint32_t *sids,
+                               const uint64_t *old_slot, uint64_t n_new) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < n_new; s += (uint64_t)gridDim.x * blockDim.x) {
+        dlen[s] = slen[old_slot[s]];
+        dids[s] = sids[old_slot[s]];
+    }
+}
+
+static unsigned grid_for(uint64_t n, unsigned block = 256) {
+    uint64_t g = (n + block - 1) / block;
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, 16384));
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+
+static uint64_t bucket_bytes(uint64_t cap_slots, uint32_t stride_log2) {
+    return cap_slots * ((4ull << stride_log2) + 8ull) + 3 * 256;
+}
+
+static uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+
+// Allocates the three arrays of a bucket with capacity cap (tail zeroed: len 0,
+// ids dead, codes 0) and copies the used prefix of the old arrays.
+static void grow_bucket(Ctx &c, Bucket &b, uint64_t cap) {
+    const uint64_t S = 1ull << b.stride_log2;
+    uint32_t *lits = (uint32_t *)c.dalloc(cap * S * 4);
+    uint32_t *len = (uint32_t *)c.dalloc(cap * 4);
+    uint32_t *ids = (uint32_t *)c.dalloc(cap * 4);
+    launch_fill_u32(c, lits, cap * S, 0);
+    launch_fill_u32(c, len, cap, 0);
+    launch_fill_u32(c, ids, cap, kDeadId);
+    if (b.n_slots) {
+        uint64_t used_tiles = (b.n_slots + c.T - 1) / c.T;
+        GSS_HIP(hipMemcpyAsync(lits, b.lits, used_tiles * S * c.T * 4, hipMemcpyDeviceToDevice, c.stream));
+        GSS_HIP(hipMemcpyAsync(len, b.len, b.n_slots * 4, hipMemcpyDeviceToDevice, c.stream));
+        GSS_HIP(hipMemcpyAsync(ids, b.ids, b.n_slots * 4, hipMemcpyDeviceToDevice, c.stream));
+    }
+    c.sync();
+    c.dfree(b.lits);
+    c.dfree(b.len);
+    c.dfree(b.ids);
+    b.lits = lits;
+    b.len = len;
+    b.ids = ids;
+    b.cap_slots = cap;
+}
+
+// Rewrites bucket b keeping only its live clauses, in slot order.  Returns false
+// (and changes nothing) when the HBM budget has no room for the new arrays.
+static bool compact_bucket(Ctx &c, int bi) {
+    Bucket &b = c.buckets[bi];
+    std::vector<uint64_t> old_slot;
+    old_slot.reserve(b.n_slots - b.n_dead);
+    for (uint64_t s = 0; s < b.n_slots; ++s)
+        if (b.h_ids[s] != kDeadId) old_slot.push_back(s);
+    const uint64_t n_new = old_slot.size();
+    const uint64_t S = 1ull << b.stride_log2;
+    const uint64_t cap = round_up(std::max<uint64_t>(n_new + n_new / 4, 256), c.T);
+    const uint64_t need = cap * S * 4 + 2 * cap * 4 + n_new * 8 + 4096;
+    if (c.cfg.hbm_budget_bytes && c.device_bytes + need > c.cfg.hbm_budget_bytes) return false;
+
+    uint32_t *lits = (uint32_t *)c.dalloc(cap * S * 4);
+    uint32_t *len = (uint32_t *)c.dalloc(cap * 4);
+    uint32_t *ids = (uint32_t *)c.dalloc(cap * 4);
+    uint64_t *dmap = (uint64_t *)c.dalloc(std::max<uint64_t>(n_new, 1) * 8);
+    launch_fill_u32(c, lits, cap * S, 0);
+    launch_fill_u32(c, len, cap, 0);
+    launch_fill_u32(c, ids, cap, kDeadId);
+    if (n_new) {
+        GSS_HIP(hipMemcpyAsync(dmap, old_slot.data(), n_new * 8, hipMemcpyHostToDevice, c.stream));
+        hipLaunchKernelGGL(k_compact_lits, dim3(grid_for(n_new * S)), dim3(256), 0, c.stream, lits, b.lits,
+                           b.stride_log2, c.T, dmap, n_new);
+        GSS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_compact_meta, dim3(grid_for(n_new)), dim3(256), 0, c.stream, len, ids, b.len, b.ids,
+                           dmap, n_new);
+        GSS_HIP(hipGetLastError());
+    }
+    c.sync();
+    c.dfree(dmap);
+    c.dfree(b.lits);
+    c.dfree(b.len);
+    c.dfree(b.ids);
+    b.lits = lits;
+    b.len = len;
+    b.ids = ids;
+    b.cap_slots = cap;
+
+    std::vector<uint32_t> h_ids(n_new), h_len(n_new);
+    for (uint64_t s = 0; s < n_new; ++s) {
+        h_ids[s] = b.h_ids[old_slot[s]];
+        h_len[s] = b.h_len[old_slot[s]];
+        c.id_loc[h_ids[s]] = ((uint64_t)bi << 40) | s;
+    }
+    b.h_ids.swap(h_ids);
+    b.h_len.swap(h_len);
+    b.n_slots = n_new;
+    b.n_dead = 0;
+    c.stats.compactions++;
+    return true;
+}
+
+}  // namespace gss
+
+using namespace gss;
+
+extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const uint64_t *offsets, uint32_t n,
+                                      uint32_t *out_ids) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    if (n == 0) return GSS_OK;
+    GSS_REQUIRE(lits && offsets && out_ids, GSS_ERR_INVALID_ARG, "null argument");
+    const uint64_t next = c.id_loc.size();
+    GSS_REQUIRE(next + n < (uint64_t)kDeadId, GSS_ERR_CAPACITY, "clause id space exhausted");
+
+    // ---- validate everything first
+    std::vector<uint8_t> cls(n);
+    uint64_t add[kMaxBuckets] = {0};
+    const int64_t V = c.cfg.num_vars;
+    for (uint32_t i = 0; i < n; ++i) {
+        GSS_REQUIRE(offsets[i + 1] >= offsets[i], GSS_ERR_INVALID_ARG, "offsets must be non-decreasing");
+        const uint64_t L = offsets[i + 1] - offsets[i];
+        GSS_REQUIRE(L >= 1, GSS_ERR_INVALID_ARG, "empty clause at index " + std::to_string(i));
+        GSS_REQUIRE(L <= kMaxClauseLen, GSS_ERR_INVALID_ARG, "clause longer than 65536 literals at index " + std::to_string(i));
+        for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t l = lits[k];
+            int64_t v = l < 0 ? -l : l;
+            GSS_REQUIRE(v >= 1 && v <= V, GSS_ERR_BAD_LITERAL,
+                        "literal " + std::to_string(l) + " of clause " + std::to_string(i) + " is 0 or beyond num_vars");
+        }
+        cls[i] = (uint8_t)length_class((uint32_t)L);
+        add[cls[i]]++;
+    }
+
+    // ---- order the batch by bucket (stable) and cut it into upload chunks, each a
+    //      run of clauses of one bucket; stage buffers sized for the largest chunk
+    std::vector<uint32_t> order(n);
+    {
+        uint64_t pos[kMaxBuckets + 1] = {0};
+        for (int b = 0; b < kMaxBuckets; ++b) pos[b + 1] = pos[b] + add[b];
+        for (uint32_t i = 0; i < n; ++i) order[pos[cls[i]]++] = i;
+    }
+    const uint64_t kChunkLits = 1ull << 24, kChunkClauses = 1ull << 21;
+    std::vector<uint32_t> cuts{0};
+    std::vector<uint64_t> chunk_lits;
+    size_t stage_bytes = 0;
+    {
+        uint32_t p = 0;
+        while (p < n) {
+            const int b = cls[order[p]];
+            uint32_t q = p;
+            uint64_t nl = 0;
+            while (q < n && cls[order[q]] == b && (q - p) < kChunkClauses) {
+                const uint32_t i = order[q];
+                const uint64_t L = offsets[i + 1] - offsets[i];
+                if (q > p && nl + L > kChunkLits) break;
+                nl += L;
+                ++q;
+            }
+            cuts.push_back(q);
+            chunk_lits.push_back(nl);
+            stage_bytes = std::max<size_t>(stage_bytes, round_up(nl * 4, 256) + round_up((uint64_t)(q - p + 1) * 8, 256) +
+                                                            round_up((uint64_t)(q - p) * 4, 256));
+            p = q;
+        }
+    }
+    c.device_stage(stage_bytes);  // may raise CAPACITY; nothing has changed yet
+    c.host_stage(stage_bytes);
+
+    // ---- capacity: every bucket that must grow, checked against the budget up front
+    uint64_t new_cap[kMaxBuckets] = {0};
+    uint64_t grow_bytes = 0;
+    for (int b = 0; b < kMaxBuckets; ++b) {
+        Bucket &B = c.buckets[b];
+        if (!add[b] || B.n_slots + add[b] <= B.cap_slots) continue;
+        const uint64_t S = 1ull << B.stride_log2;
+        const uint64_t min_slots = std::max<uint64_t>(c.T, std::min<uint64_t>(256, (1ull << 20) / S));
+        uint64_t want = std::max<uint64_t>({B.n_slots + add[b], B.cap_slots + B.cap_slots / 2, min_slots});
+        new_cap[b] = round_up(want, c.T);
+        grow_bytes += bucket_bytes(new_cap[b], B.stride_log2);
+    }
+    GSS_REQUIRE(c.cfg.hbm_budget_bytes == 0 || c.device_bytes + grow_bytes <= c.cfg.hbm_budget_bytes, GSS_ERR_CAPACITY,
+                "HBM budget exhausted by the clause store");
+    for (int b = 0; b < kMaxBuckets; ++b)
+        if (new_cap[b]) grow_bucket(c, c.buckets[b], new_cap[b]);
+
+    for (uint32_t i = 0; i < n; ++i) out_ids[i] = (uint32_t)(next + i);
+
+    // ---- upload chunk by chunk
+    uint64_t slot_cursor[kMaxBuckets];
+    for (int b = 0; b < kMaxBuckets; ++b) {
+        slot_cursor[b] = c.buckets[b].n_slots;
+        c.buckets[b].h_ids.resize(c.buckets[b].n_slots + add[b], kDeadId);
+        c.buckets[b].h_len.resize(c.buckets[b].n_slots + add[b], 0);
+    }
+    c.id_loc.resize(next + n, kNoLoc);
+
+    for (size_t ch = 0; ch + 1 < cuts.size(); ++ch) {
+        const uint32_t p = cuts[ch], q = cuts[ch + 1];
+        const uint64_t nl = chunk_lits[ch];
+        const int b = cls[order[p]];
+        Bucket &B = c.buckets[b];
+        const uint32_t m = q - p;
+        // host staging: codes | coff[m+1] | ids[m]
+        const size_t codes_bytes = round_up(nl * 4, 256);
+        const size_t coff_bytes = round_up((uint64_t)(m + 1) * 8, 256);
+        const size_t ids_bytes = round_up((uint64_t)m * 4, 256);
+        const size_t bytes = codes_bytes + coff_bytes + ids_bytes;
+        char *h = (char *)c.host_stage(bytes);
+        char *d = (char *)c.device_stage(bytes);
+        uint32_t *hcodes = (uint32_t *)h;
+        uint64_t *hcoff = (uint64_t *)(h + codes_bytes);
+        uint32_t *hids = (uint32_t *)(h + codes_bytes + coff_bytes);
+        uint64_t off = 0;
+        const uint64_t slot0 = slot_cursor[b];
+        for (uint32_t r = 0; r < m; ++r) {
+            const uint32_t i = order[p + r];
+            const uint64_t L = offsets[i + 1] - offsets[i];
+            hcoff[r] = off;
+            uint32_t *dst = hcodes + off;
+            for (uint64_t k = 0; k < L; ++k) dst[k] = lit_code(lits[offsets[i] + k]);
+            std::sort(dst, dst + L);
+            off += L;
+            const uint32_t id = (uint32_t)(next + i);
+            hids[r] = id;
+            const uint64_t slot = slot0 + r;
+            c.id_loc[id] = ((uint64_t)b << 40) | slot;
+            B.h_ids[slot] = id;
+            B.h_len[slot] = (uint32_t)L;
+        }
+        hcoff[m] = off;
+        GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
+        const uint32_t *dcodes = (const uint32_t *)d;
+        const uint64_t *dcoff = (const uint64_t *)(d + codes_bytes);
+        const uint32_t *dids = (const uint32_t *)(d + codes_bytes + coff_bytes);
+        hipLaunchKernelGGL(k_append_lits, dim3(grid_for(nl)), dim3(256), 0, c.stream, B.lits, B.stride_log2, c.T,
+                           slot0, dcodes, dcoff, m, nl);
+        GSS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_append_meta, dim3(grid_for(m)), dim3(256), 0, c.stream, B.len, B.ids, slot0, dcoff,
+                           dids, m);
+        GSS_HIP(hipGetLastError());
+        c.sync();  // the staging buffers are reused by the next chunk
+        slot_cursor[b] += m;
+        B.n_slots = slot_cursor[b];
+        B.n_lits += nl;
+    }
+    c.live += n;
+    GSS_API_END
+}
+
+extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint32_t n) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    if (n == 0) return GSS_OK;
+    GSS_REQUIRE(ids != nullptr, GSS_ERR_INVALID_ARG, "null argument");
+    // ---- validate: issued, live, and each id once
+    std::vector<uint32_t> sorted(ids, ids + n);
+    std::sort(sorted.begin(), sorted.end());
+    for (uint32_t i = 0; i < n; ++i) {
+        GSS_REQUIRE(sorted[i] < c.id_loc.size() && c.id_loc[sorted[i]] != kNoLoc, GSS_ERR_UNKNOWN_ID,
+                    "clause id " + std::to_string(sorted[i]) + " is not live");
+        GSS_REQUIRE(i == 0 || sorted[i] != sorted[i - 1], GSS_ERR_UNKNOWN_ID,
+                    "clause id " + std::to_string(sorted[i]) + " repeated");
+    }
+    // ---- apply
+    std::vector<uint64_t> per[kMaxBuckets];
+    for (uint32_t i = 0; i < n; ++i) {
+        uint64_t loc = c.id_loc[ids[i]];
+        int b = (int)(loc >> 40);
+        uint64_t slot = loc & ((1ull << 40) - 1);
+        per[b].push_back(slot);
+        Bucket &B = c.buckets[b];
+        B.n_lits -= B.h_len[slot];
+        B.h_ids[slot] = kDeadId;
+        B.h_len[slot] = 0;
+        B.n_dead++;
+        c.id_loc[ids[i]] = kNoLoc;
+    }
+    c.live -= n;
+    for (int b = 0; b < kMaxBuckets; ++b) {
+        if (per[b].empty()) continue;
+        Bucket &B = c.buckets[b];
+        const size_t bytes = per[b].size() * 8;
+        void *h = c.host_stage(bytes);
+        void *d = c.device_stage(bytes);
+        std::memcpy(h, per[b].data(), bytes);
+        GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
+        hipLaunchKernelGGL(k_tombstone, dim3(grid_for(per[b].size())), dim3(256), 0, c.stream, B.len, B.ids,
+                           (const uint64_t *)d, (uint32_t)per[b].size());
+        GSS_HIP(hipGetLastError());
+        c.sync();
+    }
+    // ---- reclaim: compact a class once more than a quarter of its slots are dead
+    for (int b = 0; b < kMaxBuckets; ++b) {
+        Bucket &B = c.buckets[b];
+        if (B.n_dead && B.n_dead * 4 > B.n_slots) compact_bucket(c, b);
+    }
+    GSS_API_END
+}
+
+extern "C" gss_status gss_store_info(const gss_ctx *ctx, uint64_t *live_clauses, uint64_t *next_id,
+                                     uint64_t *device_bytes) {
+    const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+    if (!c) return GSS_ERR_INVALID_ARG;
+    if (live_clauses) *live_clauses = c->live;
+    if (next_id) *next_id = c->id_loc.size();
+    if (device_bytes) *device_bytes = c->device_bytes;
+    return GSS_OK;
+}

@@ -85,23 +85,39 @@ def lengths_mix(rng, n: int, mix=LENGTH_MIX) -> np.ndarray:
 
 def _distinct_rows(rng, n_rows: int, length: int, n_vars: int, var_weights=None) -> np.ndarray:
     """n_rows rows of `length` distinct variables in 1..n_vars (uniform, or drawn
-    from the cumulative weights `var_weights` when given)."""
-    def draw(k):
+    from the cumulative weights `var_weights` when given).  Entries that repeat an
+    earlier entry of their row are redrawn until every row is distinct."""
+    if length > n_vars:
+        raise ValueError("more distinct variables requested than exist")
+
+    def draw(shape):
         if var_weights is None:
-            return rng.integers(1, n_vars + 1, size=(k, length), dtype=np.int64)
-        r = rng.random((k, length))
-        return np.searchsorted(var_weights, r, side="right").astype(np.int64) + 1
-    rows = draw(n_rows)
+            return rng.integers(1, n_vars + 1, size=shape, dtype=np.int64)
+        return np.searchsorted(var_weights, rng.random(shape), side="right").astype(np.int64) + 1
+
+    rows = draw((n_rows, length))
     if length == 1:
         return rows
     todo = np.arange(n_rows)
     while len(todo):
-        s = np.sort(rows[todo], axis=1)
-        bad = todo[(s[:, 1:] == s[:, :-1]).any(axis=1)]
-        if len(bad) == 0:
+        # rows that still hold a repeat (a plain sort is the cheap test)
+        srt = np.sort(rows[todo], axis=1)
+        todo = todo[(srt[:, 1:] == srt[:, :-1]).any(axis=1)]
+        if len(todo) == 0:
             break
-        rows[bad] = draw(len(bad))
-        todo = bad
+        sub = rows[todo]
+        order = np.argsort(sub, axis=1, kind="stable")
+        srt = np.take_along_axis(sub, order, axis=1)
+        dup_sorted = np.zeros_like(srt, dtype=bool)
+        dup_sorted[:, 1:] = srt[:, 1:] == srt[:, :-1]
+        if not dup_sorted.any():
+            break
+        dup = np.zeros_like(dup_sorted)
+        np.put_along_axis(dup, order, dup_sorted, axis=1)   # later copies of a value
+        r_idx, c_idx = np.nonzero(dup)
+        sub[r_idx, c_idx] = draw(len(r_idx))
+        rows[todo] = sub
+        todo = todo[np.unique(r_idx)]
     return rows
 
 

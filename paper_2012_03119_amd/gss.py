@@ -1,0 +1,358 @@
+"""Python binding of libgss (the C ABI in include/gss.h), by ctypes.
+
+Argument marshalling only: every step of the clause test runs in the HIP library.
+The module-level functions carry the ABI's names; ``Context`` wraps them for
+convenience.  PyTorch, when present, provides device memory (the caching
+allocator, through the allocator hooks) and the stream; nothing else.
+
+The library must be built first (``python -m paper_2012_03119_amd.build``); if it
+is missing, loading raises -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgss.so")
+
+GSS_OK = 0
+GSS_ERR_INVALID_ARG = -1
+GSS_ERR_BAD_LITERAL = -2
+GSS_ERR_UNKNOWN_ID = -3
+GSS_ERR_CAPACITY = -4
+GSS_ERR_REPORT_OVERFLOW = -5
+GSS_ERR_DEVICE = -6
+GSS_ERR_STATE = -7
+
+GSS_TEST_FALSIFIED = 0
+GSS_TEST_TRIGGER = 1
+GSS_TEST_NO_EARLY_EXIT = 2
+GSS_TEST_SORTED = 4
+GSS_TEST_DENSE = 8
+GSS_TEST_NO_REGROW = 16
+GSS_TEST_NO_HOT = 32
+
+REPORT_DTYPE = np.dtype([("clause_id", "<u4"), ("word", "<u4"), ("mask", "<u8")])
+
+_ERR_NAMES = {
+    GSS_ERR_INVALID_ARG: "GSS_ERR_INVALID_ARG", GSS_ERR_BAD_LITERAL: "GSS_ERR_BAD_LITERAL",
+    GSS_ERR_UNKNOWN_ID: "GSS_ERR_UNKNOWN_ID", GSS_ERR_CAPACITY: "GSS_ERR_CAPACITY",
+    GSS_ERR_REPORT_OVERFLOW: "GSS_ERR_REPORT_OVERFLOW", GSS_ERR_DEVICE: "GSS_ERR_DEVICE",
+    GSS_ERR_STATE: "GSS_ERR_STATE",
+}
+
+
+class GssError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class gss_config(ctypes.Structure):
+    _fields_ = [
+        ("num_vars", ctypes.c_uint32),
+        ("max_slots", ctypes.c_uint32),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("report_capacity", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p),
+        ("dev_alloc", ALLOC_FN),
+        ("dev_free", FREE_FN),
+        ("alloc_user", ctypes.c_void_p),
+        ("hot_vars", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class gss_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "tests_run", "last_pairs", "last_reports", "last_literals", "live_clauses", "active_slots",
+        "device_bytes", "compactions", "regrows", "kernel_launches")] + [
+        ("last_kernel_ms", ctypes.c_double), ("total_kernel_ms", ctypes.c_double),
+        ("timed_launches", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libgss.so and declares its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2012_03119_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "gss_create": ([ctypes.POINTER(gss_config), ctypes.POINTER(P)], ctypes.c_int32),
+        "gss_destroy": ([P], None),
+        "gss_last_error": ([P], ctypes.c_char_p),
+        "gss_add_clauses": ([P, P, P, u32, P], ctypes.c_int32),
+        "gss_remove_clauses": ([P, P, u32], ctypes.c_int32),
+        "gss_store_info": ([P, P, P, P], ctypes.c_int32),
+        "gss_set_assignments": ([P, u32, u32, P], ctypes.c_int32),
+        "gss_set_var_values": ([P, u32, u32, u32, P, P], ctypes.c_int32),
+        "gss_clear_slots": ([P, u32, u32], ctypes.c_int32),
+        "gss_test": ([P, u32, P], ctypes.c_int32),
+        "gss_fetch_reports": ([P, P, u64, P], ctypes.c_int32),
+        "gss_fetch_masks": ([P, P, u32, P], ctypes.c_int32),
+        "gss_get_stats": ([P, ctypes.POINTER(gss_stats)], ctypes.c_int32),
+        "gss_reset_stats": ([P], ctypes.c_int32),
+        "gss_get_stream": ([P, ctypes.POINTER(P)], ctypes.c_int32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(ctx, rc: int):
+    if rc != GSS_OK:
+        msg = load_library().gss_last_error(ctx)
+        raise GssError(rc, msg.decode() if msg else "")
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _data_ptr(x, dtype):
+    """(pointer, keep-alive, n_elements) for a numpy array or a torch tensor
+    (host or device), converted to the dtype if needed."""
+    try:
+        import torch
+        if isinstance(x, torch.Tensor):
+            tdt = {np.int8: torch.int8, np.uint32: torch.int32, np.int32: torch.int32}[dtype]
+            t = x.contiguous()
+            if t.dtype != tdt:
+                t = t.to(tdt)
+            return ctypes.c_void_p(t.data_ptr()), t, t.numel()
+    except ImportError:  # pragma: no cover
+        pass
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return _np_ptr(a), a, a.size
+
+
+# ---------------------------------------------------------------------------
+# ABI-named functions
+# ---------------------------------------------------------------------------
+
+def gss_create(cfg: gss_config):
+    lib = load_library()
+    ctx = ctypes.c_void_p()
+    rc = lib.gss_create(ctypes.byref(cfg), ctypes.byref(ctx))
+    if rc != GSS_OK:
+        msg = lib.gss_last_error(None)
+        raise GssError(rc, msg.decode() if msg else "")
+    return ctx
+
+
+def gss_destroy(ctx) -> None:
+    load_library().gss_destroy(ctx)
+
+
+def gss_add_clauses(ctx, lits, offsets) -> np.ndarray:
+    lits = np.ascontiguousarray(lits, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = len(offsets) - 1
+    ids = np.empty(max(n, 0), dtype=np.uint32)
+    if n <= 0:
+        return ids
+    _check(ctx, load_library().gss_add_clauses(ctx, _np_ptr(lits), _np_ptr(offsets), n, _np_ptr(ids)))
+    return ids
+
+
+def gss_remove_clauses(ctx, ids) -> None:
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    _check(ctx, load_library().gss_remove_clauses(ctx, _np_ptr(ids), len(ids)))
+
+
+def gss_store_info(ctx):
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(ctx, load_library().gss_store_info(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return dict(live_clauses=a.value, next_id=b.value, device_bytes=c.value)
+
+
+def gss_set_assignments(ctx, first_slot: int, values) -> None:
+    """values: int8 [n_slots][num_vars], numpy or torch (host or device)."""
+    n_slots = int(values.shape[0]) if len(values.shape) == 2 else 0
+    ptr, keep, _ = _data_ptr(values, np.int8)
+    _check(ctx, load_library().gss_set_assignments(ctx, first_slot, n_slots, ptr))
+    del keep
+
+
+def gss_set_var_values(ctx, first_slot: int, vars_, values) -> None:
+    """vars_: distinct variables (host); values: int8 [len(vars_)][n_slots] (host or device)."""
+    vars_ = np.ascontiguousarray(vars_, dtype=np.uint32)
+    n_slots = int(values.shape[1])
+    ptr, keep, _ = _data_ptr(values, np.int8)
+    _check(ctx, load_library().gss_set_var_values(ctx, first_slot, n_slots, len(vars_), _np_ptr(vars_), ptr))
+    del keep
+
+
+def gss_clear_slots(ctx, first_slot: int, n_slots: int) -> None:
+    _check(ctx, load_library().gss_clear_slots(ctx, first_slot, n_slots))
+
+
+def gss_test(ctx, flags: int = 0) -> int:
+    n = ctypes.c_uint64()
+    _check(ctx, load_library().gss_test(ctx, flags, ctypes.byref(n)))
+    return n.value
+
+
+def gss_fetch_reports(ctx, cap: int) -> np.ndarray:
+    out = np.empty(cap, dtype=REPORT_DTYPE)
+    n = ctypes.c_uint64()
+    _check(ctx, load_library().gss_fetch_reports(ctx, _np_ptr(out) if cap else None, cap, ctypes.byref(n)))
+    return out[:n.value]
+
+
+def gss_fetch_masks(ctx, ids, n_words: int) -> np.ndarray:
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    out = np.zeros((len(ids), n_words), dtype=np.uint64)
+    if len(ids):
+        _check(ctx, load_library().gss_fetch_masks(ctx, _np_ptr(ids), len(ids), _np_ptr(out)))
+    return out
+
+
+def gss_get_stats(ctx) -> dict:
+    s = gss_stats()
+    _check(ctx, load_library().gss_get_stats(ctx, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in gss_stats._fields_}
+
+
+def gss_reset_stats(ctx) -> None:
+    _check(ctx, load_library().gss_reset_stats(ctx))
+
+
+def gss_get_stream(ctx) -> int:
+    p = ctypes.c_void_p()
+    _check(ctx, load_library().gss_get_stream(ctx, ctypes.byref(p)))
+    return p.value or 0
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+class Context:
+    """One clause store plus one set of assignment slots on the current GPU."""
+
+    def __init__(self, num_vars: int, max_slots: int = 64, *, hbm_budget_bytes: int = 0,
+                 report_capacity: int = 1 << 16, hot_vars: int = 0, use_torch: bool = True):
+        self.num_vars = int(num_vars)
+        self.max_slots = int(max_slots)
+        self.n_words = self.max_slots // 64
+        self._keep = []
+        cfg = gss_config()
+        cfg.num_vars = self.num_vars
+        cfg.max_slots = self.max_slots
+        cfg.hbm_budget_bytes = hbm_budget_bytes
+        cfg.report_capacity = report_capacity
+        cfg.hot_vars = hot_vars
+        self.torch_stream = None
+        if use_torch:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible to torch")
+            dev = torch.cuda.current_device()
+            self.torch_stream = torch.cuda.Stream(device=dev)   # default priority
+            cfg.stream = self.torch_stream.cuda_stream
+
+            def _alloc(size, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(size, dev, stream)
+                except Exception:
+                    return None
+
+            def _free(ptr, stream, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            cfg.dev_alloc = ALLOC_FN(_alloc)
+            cfg.dev_free = FREE_FN(_free)
+            self._keep += [cfg.dev_alloc, cfg.dev_free]
+        self._cfg = cfg
+        self.ctx = gss_create(cfg)
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "ctx", None):
+            gss_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _sync_inputs(self, *xs):
+        # device inputs produced on torch's current stream must be ready for ours
+        if self.torch_stream is None:
+            return
+        import torch
+        if any(isinstance(x, torch.Tensor) and x.is_cuda for x in xs):
+            self.torch_stream.wait_stream(torch.cuda.current_stream())
+
+    # -- ABI calls
+    def add_clauses(self, lits, offsets) -> np.ndarray:
+        return gss_add_clauses(self.ctx, lits, offsets)
+
+    def remove_clauses(self, ids) -> None:
+        gss_remove_clauses(self.ctx, ids)
+
+    def store_info(self) -> dict:
+        return gss_store_info(self.ctx)
+
+    def set_assignments(self, first_slot: int, values) -> None:
+        self._sync_inputs(values)
+        gss_set_assignments(self.ctx, first_slot, values)
+
+    def set_var_values(self, first_slot: int, vars_, values) -> None:
+        self._sync_inputs(values)
+        gss_set_var_values(self.ctx, first_slot, vars_, values)
+
+    def clear_slots(self, first_slot: int, n_slots: int) -> None:
+        gss_clear_slots(self.ctx, first_slot, n_slots)
+
+    def test(self, flags: int = 0) -> int:
+        return gss_test(self.ctx, flags)
+
+    def fetch_reports(self, cap: Optional[int] = None) -> np.ndarray:
+        if cap is None:
+            cap = self.stats()["last_reports"]
+        return gss_fetch_reports(self.ctx, int(cap))
+
+    def fetch_masks(self, ids) -> np.ndarray:
+        return gss_fetch_masks(self.ctx, ids, self.n_words)
+
+    def stats(self) -> dict:
+        return gss_get_stats(self.ctx)
+
+    def reset_stats(self) -> None:
+        gss_reset_stats(self.ctx)
+
+    @property
+    def stream(self) -> int:
+        return gss_get_stream(self.ctx)
+
+
+def sort_reports(r: np.ndarray) -> np.ndarray:
+    """Orders records by (clause_id, word), the canonical order for comparisons."""
+    return np.sort(r, order=["clause_id", "word"])

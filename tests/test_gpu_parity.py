@@ -1,0 +1,312 @@
+"""Parity of the HIP path with the oracle, through the C ABI (GPU).
+
+Every test builds seeded inputs with the workload generator, runs them through
+libgss and through the oracle, and compares the results element by element:
+bit-exact, since the method is integer and bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import csr, full_values, gpu_dense, mismatch_summary, new_context, oracle_dense, reports_to_dense
+from paper_2012_03119_amd import gen, gss
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(got, want):
+    assert got.shape == want.shape
+    assert np.array_equal(got, want), mismatch_summary(got, want)
+
+
+# ---------------------------------------------------------------------------
+# the tiny workload, seeds 1..10
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(1, 11))
+def test_tiny_seeds(seed):
+    w = gen.tiny(seed)
+    print(f"tiny seed {seed}", flush=True)
+    with new_context(w.n_vars, 64) as ctx:
+        ids = ctx.add_clauses(w.lits, w.offsets)
+        assert np.array_equal(ids, np.arange(w.n_clauses, dtype=np.uint32))
+        ctx.set_assignments(0, w.values)
+        got = gpu_dense(ctx, w.n_clauses)
+    want = oracle.masks(w.lits, w.offsets, w.values)
+    _check(got, want)
+    for c, a in w.planted.tolist():
+        assert (int(got[c, a // 64]) >> (a % 64)) & 1
+
+
+def test_tiny_dense_output():
+    w = gen.tiny(1)
+    with new_context(w.n_vars, 64) as ctx:
+        ids = ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, w.values)
+        assert ctx.test(gss.GSS_TEST_DENSE) == 0
+        got = ctx.fetch_masks(ids)
+    _check(got, oracle.masks(w.lits, w.offsets, w.values))
+
+
+# ---------------------------------------------------------------------------
+# every lanes-per-clause width, partial slot ranges, several tiles + ragged tails
+# ---------------------------------------------------------------------------
+
+def _small_workload(seed, n_clauses, n_vars, max_len=70):
+    rng = np.random.default_rng(seed)
+    # mostly short clauses (hits), some long ones crossing literal-block boundaries
+    lengths = np.where(rng.random(n_clauses) < 0.8, rng.integers(1, 7, n_clauses), rng.integers(7, max_len + 1, n_clauses))
+    lits, offsets = gen.random_clauses(rng, lengths, n_vars)
+    return rng, lits, offsets
+
+
+@pytest.mark.parametrize("max_slots,first,count", [
+    (64, 0, 64), (64, 3, 50), (128, 0, 128), (192, 7, 170), (320, 64, 200),
+    (512, 0, 512), (1024, 33, 900), (2048, 0, 2048), (4096, 100, 3900),
+])
+@pytest.mark.parametrize("mode", ["falsified", "trigger"])
+def test_widths_and_partial_slots(max_slots, first, count, mode):
+    n_vars = 300
+    rng, lits, offsets = _small_workload(max_slots + first, 2500, n_vars)
+    vals_n = gen.assignments_bernoulli(rng, count, n_vars, rng.uniform(0.3, 0.95, count))
+    vals, active = full_values(vals_n, max_slots, first)
+    print(f"widths max_slots={max_slots} first={first} count={count} mode={mode}", flush=True)
+    flags = gss.GSS_TEST_TRIGGER if mode == "trigger" else 0
+    with new_context(n_vars, max_slots) as ctx:
+        ctx.add_clauses(lits, offsets)
+        ctx.set_assignments(first, vals_n)
+        got = gpu_dense(ctx, len(offsets) - 1, flags)
+        got_ne = gpu_dense(ctx, len(offsets) - 1, flags | gss.GSS_TEST_NO_EARLY_EXIT)
+    want = oracle_dense(lits, offsets, vals, active, mode)
+    _check(got, want)
+    _check(got_ne, want)
+
+
+@pytest.mark.parametrize("max_slots", [64, 1024])
+@pytest.mark.parametrize("mode", ["falsified", "trigger"])
+def test_hot_rows_in_lds(max_slots, mode):
+    # variables drawn Zipf-like so the first rows are hot; staging must not change results
+    n_vars = 4000
+    rng = np.random.default_rng(5)
+    lengths = rng.integers(1, 40, 6000)
+    lits, offsets = gen.random_clauses(rng, lengths, n_vars, gen.zipf_weights(n_vars, 1.1))
+    vals_n = gen.assignments_bernoulli(rng, max_slots, n_vars, rng.uniform(0.5, 0.95, max_slots))
+    vals, active = full_values(vals_n, max_slots)
+    flags = gss.GSS_TEST_TRIGGER if mode == "trigger" else 0
+    want = oracle_dense(lits, offsets, vals, active, mode)
+    for hot in (0, 63, 200):
+        print(f"hot_vars={hot} max_slots={max_slots} mode={mode}", flush=True)
+        with new_context(n_vars, max_slots, hot_vars=hot) as ctx:
+            ctx.add_clauses(lits, offsets)
+            ctx.set_assignments(0, vals_n)
+            _check(gpu_dense(ctx, len(offsets) - 1, flags), want)
+            _check(gpu_dense(ctx, len(offsets) - 1, flags | gss.GSS_TEST_NO_HOT), want)
+
+
+# ---------------------------------------------------------------------------
+# edge cases of the method
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("max_slots", [64, 256, 1024])
+def test_edge_clauses(max_slots):
+    n_vars = 40
+    rng = np.random.default_rng(9)
+    clauses = [[1], [-1], [2, 2], [3, -3], [4, -4, 5], [5, 5, -6, -6], [7, 8, 9, 7],
+               list(range(1, 41)), [-(v % 40 + 1) for v in range(300)],
+               [(-1) ** v * (v % 40 + 1) for v in range(4097)],
+               [(v % 40 + 1) for v in range(65536)]]
+    clauses += [[int(x) for x in rng.choice(np.r_[-40:0, 1:41], size=rng.integers(1, 5))] for _ in range(500)]
+    lits, offsets = csr(clauses)
+    vals_n = gen.assignments_bernoulli(rng, max_slots, n_vars, 0.9)
+    vals_n[: max_slots // 4] = -1          # some slots with every variable F
+    vals_n[max_slots // 4: max_slots // 2] = 0   # all-Undef slots
+    vals, active = full_values(vals_n, max_slots)
+    for mode, flags in (("falsified", 0), ("trigger", gss.GSS_TEST_TRIGGER)):
+        print(f"edge max_slots={max_slots} mode={mode}", flush=True)
+        with new_context(n_vars, max_slots) as ctx:
+            ctx.add_clauses(lits, offsets)
+            ctx.set_assignments(0, vals_n)
+            got = gpu_dense(ctx, len(clauses), flags)
+        _check(got, oracle_dense(lits, offsets, vals, active, mode))
+
+
+def test_empty_store_and_no_active_slots():
+    with new_context(10, 128) as ctx:
+        assert ctx.test() == 0                       # no clauses
+        assert len(ctx.fetch_reports(10)) == 0
+        ctx.add_clauses(np.array([1, -2, 3], np.int32), np.array([0, 1, 3], np.int64))
+        assert ctx.test() == 0                       # no active slot
+        ctx.set_assignments(0, np.full((1, 10), -1, np.int8))
+        n = ctx.test()
+        r = gss.sort_reports(ctx.fetch_reports(n))
+        assert n == 1 and r["clause_id"][0] == 0 and r["mask"][0] == 1
+
+
+def test_all_undef_falsifies_nothing():
+    w = gen.tiny(2)
+    with new_context(w.n_vars, 1024) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, np.zeros((1024, w.n_vars), np.int8))
+        assert ctx.test() == 0
+
+
+# ---------------------------------------------------------------------------
+# store mutations, deltas, slot clearing
+# ---------------------------------------------------------------------------
+
+def test_add_remove_compact_sequence():
+    n_vars, max_slots = 500, 256
+    rng = np.random.default_rng(21)
+    vals_n = gen.assignments_bernoulli(rng, max_slots, n_vars, 0.8)
+    vals, active = full_values(vals_n, max_slots)
+    model = {}  # id -> clause
+    with new_context(n_vars, max_slots) as ctx:
+        ctx.set_assignments(0, vals_n)
+        next_id = 0
+        for step in range(12):
+            k = int(rng.integers(200, 3000))
+            _, lits, offsets = _small_workload(1000 + step, k, n_vars, max_len=150)
+            ids = ctx.add_clauses(lits, offsets)
+            assert np.array_equal(ids, np.arange(next_id, next_id + k, dtype=np.uint32))
+            next_id += k
+            for i, cid in enumerate(ids.tolist()):
+                model[cid] = lits[offsets[i]:offsets[i + 1]]
+            live = np.array(sorted(model), dtype=np.uint32)
+            kill = rng.choice(live, size=int(len(live) * rng.uniform(0.1, 0.5)), replace=False)
+            ctx.remove_clauses(kill)
+            for cid in kill.tolist():
+                del model[cid]
+            print(f"mutation step {step}: live {len(model)}", flush=True)
+            assert ctx.store_info()["live_clauses"] == len(model)
+            got = gpu_dense(ctx, next_id)
+            ids_live = np.array(sorted(model), dtype=np.int64)
+            l2, o2 = csr([model[i] for i in ids_live.tolist()])
+            want = np.zeros_like(got)
+            want[ids_live] = oracle_dense(l2, o2, vals, active)
+            _check(got, want)
+        assert ctx.stats()["compactions"] > 0
+        with pytest.raises(gss.GssError) as e:
+            ctx.remove_clauses(kill[:1])           # already removed
+        assert e.value.code == gss.GSS_ERR_UNKNOWN_ID
+
+
+def test_var_value_deltas_and_flips():
+    w = gen.paper(3, n_clauses=30_000, n_vars=5_000, n_slots=512)
+    vals = w.values.copy()
+    rng = np.random.default_rng(4)
+    with new_context(w.n_vars, 512) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, vals)
+        _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, vals))
+        for r, flip in enumerate(gen.flip_rounds(7, w.n_vars, 4)):
+            gen.apply_flips(vals, flip)
+            ctx.set_var_values(0, flip, np.ascontiguousarray(vals[:, flip - 1].T))
+            print(f"flip round {r + 1}", flush=True)
+            _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, vals))
+        # a partial-range delta on unaligned slots
+        vs = np.sort(rng.choice(w.n_vars, 700, replace=False)) + 1
+        new = rng.integers(-1, 2, size=(700, 77)).astype(np.int8)
+        ctx.set_var_values(100, vs, new)
+        vals[100:177, vs - 1] = new.T
+        _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, vals))
+
+
+def test_clear_slots():
+    w = gen.tiny(3)
+    with new_context(w.n_vars, 192) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        vals_n = np.concatenate([w.values, w.values[::-1], w.values[:50]])
+        ctx.set_assignments(0, vals_n)
+        ctx.clear_slots(30, 100)
+        vals, active = full_values(vals_n, 192)
+        vals[30:130] = 0
+        active[30:130] = False
+        _check(gpu_dense(ctx, w.n_clauses), oracle_dense(w.lits, w.offsets, vals, active))
+        ctx.set_assignments(40, w.values[:10])    # reuse freed slots
+        vals[40:50] = w.values[:10]
+        active[40:50] = True
+        _check(gpu_dense(ctx, w.n_clauses), oracle_dense(w.lits, w.offsets, vals, active))
+
+
+def test_device_inputs():
+    import torch
+    w = gen.tiny(6)
+    with new_context(w.n_vars, 64) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, torch.from_numpy(w.values).cuda())
+        _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, w.values))
+        vals = w.values.copy()
+        vs = np.arange(1, w.n_vars + 1, 3)
+        vals[:, vs - 1] = -vals[:, vs - 1]
+        ctx.set_var_values(0, vs, torch.from_numpy(np.ascontiguousarray(vals[:, vs - 1].T)).cuda())
+        _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, vals))
+
+
+# ---------------------------------------------------------------------------
+# errors and capacity
+# ---------------------------------------------------------------------------
+
+def test_argument_errors_leave_state_unchanged():
+    with new_context(10, 64) as ctx:
+        ctx.add_clauses(np.array([1, 2], np.int32), np.array([0, 2], np.int64))
+        cases = [
+            (np.array([1, 11], np.int32), np.array([0, 2], np.int64), gss.GSS_ERR_BAD_LITERAL),
+            (np.array([1, 0], np.int32), np.array([0, 2], np.int64), gss.GSS_ERR_BAD_LITERAL),
+            (np.array([1, 2], np.int32), np.array([0, 0, 2], np.int64), gss.GSS_ERR_INVALID_ARG),
+        ]
+        for lits, offs, code in cases:
+            with pytest.raises(gss.GssError) as e:
+                ctx.add_clauses(lits, offs)
+            assert e.value.code == code
+        assert ctx.store_info() == dict(live_clauses=1, next_id=1, device_bytes=ctx.store_info()["device_bytes"])
+        with pytest.raises(gss.GssError) as e:
+            ctx.fetch_reports(1)
+        assert e.value.code == gss.GSS_ERR_STATE
+        with pytest.raises(gss.GssError) as e:
+            ctx.set_assignments(60, np.zeros((5, 10), np.int8))
+        assert e.value.code == gss.GSS_ERR_CAPACITY
+        bad = np.zeros((1, 10), np.int8)
+        bad[0, 3] = 2
+        with pytest.raises(gss.GssError) as e:
+            ctx.set_assignments(0, bad)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+        with pytest.raises(gss.GssError) as e:
+            ctx.set_var_values(0, [1], np.zeros((1, 4), np.int8))   # slots not active
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+        with pytest.raises(gss.GssError) as e:
+            ctx.remove_clauses([0, 0])
+        assert e.value.code == gss.GSS_ERR_UNKNOWN_ID
+        assert ctx.store_info()["live_clauses"] == 1
+        with pytest.raises(gss.GssError) as e:
+            ctx.test(1 << 20)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+
+
+def test_report_overflow_and_regrow():
+    w = gen.tiny(7)
+    want = oracle.masks(w.lits, w.offsets, w.values)
+    n_want = int(np.count_nonzero(want))
+    with new_context(w.n_vars, 64, report_capacity=16) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, w.values)
+        with pytest.raises(gss.GssError) as e:
+            ctx.test(gss.GSS_TEST_NO_REGROW)
+        assert e.value.code == gss.GSS_ERR_REPORT_OVERFLOW
+        assert ctx.stats()["last_reports"] == n_want     # exact count despite overflow
+        assert len(ctx.fetch_reports(10 ** 6)) == 16     # the records that fit
+        got = gpu_dense(ctx, w.n_clauses)                # grows and reruns
+        assert ctx.stats()["regrows"] >= 1
+    _check(got, want)
+
+
+def test_hbm_budget():
+    w = gen.tiny(8)
+    with new_context(w.n_vars, 64, hbm_budget_bytes=4 << 20) as ctx:
+        with pytest.raises(gss.GssError) as e:
+            big = gen.paper(1, n_clauses=200_000, n_vars=w.n_vars, n_slots=64)
+            ctx.add_clauses(big.lits, big.offsets)
+        assert e.value.code == gss.GSS_ERR_CAPACITY
+        assert ctx.store_info()["live_clauses"] == 0
+        ctx.add_clauses(w.lits, w.offsets)             # a small batch still fits
+        ctx.set_assignments(0, w.values)
+        _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, w.values))
