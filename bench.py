@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--slots", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--hot-vars", type=int, default=0)
+    ap.add_argument("--report-capacity", type=int, default=1 << 20)
     ap.add_argument("--no-early-exit", action="store_true")
     ap.add_argument("--trigger", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -144,7 +145,7 @@ def main():
         flags |= gss.GSS_TEST_NO_EARLY_EXIT
     if args.trigger:
         flags |= gss.GSS_TEST_TRIGGER
-    ctx = gss.Context(w.n_vars, w.n_slots, hot_vars=args.hot_vars, report_capacity=1 << 20)
+    ctx = gss.Context(w.n_vars, w.n_slots, hot_vars=args.hot_vars, report_capacity=args.report_capacity)
     t0 = time.perf_counter()
     ctx.add_clauses(w.lits, w.offsets)
     log(f"clauses stored in {time.perf_counter() - t0:.1f} s")

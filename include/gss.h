@@ -76,7 +76,8 @@ typedef struct gss_config {
     uint32_t num_vars;          /* variables 1..num_vars (>= 1) */
     uint32_t max_slots;         /* assignment capacity: multiple of 64, 64..4096 (W = max_slots/64 words) */
     uint64_t hbm_budget_bytes;  /* cap on the context's device memory; 0 = no cap */
-    uint64_t report_capacity;   /* initial report buffer entries (grown by gss_test unless GSS_TEST_NO_REGROW) */
+    uint64_t report_capacity;   /* initial report buffer entries, split evenly over the test kernel's
+                                   wavefronts (at least 64 each); grown by gss_test unless GSS_TEST_NO_REGROW */
     void *stream;               /* borrowed hipStream_t; NULL = the context creates its own */
     gss_dev_alloc_fn dev_alloc; /* optional, see above */
     gss_dev_free_fn dev_free;
@@ -147,16 +148,19 @@ gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots);
 /* Tests every live clause against every active slot (Section 3.6: a GPU run tests
  * all clauses against all assignments not yet tested and reports every hit).
  * *out_n_reports receives the number of gss_report records (one per clause and
- * 64-slot word with at least one hit; 0 with GSS_TEST_DENSE).  If the report
- * buffer is too small it is grown within the HBM budget and the test repeated,
- * unless GSS_TEST_NO_REGROW: then GSS_ERR_REPORT_OVERFLOW is returned, the first
- * report_capacity records are kept and *out_n_reports holds the exact count.
- * Record order is unspecified unless GSS_TEST_SORTED. */
+ * 64-slot word with at least one hit; 0 with GSS_TEST_DENSE).  Each wavefront of
+ * the test kernel appends to its own segment of the report buffer; if one is too
+ * small the buffer is grown within the HBM budget and the test repeated, unless
+ * GSS_TEST_NO_REGROW: then GSS_ERR_REPORT_OVERFLOW is returned, *out_n_reports
+ * holds the exact count, and only the records that fit are kept (which ones is
+ * unspecified).  Records come in a deterministic order for a given store, slot
+ * set and device (GSS_TEST_SORTED, ordering by id and word, is reserved and
+ * rejected with GSS_ERR_INVALID_ARG by this version). */
 gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_reports);
 
 /* Copies the records of the last gss_test into out (host or device, room for cap
- * records).  *out_n receives the number copied: min(cap, records available).
- * GSS_ERR_STATE before the first test. */
+ * records) as one list.  *out_n receives the number copied: min(cap, records
+ * kept).  GSS_ERR_STATE before the first test. */
 gss_status gss_fetch_reports(gss_ctx *ctx, gss_report *out, uint64_t cap, uint64_t *out_n);
 
 /* After a gss_test with GSS_TEST_DENSE: copies the mask rows of n clause ids into

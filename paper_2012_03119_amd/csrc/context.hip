@@ -1,6 +1,7 @@
 // Context lifetime, device memory accounting, errors and statistics of libgss.
 #include "gss_internal.h"
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -146,17 +147,18 @@ static void destroy_ctx(Ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (auto &b : c->buckets) {
         c->dfree(b.lits);
-        c->dfree(b.len);
-        c->dfree(b.ids);
+        c->dfree(b.meta);
     }
     c->dfree(c->planes);
     c->dfree(c->active);
     c->dfree(c->reports);
-    c->dfree(c->counter);
+    c->dfree(c->seg_counts);
+    c->dfree(c->seg_offsets);
+    c->dfree(c->d_summary);
     c->dfree(c->dense);
     c->dfree(c->dstage);
     if (c->hstage) (void)hipHostFree(c->hstage);
-    if (c->h_counter) (void)hipHostFree(c->h_counter);
+    if (c->h_summary) (void)hipHostFree(c->h_summary);
     c->dfree(c->dsmall);
     c->dfree(c->d_desc);
     if (c->hsmall_desc) (void)hipHostFree(c->hsmall_desc);
@@ -218,10 +220,15 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         launch_fill_u64(*c, c->active, c->W, 0);
         c->h_active.assign(c->W, 0);
 
-        c->report_cap = cfg->report_capacity ? cfg->report_capacity : (1u << 16);
-        c->reports = (gss_report *)c->dalloc(c->report_cap * sizeof(gss_report));
-        c->counter = (unsigned long long *)c->dalloc(sizeof(unsigned long long));
-        GSS_HIP(hipHostMalloc(&c->h_counter, sizeof(unsigned long long), hipHostMallocDefault));
+        // one report segment per wavefront of the widest test launch
+        c->max_waves = (uint32_t)c->n_cu * kTestBlocksPerCU * kTestWavesPerBlock;
+        const uint64_t want = cfg->report_capacity ? cfg->report_capacity : (1u << 20);
+        c->seg_cap = (uint32_t)std::max<uint64_t>(kMinSegment, (want + c->max_waves - 1) / c->max_waves);
+        c->reports = (gss_report *)c->dalloc((uint64_t)c->max_waves * c->seg_cap * sizeof(gss_report));
+        c->seg_counts = (uint32_t *)c->dalloc((uint64_t)c->max_waves * 4);
+        c->seg_offsets = (uint64_t *)c->dalloc(((uint64_t)c->max_waves + 1) * 8);
+        c->d_summary = (unsigned long long *)c->dalloc(4 * sizeof(unsigned long long));
+        GSS_HIP(hipHostMalloc(&c->h_summary, 4 * sizeof(unsigned long long), hipHostMallocDefault));
         c->dsmall = (uint32_t *)c->dalloc(256);
         c->d_desc = c->dalloc(kMaxBuckets * sizeof(BucketDesc));
         GSS_HIP(hipHostMalloc(&c->hsmall_desc, kMaxBuckets * sizeof(BucketDesc), hipHostMallocDefault));

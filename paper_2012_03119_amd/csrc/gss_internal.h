@@ -54,6 +54,11 @@ constexpr uint32_t kMaxClauseLen = 65536;
 constexpr uint32_t kDeadId = 0xFFFFFFFFu;
 constexpr uint64_t kNoLoc = ~0ull;
 
+// test kernel launch shape: persistent workgroups of 4 wavefronts, up to 8 per CU
+constexpr uint32_t kTestWavesPerBlock = 4;
+constexpr uint32_t kTestBlocksPerCU = 8;
+constexpr uint32_t kMinSegment = 64;  // one tile of one wavefront yields at most 64 records
+
 // length class: smallest c with 2^c >= len
 inline int length_class(uint32_t len) {
     int c = 0;
@@ -70,8 +75,7 @@ inline int length_class(uint32_t len) {
 // literal-major: lits[(t * S + k) * T + j] is literal k of clause j of the tile.
 struct BucketDesc {
     const uint32_t *lits;
-    const uint32_t *len;   // per slot; 0 = empty or removed
-    const uint32_t *ids;   // per slot
+    const uint2 *meta;     // per slot: (length, clause id); length 0 = empty or removed
     uint32_t stride_log2;  // S = 1 << stride_log2 literal rows per tile
     uint32_t tile_begin;   // global index of the bucket's first tile
 };
@@ -84,9 +88,9 @@ struct TestArgs {
     const uint64_t *active;   // [W]
     uint32_t W;
     uint32_t hot_rows;        // rows [0, hot_rows) are staged in LDS (0 = off)
-    gss_report *reports;
-    unsigned long long *counter;
-    unsigned long long cap;
+    gss_report *reports;      // n_waves segments of seg_cap records, one per wavefront
+    uint32_t *seg_counts;     // [n_waves]: records produced by each wavefront (beyond seg_cap: counted only)
+    uint32_t seg_cap;
     uint64_t *dense;          // GSS_TEST_DENSE: [n_ids][W]
 };
 
@@ -101,8 +105,7 @@ struct Bucket {
     uint64_t cap_slots = 0;  // allocated slots, a multiple of T
     uint64_t n_lits = 0;     // literals of the live clauses
     uint32_t *lits = nullptr;
-    uint32_t *len = nullptr;
-    uint32_t *ids = nullptr;
+    uint2 *meta = nullptr;        // per slot (length, id)
     std::vector<uint32_t> h_ids;  // mirror of ids (kDeadId = removed)
     std::vector<uint32_t> h_len;  // mirror of len
 };
@@ -130,15 +133,21 @@ struct Ctx {
     std::vector<uint64_t> id_loc;  // per id: bucket << 40 | slot, or kNoLoc
     uint64_t live = 0;
 
+    // reports: one segment of seg_cap records per wavefront of the test kernel
     gss_report *reports = nullptr;
-    uint64_t report_cap = 0;
-    unsigned long long *counter = nullptr;   // device
-    unsigned long long *h_counter = nullptr; // pinned host
+    uint32_t max_waves = 0;                  // wavefronts of the largest test launch
+    uint32_t seg_cap = 0;
+    uint32_t last_waves = 0;                 // wavefronts of the last launch
+    uint32_t *seg_counts = nullptr;          // [max_waves]
+    uint64_t *seg_offsets = nullptr;         // [max_waves + 1] exclusive prefix of the kept records
+    unsigned long long *d_summary = nullptr; // device {total, max, kept}
+    unsigned long long *h_summary = nullptr; // pinned host copy
     uint32_t *dsmall = nullptr;              // 256 B device scratch for flags
     uint32_t *hsmall = nullptr;              // 256 B pinned host
     void *d_desc = nullptr;                  // device copy of the test kernel's bucket descriptors
     void *hsmall_desc = nullptr;             // pinned host staging of the same
-    uint64_t n_reports = 0;
+    uint64_t n_reports = 0;  // records found by the last test
+    uint64_t n_kept = 0;     // records stored (fewer on overflow)
     bool tested = false;
     uint32_t last_flags = 0;
 

@@ -37,20 +37,16 @@ __global__ void k_append_lits(uint32_t *lits, uint32_t stride_log2, uint32_t T, 
     }
 }
 
-__global__ void k_append_meta(uint32_t *len, uint32_t *ids, uint64_t slot0, const uint64_t *coff,
-                              const uint32_t *new_ids, uint32_t n_clauses) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_clauses; i += gridDim.x * blockDim.x) {
-        len[slot0 + i] = (uint32_t)(coff[i + 1] - coff[i]);
-        ids[slot0 + i] = new_ids[i];
-    }
+__global__ void k_append_meta(uint2 *meta, uint64_t slot0, const uint64_t *coff, const uint32_t *new_ids,
+                              uint32_t n_clauses) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_clauses; i += gridDim.x * blockDim.x)
+        meta[slot0 + i] = make_uint2((uint32_t)(coff[i + 1] - coff[i]), new_ids[i]);
 }
 
-// Marks slots removed.
-__global__ void k_tombstone(uint32_t *len, uint32_t *ids, const uint64_t *slots, uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        len[slots[i]] = 0;
-        ids[slots[i]] = kDeadId;
-    }
+// Marks slots removed: length 0 (the test skips the slot without reading a literal).
+__global__ void k_tombstone(uint2 *meta, const uint64_t *slots, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        meta[slots[i]] = make_uint2(0u, kDeadId);
 }
 
 // Compaction: new slot s takes the clause of old slot old_slot[s]; thread per
@@ -66,12 +62,9 @@ __global__ void k_compact_lits(uint32_t *dst, const uint32_t *src, uint32_t stri
     }
 }
 
-__global__ void k_compact_meta(uint32_t *dlen, uint32_t *dids, const uint32_t *slen, const uint32_t *sids,
-                               const uint64_t *old_slot, uint64_t n_new) {
-    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < n_new; s += (uint64_t)gridDim.x * blockDim.x) {
-        dlen[s] = slen[old_slot[s]];
-        dids[s] = sids[old_slot[s]];
-    }
+__global__ void k_compact_meta(uint2 *dmeta, const uint2 *smeta, const uint64_t *old_slot, uint64_t n_new) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < n_new; s += (uint64_t)gridDim.x * blockDim.x)
+        dmeta[s] = smeta[old_slot[s]];
 }
 
 static unsigned grid_for(uint64_t n, unsigned block = 256) {
@@ -84,34 +77,34 @@ static unsigned grid_for(uint64_t n, unsigned block = 256) {
 // ---------------------------------------------------------------------------
 
 static uint64_t bucket_bytes(uint64_t cap_slots, uint32_t stride_log2) {
-    return cap_slots * ((4ull << stride_log2) + 8ull) + 3 * 256;
+    return cap_slots * ((4ull << stride_log2) + 8ull) + 2 * 256;
 }
 
 static uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 
-// Allocates the three arrays of a bucket with capacity cap (tail zeroed: len 0,
-// ids dead, codes 0) and copies the used prefix of the old arrays.
+// Fills a meta array with empty slots (length 0, dead id).
+static void fill_meta(Ctx &c, uint2 *meta, uint64_t n) {
+    launch_fill_u64(c, reinterpret_cast<uint64_t *>(meta), n, (uint64_t)kDeadId << 32);
+}
+
+// Allocates the arrays of a bucket with capacity cap (tail empty: length 0, codes
+// 0) and copies the used prefix of the old arrays.
 static void grow_bucket(Ctx &c, Bucket &b, uint64_t cap) {
     const uint64_t S = 1ull << b.stride_log2;
     uint32_t *lits = (uint32_t *)c.dalloc(cap * S * 4);
-    uint32_t *len = (uint32_t *)c.dalloc(cap * 4);
-    uint32_t *ids = (uint32_t *)c.dalloc(cap * 4);
+    uint2 *meta = (uint2 *)c.dalloc(cap * 8);
     launch_fill_u32(c, lits, cap * S, 0);
-    launch_fill_u32(c, len, cap, 0);
-    launch_fill_u32(c, ids, cap, kDeadId);
+    fill_meta(c, meta, cap);
     if (b.n_slots) {
         uint64_t used_tiles = (b.n_slots + c.T - 1) / c.T;
         GSS_HIP(hipMemcpyAsync(lits, b.lits, used_tiles * S * c.T * 4, hipMemcpyDeviceToDevice, c.stream));
-        GSS_HIP(hipMemcpyAsync(len, b.len, b.n_slots * 4, hipMemcpyDeviceToDevice, c.stream));
-        GSS_HIP(hipMemcpyAsync(ids, b.ids, b.n_slots * 4, hipMemcpyDeviceToDevice, c.stream));
+        GSS_HIP(hipMemcpyAsync(meta, b.meta, b.n_slots * 8, hipMemcpyDeviceToDevice, c.stream));
     }
     c.sync();
     c.dfree(b.lits);
-    c.dfree(b.len);
-    c.dfree(b.ids);
+    c.dfree(b.meta);
     b.lits = lits;
-    b.len = len;
-    b.ids = ids;
+    b.meta = meta;
     b.cap_slots = cap;
 }
 
@@ -126,33 +119,28 @@ static bool compact_bucket(Ctx &c, int bi) {
     const uint64_t n_new = old_slot.size();
     const uint64_t S = 1ull << b.stride_log2;
     const uint64_t cap = round_up(std::max<uint64_t>(n_new + n_new / 4, 256), c.T);
-    const uint64_t need = cap * S * 4 + 2 * cap * 4 + n_new * 8 + 4096;
+    const uint64_t need = cap * S * 4 + cap * 8 + n_new * 8 + 4096;
     if (c.cfg.hbm_budget_bytes && c.device_bytes + need > c.cfg.hbm_budget_bytes) return false;
 
     uint32_t *lits = (uint32_t *)c.dalloc(cap * S * 4);
-    uint32_t *len = (uint32_t *)c.dalloc(cap * 4);
-    uint32_t *ids = (uint32_t *)c.dalloc(cap * 4);
+    uint2 *meta = (uint2 *)c.dalloc(cap * 8);
     uint64_t *dmap = (uint64_t *)c.dalloc(std::max<uint64_t>(n_new, 1) * 8);
     launch_fill_u32(c, lits, cap * S, 0);
-    launch_fill_u32(c, len, cap, 0);
-    launch_fill_u32(c, ids, cap, kDeadId);
+    fill_meta(c, meta, cap);
     if (n_new) {
         GSS_HIP(hipMemcpyAsync(dmap, old_slot.data(), n_new * 8, hipMemcpyHostToDevice, c.stream));
         hipLaunchKernelGGL(k_compact_lits, dim3(grid_for(n_new * S)), dim3(256), 0, c.stream, lits, b.lits,
                            b.stride_log2, c.T, dmap, n_new);
         GSS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_compact_meta, dim3(grid_for(n_new)), dim3(256), 0, c.stream, len, ids, b.len, b.ids,
-                           dmap, n_new);
+        hipLaunchKernelGGL(k_compact_meta, dim3(grid_for(n_new)), dim3(256), 0, c.stream, meta, b.meta, dmap, n_new);
         GSS_HIP(hipGetLastError());
     }
     c.sync();
     c.dfree(dmap);
     c.dfree(b.lits);
-    c.dfree(b.len);
-    c.dfree(b.ids);
+    c.dfree(b.meta);
     b.lits = lits;
-    b.len = len;
-    b.ids = ids;
+    b.meta = meta;
     b.cap_slots = cap;
 
     std::vector<uint32_t> h_ids(n_new), h_len(n_new);
@@ -305,8 +293,7 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         hipLaunchKernelGGL(k_append_lits, dim3(grid_for(nl)), dim3(256), 0, c.stream, B.lits, B.stride_log2, c.T,
                            slot0, dcodes, dcoff, m, nl);
         GSS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_append_meta, dim3(grid_for(m)), dim3(256), 0, c.stream, B.len, B.ids, slot0, dcoff,
-                           dids, m);
+        hipLaunchKernelGGL(k_append_meta, dim3(grid_for(m)), dim3(256), 0, c.stream, B.meta, slot0, dcoff, dids, m);
         GSS_HIP(hipGetLastError());
         c.sync();  // the staging buffers are reused by the next chunk
         slot_cursor[b] += m;
@@ -354,7 +341,7 @@ extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint
         void *d = c.device_stage(bytes);
         std::memcpy(h, per[b].data(), bytes);
         GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
-        hipLaunchKernelGGL(k_tombstone, dim3(grid_for(per[b].size())), dim3(256), 0, c.stream, B.len, B.ids,
+        hipLaunchKernelGGL(k_tombstone, dim3(grid_for(per[b].size())), dim3(256), 0, c.stream, B.meta,
                            (const uint64_t *)d, (uint32_t)per[b].size());
         GSS_HIP(hipGetLastError());
         c.sync();

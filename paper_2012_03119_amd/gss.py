@@ -82,11 +82,13 @@ class gss_stats(ctypes.Structure):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Loads libgss.so and declares its signatures.  Raises if it is not built."""
+def load_library(path: Optional[str] = None):
+    """Loads libgss.so (or the build named by $GSS_LIBRARY) and declares its
+    signatures.  Raises if it is not built."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("GSS_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2012_03119_amd.build`")
     lib = ctypes.CDLL(path)

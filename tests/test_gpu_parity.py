@@ -283,25 +283,34 @@ def test_argument_errors_leave_state_unchanged():
 
 
 def test_report_overflow_and_regrow():
-    w = gen.tiny(7)
-    want = oracle.masks(w.lits, w.offsets, w.values)
+    # more tiles than wavefronts, each tile full of hits: segments of 64 records overflow
+    n_vars, max_slots = 64, 1024
+    rng = np.random.default_rng(17)
+    lengths = rng.integers(1, 3, 60_000)
+    lits, offsets = gen.random_clauses(rng, lengths, n_vars)
+    vals_n = np.where(rng.random((max_slots, n_vars)) < 0.9, -1, 0).astype(np.int8)
+    vals_n[:, ::2] *= -1
+    want = oracle.masks(lits, offsets, vals_n)
     n_want = int(np.count_nonzero(want))
-    with new_context(w.n_vars, 64, report_capacity=16) as ctx:
-        ctx.add_clauses(w.lits, w.offsets)
-        ctx.set_assignments(0, w.values)
+    with new_context(n_vars, max_slots, report_capacity=1) as ctx:
+        ctx.add_clauses(lits, offsets)
+        ctx.set_assignments(0, vals_n)
         with pytest.raises(gss.GssError) as e:
             ctx.test(gss.GSS_TEST_NO_REGROW)
         assert e.value.code == gss.GSS_ERR_REPORT_OVERFLOW
         assert ctx.stats()["last_reports"] == n_want     # exact count despite overflow
-        assert len(ctx.fetch_reports(10 ** 6)) == 16     # the records that fit
-        got = gpu_dense(ctx, w.n_clauses)                # grows and reruns
+        kept = ctx.fetch_reports(10 ** 8)
+        assert 0 < len(kept) < n_want
+        sub = reports_to_dense(kept, len(offsets) - 1, ctx.n_words)
+        assert np.array_equal(sub & want, sub)           # every kept record is right
+        got = gpu_dense(ctx, len(offsets) - 1)           # grows and reruns
         assert ctx.stats()["regrows"] >= 1
     _check(got, want)
 
 
 def test_hbm_budget():
     w = gen.tiny(8)
-    with new_context(w.n_vars, 64, hbm_budget_bytes=4 << 20) as ctx:
+    with new_context(w.n_vars, 64, hbm_budget_bytes=24 << 20) as ctx:
         with pytest.raises(gss.GssError) as e:
             big = gen.paper(1, n_clauses=200_000, n_vars=w.n_vars, n_slots=64)
             ctx.add_clauses(big.lits, big.offsets)
