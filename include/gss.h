@@ -191,6 +191,54 @@ gss_status gss_reset_stats(gss_ctx *ctx);
 /* hipStream_t the context issues work on (borrowed or owned). */
 gss_status gss_get_stream(const gss_ctx *ctx, void **stream);
 
+/* ---- Batched test: several independent stores in one persistent launch ----
+ *
+ * A batch groups n contexts (1..64) created on the same device with the same
+ * stream (pass one hipStream_t in every gss_config).  gss_batch_test tests every
+ * store against its own active slots in ONE persistent kernel launch; afterwards
+ * each context holds its records exactly as after its own gss_test (fetch them
+ * with gss_fetch_reports).  The contexts stay usable on their own; a batch only
+ * reads them and must be destroyed before them.  This has no counterpart in the
+ * paper, whose GPU serves one clause database; it serves several at once. */
+typedef struct gss_batch gss_batch;
+
+#define GSS_ORDER_STORE 0u         /* all tiles of store 0, then store 1, ... */
+#define GSS_ORDER_INTERLEAVE 1u    /* chunks of chunk_tiles tiles, stores in turn */
+#define GSS_ORDER_LONGEST_FIRST 2u /* length classes by decreasing stride across stores, stores in turn */
+
+/* The order in which the stores' tiles are dealt to the wavefronts, and the
+ * number of persistent workgroups per compute unit (0 = as many as fit).  Any
+ * schedule gives the same results; the autotuner picks the fastest. */
+typedef struct gss_schedule {
+    uint32_t order;
+    uint32_t chunk_tiles;   /* 0 = 64 */
+    uint32_t blocks_per_cu; /* 0..8 */
+    uint32_t reserved;
+} gss_schedule;
+
+/* Flag of gss_batch_test: capture the launch sequence (table uploads, kernels,
+ * the copy of the counts) in a hipGraph on first use and replay it while no store
+ * changed (clauses added or removed, report segments grown), and the schedule
+ * and flags are the same; otherwise capture again. */
+#define GSS_TEST_GRAPH 64u
+
+gss_status gss_batch_create(gss_ctx *const *ctxs, uint32_t n, gss_batch **out);
+void gss_batch_destroy(gss_batch *batch);
+const char *gss_batch_last_error(const gss_batch *batch);
+gss_status gss_batch_set_schedule(gss_batch *batch, const gss_schedule *schedule);
+
+/* Tests every store of the batch.  flags: GSS_TEST_TRIGGER, GSS_TEST_NO_EARLY_EXIT,
+ * GSS_TEST_NO_REGROW, GSS_TEST_GRAPH.  out_n_reports (n entries, may be NULL)
+ * receives each store's record count.  A store whose report segments overflow is
+ * grown and the whole batch repeated (unless GSS_TEST_NO_REGROW: then
+ * GSS_ERR_REPORT_OVERFLOW, with exact counts). */
+gss_status gss_batch_test(gss_batch *batch, uint32_t flags, uint64_t *out_n_reports);
+
+/* Duration of the last batched launch sequence in ms (HIP events around it),
+ * launches and graph captures so far, and the tiles of the last plan. */
+gss_status gss_batch_info(const gss_batch *batch, double *last_ms, uint64_t *launches, uint64_t *captures,
+                          uint64_t *tiles);
+
 #ifdef __cplusplus
 }
 #endif

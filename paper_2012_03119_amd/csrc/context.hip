@@ -48,16 +48,23 @@ __global__ void k_check_values(const int8_t *v, uint64_t n, unsigned int *bad) {
     if (found) atomicOr(bad, 1u);
 }
 
-void check_values_device(Ctx &c, const int8_t *values, uint64_t n) {
-    if (!n) return;
-    unsigned int *flag = c.hsmall;
-    unsigned int *dflag = c.dsmall;
-    launch_fill_u32(c, dflag, 1, 0);
-    hipLaunchKernelGGL(k_check_values, dim3(fill_grid(n)), dim3(256), 0, c.stream, values, n, dflag);
-    GSS_HIP(hipGetLastError());
-    GSS_HIP(hipMemcpyAsync(flag, dflag, sizeof(unsigned int), hipMemcpyDeviceToHost, c.stream));
+// Queues the check of n device-resident truth values; the verdict lands in
+// c.dsmall[0] (nonzero = some value outside {-1, 0, +1}).  Kernels that apply the
+// values read that word first and do nothing when it is set, so one
+// synchronisation (check_flag) gives validate-then-apply semantics.
+const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n) {
+    launch_fill_u32(c, c.dsmall, 1, 0);
+    if (n) {
+        hipLaunchKernelGGL(k_check_values, dim3(fill_grid(n)), dim3(256), 0, c.stream, values, n, c.dsmall);
+        GSS_HIP(hipGetLastError());
+    }
+    return c.dsmall;
+}
+
+void check_flag(Ctx &c) {
+    GSS_HIP(hipMemcpyAsync(c.hsmall, c.dsmall, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
     c.sync();
-    GSS_REQUIRE(*flag == 0, GSS_ERR_INVALID_ARG, "truth values must be -1, 0 or +1");
+    GSS_REQUIRE(c.hsmall[0] == 0, GSS_ERR_INVALID_ARG, "truth values must be -1, 0 or +1");
 }
 
 bool is_device_pointer(const void *p) {
@@ -103,7 +110,20 @@ void Ctx::dfree(void *p) {
         (void)hipFree(p);
 }
 
+static void stage_wait(Ctx &c) {
+    if (c.stage_pending) {
+        GSS_HIP(hipEventSynchronize(c.ev_stage));
+        c.stage_pending = false;
+    }
+}
+
+void Ctx::stage_release() {
+    GSS_HIP(hipEventRecord(ev_stage, stream));
+    stage_pending = true;
+}
+
 void *Ctx::device_stage(size_t bytes) {
+    stage_wait(*this);
     if (bytes > dstage_bytes) {
         // the old buffer may still be read by queued work
         sync();
@@ -118,6 +138,7 @@ void *Ctx::device_stage(size_t bytes) {
 }
 
 void *Ctx::host_stage(size_t bytes) {
+    stage_wait(*this);
     if (bytes > hstage_bytes) {
         sync();
         if (hstage) (void)hipHostFree(hstage);
@@ -165,6 +186,7 @@ static void destroy_ctx(Ctx *c) {
     if (c->hsmall) (void)hipHostFree(c->hsmall);
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
+    if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -201,11 +223,15 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
             c->own_stream = true;
         }
         c->W = cfg->max_slots / 64;
-        c->LPC = 1;
-        while (c->LPC < c->W) c->LPC <<= 1;
+        c->RW = 1;
+        while (c->RW < c->W) c->RW <<= 1;
+        c->LPC = c->RW <= 4 ? 1 : c->RW / 4;  // one lane per 32-byte sector of a row
         c->T = 64 / c->LPC;
+        // the test kernel addresses the plane table with 32-bit byte offsets
+        if (2ull * ((uint64_t)cfg->num_vars + 1) * c->RW * 8 >= (1ull << 32))
+            throw Error(GSS_ERR_INVALID_ARG, "num_vars x max_slots too large: the plane table must stay under 4 GiB");
         // LDS staging: rows of variables 0..hot_vars, at most 64 KiB per workgroup
-        uint64_t max_rows = 65536 / (8ull * c->W);
+        uint64_t max_rows = 65536 / (8ull * c->RW);
         uint64_t rows = cfg->hot_vars ? 2ull * ((uint64_t)cfg->hot_vars + 1) : 0;
         if (rows > max_rows) rows = max_rows & ~1ull;
         if (rows > 2ull * ((uint64_t)cfg->num_vars + 1)) rows = 2ull * ((uint64_t)cfg->num_vars + 1);
@@ -213,9 +239,9 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         for (int b = 0; b < kMaxBuckets; ++b) c->buckets[b].stride_log2 = (uint32_t)b;
 
         const uint64_t n_rows = 2ull * ((uint64_t)cfg->num_vars + 1);
-        c->planes = (uint64_t *)c->dalloc(n_rows * c->W * sizeof(uint64_t));
-        launch_fill_u64(*c, c->planes, n_rows * c->W, 0);
-        launch_fill_u64(*c, c->planes, c->W, ~0ull);  // row 0: always F
+        c->planes = (uint64_t *)c->dalloc(n_rows * c->RW * sizeof(uint64_t));
+        launch_fill_u64(*c, c->planes, n_rows * c->RW, 0);
+        launch_fill_u64(*c, c->planes, c->RW, ~0ull);  // row 0: always F
         c->active = (uint64_t *)c->dalloc(c->W * sizeof(uint64_t));
         launch_fill_u64(*c, c->active, c->W, 0);
         c->h_active.assign(c->W, 0);
@@ -230,11 +256,13 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         c->d_summary = (unsigned long long *)c->dalloc(4 * sizeof(unsigned long long));
         GSS_HIP(hipHostMalloc(&c->h_summary, 4 * sizeof(unsigned long long), hipHostMallocDefault));
         c->dsmall = (uint32_t *)c->dalloc(256);
+        launch_fill_u32(*c, c->dsmall, 64, 0);  // dsmall[1] stays zero: the verdict of host-checked inputs
         c->d_desc = c->dalloc(kMaxBuckets * sizeof(BucketDesc));
         GSS_HIP(hipHostMalloc(&c->hsmall_desc, kMaxBuckets * sizeof(BucketDesc), hipHostMallocDefault));
         GSS_HIP(hipHostMalloc(&c->hsmall, 256, hipHostMallocDefault));
         GSS_HIP(hipEventCreate(&c->ev_start));
         GSS_HIP(hipEventCreate(&c->ev_stop));
+        GSS_HIP(hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming));
         c->sync();
     } catch (const Error &e) {
         g_create_error = e.what();

@@ -49,7 +49,8 @@ __host__ __device__ inline uint32_t lit_code(int32_t lit) {
     return lit > 0 ? 2u * (uint32_t)lit : 2u * (uint32_t)(-lit) + 1u;
 }
 
-constexpr int kMaxBuckets = 17;              // length classes 1, 2, 4, ..., 65536
+constexpr int kMaxBuckets = 17;              // length classes 4, 8, ..., 65536 (classes 0-1 unused)
+constexpr int kMinClass = 2;                 // strides start at 4 codes: one 16-byte load
 constexpr uint32_t kMaxClauseLen = 65536;
 constexpr uint32_t kDeadId = 0xFFFFFFFFu;
 constexpr uint64_t kNoLoc = ~0ull;
@@ -57,11 +58,11 @@ constexpr uint64_t kNoLoc = ~0ull;
 // test kernel launch shape: persistent workgroups of 4 wavefronts, up to 8 per CU
 constexpr uint32_t kTestWavesPerBlock = 4;
 constexpr uint32_t kTestBlocksPerCU = 8;
-constexpr uint32_t kMinSegment = 64;  // one tile of one wavefront yields at most 64 records
+constexpr uint32_t kMinSegment = 16;   // smallest report segment per wavefront (grown on demand)
 
-// length class: smallest c with 2^c >= len
+// length class: smallest c >= kMinClass with 2^c >= len
 inline int length_class(uint32_t len) {
-    int c = 0;
+    int c = kMinClass;
     while ((1u << c) < len) ++c;
     return c;
 }
@@ -70,13 +71,16 @@ inline int length_class(uint32_t len) {
 // device-side descriptors
 // ---------------------------------------------------------------------------
 
-// One length class of the clause store as the test kernel sees it.  Tiles hold T
-// clauses (T = 64 / lanes-per-clause); tile t stores its literal codes
-// literal-major: lits[(t * S + k) * T + j] is literal k of clause j of the tile.
+// One length class of the clause store as the test kernel sees it.  Slot s holds
+// its clause's codes at lits[s * S + k] (k < S, sorted, padded with code 0), so a
+// lane reads four codes with one 16-byte load.  A tile is T consecutive slots
+// (T = 64 / lanes-per-clause): the clauses one wavefront tests together.
 struct BucketDesc {
     const uint32_t *lits;
     const uint2 *meta;     // per slot: (length, clause id); length 0 = empty or removed
-    uint32_t stride_log2;  // S = 1 << stride_log2 literal rows per tile
+    uint64_t lits_bytes;   // sizes of the two arrays (the kernel's buffer-load bounds)
+    uint64_t meta_bytes;
+    uint32_t stride_log2;  // S = 1 << stride_log2 codes per slot
     uint32_t tile_begin;   // global index of the bucket's first tile
 };
 
@@ -84,7 +88,7 @@ struct TestArgs {
     BucketDesc b[kMaxBuckets];
     uint32_t n_buckets;
     uint32_t n_tiles;
-    const uint64_t *planes;   // [2 * (num_vars + 1)][W]
+    const uint64_t *planes;   // [2 * (num_vars + 1)][RW], RW = lanes per clause >= W
     const uint64_t *active;   // [W]
     uint32_t W;
     uint32_t hot_rows;        // rows [0, hot_rows) are staged in LDS (0 = off)
@@ -116,8 +120,9 @@ struct Ctx {
     int n_cu = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    uint32_t W = 0;     // 64-slot words per plane row
-    uint32_t LPC = 0;   // lanes per clause in the test kernel (power of two >= W)
+    uint32_t W = 0;     // 64-slot words in use per plane row
+    uint32_t RW = 0;    // stored words per plane row (power of two >= W; words >= W stay zero)
+    uint32_t LPC = 0;   // lanes per clause in the test kernel (RW / words per lane)
     uint32_t T = 0;     // clauses per tile = 64 / LPC
     uint32_t hot_rows = 0;
 
@@ -132,6 +137,7 @@ struct Ctx {
     Bucket buckets[kMaxBuckets];
     std::vector<uint64_t> id_loc;  // per id: bucket << 40 | slot, or kNoLoc
     uint64_t live = 0;
+    uint64_t version = 0;  // bumped whenever store arrays or report segments move (batch graphs check it)
 
     // reports: one segment of seg_cap records per wavefront of the test kernel
     gss_report *reports = nullptr;
@@ -161,14 +167,20 @@ struct Ctx {
     size_t hstage_bytes = 0;
 
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    hipEvent_t ev_stage = nullptr;  // recorded after the last queued use of the staging buffers
+    bool stage_pending = false;
     gss_stats stats{};
     std::string last_error;
 
     // device memory within the budget
     void *dalloc(size_t bytes);
     void dfree(void *p);
+    // Staging buffers: the returned memory is free to write (queued work that read
+    // it has finished).  A call that leaves work reading staging memory queued
+    // calls stage_release() instead of synchronising.
     void *device_stage(size_t bytes);
     void *host_stage(size_t bytes);
+    void stage_release();
     void sync();
 };
 
@@ -176,7 +188,8 @@ struct Ctx {
 void launch_fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t value);
 void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value);
 bool is_device_pointer(const void *p);
-void check_values_device(Ctx &c, const int8_t *values, uint64_t n);
+const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n);
+void check_flag(Ctx &c);
 
 // Wrapper of every ABI entry point taking a context: converts exceptions into
 // status codes and records the message for gss_last_error.

@@ -19,8 +19,10 @@ namespace gss {
 // Packs the slots of word w from a slot-major staging block.  One wavefront per
 // 64 variables; lane b reads slot 64*w + b.  Staging row r holds slot s_lo + r,
 // `pitch` bytes per row (a multiple of 64), byte v-1 = value of variable v.
-__global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t W, uint32_t w, uint32_t num_vars,
-                                                  const int8_t *stage, uint64_t pitch, uint32_t s_lo, uint32_t s_hi) {
+__global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RW, uint32_t w, uint32_t num_vars,
+                                                  const int8_t *stage, uint64_t pitch, uint32_t s_lo, uint32_t s_hi,
+                                                  const uint32_t *bad) {
+    if (*bad) return;  // the inputs failed validation: apply nothing
     const uint32_t lane = threadIdx.x;
     const uint32_t v0 = 1 + 64 * blockIdx.x;
     const uint32_t slot = 64 * w + lane;
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t W, 
     }
     const uint32_t v = v0 + lane;
     if (v <= num_vars) {
-        const uint64_t r0 = (uint64_t)(2 * v) * W + w, r1 = r0 + W;
+        const uint64_t r0 = (uint64_t)(2 * v) * RW + w, r1 = r0 + RW;
         if (sm != ~0ull) {
             f = (planes[r0] & ~sm) | (f & sm);
             t = (planes[r1] & ~sm) | (t & sm);
@@ -61,8 +63,10 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t W, 
 // per variable; lane b covers slot 64*w + b of each word w in the range, and the
 // finished words are written by lanes 0..(words-1).  vals is var-major
 // [n_vars][n_slots].
-__global__ __launch_bounds__(64) void k_set_vars(uint64_t *planes, uint32_t W, const uint32_t *vars, uint32_t n_vars,
-                                                 const int8_t *vals, uint32_t first, uint32_t n_slots) {
+__global__ __launch_bounds__(64) void k_set_vars(uint64_t *planes, uint32_t RW, const uint32_t *vars, uint32_t n_vars,
+                                                 const int8_t *vals, uint32_t first, uint32_t n_slots,
+                                                 const uint32_t *bad) {
+    if (*bad) return;  // the inputs failed validation: apply nothing
     const uint32_t lane = threadIdx.x;
     const uint32_t w_lo = first / 64, w_hi = (first + n_slots - 1) / 64;
     for (uint32_t i = blockIdx.x; i < n_vars; i += gridDim.x) {
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(64) void k_set_vars(uint64_t *planes, uint32_t W, c
         }
         if (lane <= w_hi - w_lo) {
             const uint32_t w = w_lo + lane;
-            const uint64_t r0 = (uint64_t)(2 * v) * W + w, r1 = r0 + W;
+            const uint64_t r0 = (uint64_t)(2 * v) * RW + w, r1 = r0 + RW;
             uint64_t f = my_f, t = my_t;
             if (my_sm != ~0ull) {
                 f = (planes[r0] & ~my_sm) | (f & my_sm);
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(64) void k_set_vars(uint64_t *planes, uint32_t W, c
 }
 
 // Clears slots [first, first+n) in every row of real variables (rows >= 2).
-__global__ void k_clear_slots(uint64_t *planes, uint32_t W, uint64_t n_rows, uint32_t first, uint32_t n_slots) {
+__global__ void k_clear_slots(uint64_t *planes, uint32_t RW, uint64_t n_rows, uint32_t first, uint32_t n_slots) {
     const uint32_t w_lo = first / 64, w_hi = (first + n_slots - 1) / 64, nw = w_hi - w_lo + 1;
     const uint64_t total = (n_rows - 2) * nw;
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
@@ -104,7 +108,7 @@ __global__ void k_clear_slots(uint64_t *planes, uint32_t W, uint64_t n_rows, uin
         const uint32_t w = w_lo + (uint32_t)(x % nw);
         const uint32_t a = std::max(first, 64 * w), b = std::min(first + n_slots, 64 * w + 64);
         const uint64_t sm = (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1) << (a - 64 * w));
-        planes[row * W + w] &= ~sm;
+        planes[row * RW + w] &= ~sm;
     }
 }
 
@@ -118,7 +122,7 @@ static void upload_active(Ctx &c) {
     uint64_t *h = (uint64_t *)c.host_stage(c.W * 8);
     std::memcpy(h, c.h_active.data(), c.W * 8);
     GSS_HIP(hipMemcpyAsync(c.active, h, c.W * 8, hipMemcpyHostToDevice, c.stream));
-    c.sync();
+    c.stage_release();
 }
 
 static void check_values_host(const int8_t *v, uint64_t n) {
@@ -139,8 +143,9 @@ extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uin
     GSS_REQUIRE((uint64_t)first_slot + n_slots <= c.cfg.max_slots, GSS_ERR_CAPACITY, "slot range beyond max_slots");
     const uint64_t V = c.cfg.num_vars;
     const bool dev = is_device_pointer(values);
+    const uint32_t *bad = c.dsmall + 1;  // always zero
     if (dev)
-        check_values_device(c, values, (uint64_t)n_slots * V);
+        bad = queue_value_check(c, values, (uint64_t)n_slots * V);
     else
         check_values_host(values, (uint64_t)n_slots * V);
 
@@ -152,12 +157,14 @@ extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uin
         const int8_t *src = values + (uint64_t)(s_lo - first_slot) * V;
         GSS_HIP(hipMemcpy2DAsync(stage, pitch, src, V, V, s_hi - s_lo,
                                  dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.stream));
-        hipLaunchKernelGGL(k_pack_word, dim3((unsigned)((V + 63) / 64)), dim3(64), 0, c.stream, c.planes, c.W, w,
-                           (uint32_t)V, stage, pitch, s_lo, s_hi);
+        hipLaunchKernelGGL(k_pack_word, dim3((unsigned)((V + 63) / 64)), dim3(64), 0, c.stream, c.planes, c.RW, w,
+                           (uint32_t)V, stage, pitch, s_lo, s_hi, bad);
         GSS_HIP(hipGetLastError());
-        c.h_active[w] |= slot_mask(first_slot, n_slots, w);
     }
-    upload_active(c);  // synchronises: the staging block is free again
+    if (dev) check_flag(c);  // throws, having applied nothing, if a value was invalid
+    for (uint32_t w = first_slot / 64; w <= (last - 1) / 64; ++w) c.h_active[w] |= slot_mask(first_slot, n_slots, w);
+    upload_active(c);
+    c.sync();  // host inputs are read by the copies above: done before returning
     GSS_API_END
 }
 
@@ -192,24 +199,26 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
     }
     const uint64_t nv = (uint64_t)n_vars * n_slots;
     const bool dev = is_device_pointer(values);
+    const uint32_t *bad = c.dsmall + 1;  // always zero
     if (dev)
-        check_values_device(c, values, nv);
+        bad = queue_value_check(c, values, nv);
     else
         check_values_host(values, nv);
 
     const size_t vars_bytes = ((size_t)n_vars * 4 + 255) / 256 * 256;
-    char *d = (char *)c.device_stage(vars_bytes + (dev ? 0 : nv));
-    GSS_HIP(hipMemcpyAsync(d, vars, (size_t)n_vars * 4, hipMemcpyHostToDevice, c.stream));
-    const int8_t *dvals = values;
-    if (!dev) {
-        GSS_HIP(hipMemcpyAsync(d + vars_bytes, values, nv, hipMemcpyHostToDevice, c.stream));
-        dvals = (const int8_t *)(d + vars_bytes);
-    }
+    const size_t bytes = vars_bytes + (dev ? 0 : nv);
+    char *h = (char *)c.host_stage(bytes);
+    char *d = (char *)c.device_stage(bytes);
+    std::memcpy(h, vars, (size_t)n_vars * 4);
+    if (!dev) std::memcpy(h + vars_bytes, values, nv);
+    GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
+    const int8_t *dvals = dev ? values : (const int8_t *)(d + vars_bytes);
     const unsigned grid = std::min<uint32_t>(n_vars, 65536);
-    hipLaunchKernelGGL(k_set_vars, dim3(grid), dim3(64), 0, c.stream, c.planes, c.W, (const uint32_t *)d, n_vars,
-                       dvals, first_slot, n_slots);
+    hipLaunchKernelGGL(k_set_vars, dim3(grid), dim3(64), 0, c.stream, c.planes, c.RW, (const uint32_t *)d, n_vars,
+                       dvals, first_slot, n_slots, bad);
     GSS_HIP(hipGetLastError());
-    c.sync();
+    c.stage_release();
+    if (dev) check_flag(c);  // one synchronisation: device inputs are fully read when the call returns
     GSS_API_END
 }
 
@@ -222,7 +231,7 @@ extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_
     const uint64_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
     const uint64_t total = (n_rows - 2) * nw;
     const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
-    hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(256), 0, c.stream, c.planes, c.W, n_rows, first_slot, n_slots);
+    hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, n_rows, first_slot, n_slots);
     GSS_HIP(hipGetLastError());
     for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w)
         c.h_active[w] &= ~slot_mask(first_slot, n_slots, w);

@@ -1,11 +1,11 @@
 // The clause store: length-bucketed SoA tiles of literal codes, with insertion,
 // deletion and compaction.
 //
-// Layout (per length class b, stride S = 2^b literal rows): slots are grouped in
-// tiles of T clauses (T = 64 / lanes-per-clause of the test kernel) and a tile
-// stores its codes literal-major, lits[(tile * S + k) * T + j] = literal k of
-// clause j, so the T clauses of one wavefront read their k-th literals from one
-// contiguous run.  Literals of a clause are kept sorted by code (variable order):
+// Layout (per length class b, stride S = 2^b codes, S >= 4): slot s holds its
+// clause at lits[s * S .. s * S + S), codes sorted and padded with code 0, so the
+// test kernel reads four codes per 16-byte load; a tile is T consecutive slots (T
+// = 64 / lanes-per-clause), one wavefront's share.  Literals of a clause are kept
+// sorted by code (variable order):
 // the order does not change the result, and it concentrates the first literals of
 // long clauses -- the ones the early exit actually reads -- on low variable rows.
 #include "gss_internal.h"
@@ -21,7 +21,7 @@ namespace gss {
 
 // Appends one segment of new clauses to a bucket: thread per literal.  Clause i
 // of the segment goes to slot slot0 + i; its codes are codes[coff[i] .. coff[i+1]).
-__global__ void k_append_lits(uint32_t *lits, uint32_t stride_log2, uint32_t T, uint64_t slot0,
+__global__ void k_append_lits(uint32_t *lits, uint32_t stride_log2, uint64_t slot0,
                               const uint32_t *codes, const uint64_t *coff, uint32_t n_clauses, uint64_t n_lits) {
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n_lits; x += (uint64_t)gridDim.x * blockDim.x) {
         // clause owning literal x: last i with coff[i] <= x
@@ -30,10 +30,8 @@ __global__ void k_append_lits(uint32_t *lits, uint32_t stride_log2, uint32_t T, 
             uint32_t mid = (lo + hi) >> 1;
             if (coff[mid] <= x) lo = mid; else hi = mid;
         }
-        uint64_t k = x - coff[lo];
-        uint64_t slot = slot0 + lo;
-        uint64_t tile = slot / T, j = slot % T;
-        lits[((tile << stride_log2) + k) * T + j] = codes[x];
+        const uint64_t k = x - coff[lo];
+        lits[((slot0 + lo) << stride_log2) + k] = codes[x];
     }
 }
 
@@ -51,14 +49,14 @@ __global__ void k_tombstone(uint2 *meta, const uint64_t *slots, uint32_t n) {
 
 // Compaction: new slot s takes the clause of old slot old_slot[s]; thread per
 // (new slot, literal row).
-__global__ void k_compact_lits(uint32_t *dst, const uint32_t *src, uint32_t stride_log2, uint32_t T,
-                               const uint64_t *old_slot, uint64_t n_new) {
+__global__ void k_compact_lits(uint32_t *dst, const uint32_t *src, uint32_t stride_log2, const uint64_t *old_slot,
+                               uint64_t n_new) {
     const uint64_t S = 1ull << stride_log2;
     const uint64_t total = n_new * S;
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t s = x >> stride_log2, k = x & (S - 1);
-        uint64_t o = old_slot[s];
-        dst[(((s / T) << stride_log2) + k) * T + s % T] = src[(((o / T) << stride_log2) + k) * T + o % T];
+        const uint64_t s = x >> stride_log2, k = x & (S - 1);
+        dst[x] = src[(old_slot[s] << stride_log2) + k];
+        (void)s;
     }
 }
 
@@ -96,8 +94,7 @@ static void grow_bucket(Ctx &c, Bucket &b, uint64_t cap) {
     launch_fill_u32(c, lits, cap * S, 0);
     fill_meta(c, meta, cap);
     if (b.n_slots) {
-        uint64_t used_tiles = (b.n_slots + c.T - 1) / c.T;
-        GSS_HIP(hipMemcpyAsync(lits, b.lits, used_tiles * S * c.T * 4, hipMemcpyDeviceToDevice, c.stream));
+        GSS_HIP(hipMemcpyAsync(lits, b.lits, b.n_slots * S * 4, hipMemcpyDeviceToDevice, c.stream));
         GSS_HIP(hipMemcpyAsync(meta, b.meta, b.n_slots * 8, hipMemcpyDeviceToDevice, c.stream));
     }
     c.sync();
@@ -130,7 +127,7 @@ static bool compact_bucket(Ctx &c, int bi) {
     if (n_new) {
         GSS_HIP(hipMemcpyAsync(dmap, old_slot.data(), n_new * 8, hipMemcpyHostToDevice, c.stream));
         hipLaunchKernelGGL(k_compact_lits, dim3(grid_for(n_new * S)), dim3(256), 0, c.stream, lits, b.lits,
-                           b.stride_log2, c.T, dmap, n_new);
+                           b.stride_log2, dmap, n_new);
         GSS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_compact_meta, dim3(grid_for(n_new)), dim3(256), 0, c.stream, meta, b.meta, dmap, n_new);
         GSS_HIP(hipGetLastError());
@@ -172,6 +169,7 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
 
     // ---- validate everything first
     std::vector<uint8_t> cls(n);
+    std::vector<uint32_t> lead(n);  // smallest literal code of each clause
     uint64_t add[kMaxBuckets] = {0};
     const int64_t V = c.cfg.num_vars;
     for (uint32_t i = 0; i < n; ++i) {
@@ -179,23 +177,34 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         const uint64_t L = offsets[i + 1] - offsets[i];
         GSS_REQUIRE(L >= 1, GSS_ERR_INVALID_ARG, "empty clause at index " + std::to_string(i));
         GSS_REQUIRE(L <= kMaxClauseLen, GSS_ERR_INVALID_ARG, "clause longer than 65536 literals at index " + std::to_string(i));
+        uint32_t lo = ~0u;
         for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
             int64_t l = lits[k];
             int64_t v = l < 0 ? -l : l;
             GSS_REQUIRE(v >= 1 && v <= V, GSS_ERR_BAD_LITERAL,
                         "literal " + std::to_string(l) + " of clause " + std::to_string(i) + " is 0 or beyond num_vars");
+            lo = std::min(lo, lit_code((int32_t)l));
         }
+        lead[i] = lo;
         cls[i] = (uint8_t)length_class((uint32_t)L);
         add[cls[i]]++;
     }
 
-    // ---- order the batch by bucket (stable) and cut it into upload chunks, each a
-    //      run of clauses of one bucket; stage buffers sized for the largest chunk
+    // ---- order the batch by bucket, and inside a bucket by lead code: clauses a
+    //      wavefront (and an XCD) tests at the same time then share the plane row
+    //      of their first literal, the one every clause reads in full.  Then cut
+    //      the batch into upload chunks, each a run of clauses of one bucket; stage
+    //      buffers are sized for the largest chunk.
     std::vector<uint32_t> order(n);
     {
         uint64_t pos[kMaxBuckets + 1] = {0};
         for (int b = 0; b < kMaxBuckets; ++b) pos[b + 1] = pos[b] + add[b];
+        uint64_t start[kMaxBuckets + 1];
+        std::copy(pos, pos + kMaxBuckets + 1, start);
         for (uint32_t i = 0; i < n; ++i) order[pos[cls[i]]++] = i;
+        for (int b = 0; b < kMaxBuckets; ++b)
+            std::stable_sort(order.begin() + start[b], order.begin() + start[b + 1],
+                             [&](uint32_t x, uint32_t y) { return lead[x] < lead[y]; });
     }
     const uint64_t kChunkLits = 1ull << 24, kChunkClauses = 1ull << 21;
     std::vector<uint32_t> cuts{0};
@@ -234,6 +243,11 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         const uint64_t min_slots = std::max<uint64_t>(c.T, std::min<uint64_t>(256, (1ull << 20) / S));
         uint64_t want = std::max<uint64_t>({B.n_slots + add[b], B.cap_slots + B.cap_slots / 2, min_slots});
         new_cap[b] = round_up(want, c.T);
+        // the test kernel addresses a class's codes with 32-bit byte offsets
+        if ((new_cap[b] << B.stride_log2 << 2) >= (1ull << 32))
+            new_cap[b] = std::max<uint64_t>(B.n_slots + add[b], ((1ull << 30) >> B.stride_log2) / c.T * c.T - c.T);
+        GSS_REQUIRE((new_cap[b] << B.stride_log2 << 2) < (1ull << 32) && new_cap[b] >= B.n_slots + add[b],
+                    GSS_ERR_CAPACITY, "length class " + std::to_string(1u << B.stride_log2) + " would exceed 4 GiB of codes");
         grow_bytes += bucket_bytes(new_cap[b], B.stride_log2);
     }
     GSS_REQUIRE(c.cfg.hbm_budget_bytes == 0 || c.device_bytes + grow_bytes <= c.cfg.hbm_budget_bytes, GSS_ERR_CAPACITY,
@@ -290,8 +304,8 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         const uint32_t *dcodes = (const uint32_t *)d;
         const uint64_t *dcoff = (const uint64_t *)(d + codes_bytes);
         const uint32_t *dids = (const uint32_t *)(d + codes_bytes + coff_bytes);
-        hipLaunchKernelGGL(k_append_lits, dim3(grid_for(nl)), dim3(256), 0, c.stream, B.lits, B.stride_log2, c.T,
-                           slot0, dcodes, dcoff, m, nl);
+        hipLaunchKernelGGL(k_append_lits, dim3(grid_for(nl)), dim3(256), 0, c.stream, B.lits, B.stride_log2, slot0,
+                           dcodes, dcoff, m, nl);
         GSS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_append_meta, dim3(grid_for(m)), dim3(256), 0, c.stream, B.meta, slot0, dcoff, dids, m);
         GSS_HIP(hipGetLastError());
@@ -301,6 +315,7 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         B.n_lits += nl;
     }
     c.live += n;
+    c.version++;
     GSS_API_END
 }
 
@@ -346,6 +361,7 @@ extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint
         GSS_HIP(hipGetLastError());
         c.sync();
     }
+    c.version++;
     // ---- reclaim: compact a class once more than a quarter of its slots are dead
     for (int b = 0; b < kMaxBuckets; ++b) {
         Bucket &B = c.buckets[b];

@@ -1,237 +1,59 @@
-// The clause test (Sections 3.4-3.5) and its report compaction.
-//
-// Two forms of parallelism, as in Section 3.5: wavefront lanes work on different
-// clauses, and each lane tests 64 assignment slots at once with 64-bit bitwise
-// operations.  A clause is spread over LPC lanes, one 64-slot word per lane, so a
-// wavefront covers T = 64 / LPC clauses and the W words of one plane row are read
-// by adjacent lanes as one contiguous access.
-//
-// Falsified mode: the clause mask is the AND over its literals of the gathered
-// plane words (the allFalse half of the bitwise trigger test of Section 3.4).
-// Trigger mode (Definition 1): the same loop also carries the oneUndef word, which
-// needs the row of the opposite literal as well (isSet = F-row | T-row).
-//
-// Early exit: after every group of gathers the wavefront votes; once no lane of
-// any of its clauses has a live bit left, it stops reading literals.  Hot rows
-// (the first `hot_rows` plane rows; variables are kept in code order inside a
-// clause, so the first literals land there most often) can be staged in LDS.
-//
-// The kernel is persistent: each wavefront walks the tiles t = wave, wave + N, ...
-// (N wavefronts in the grid) and prefetches the next tile's metadata and first
-// literal block while it tests the current one.  Reports need no atomics: every
-// wavefront owns one segment of the report buffer and appends its records there,
-// at its running count + (records of lower lanes, from mbcnt).  A one-block
-// finalize kernel turns the per-wavefront counts into totals and segment offsets;
-// fetching stitches the segments into one list.  Counts beyond a segment's
-// capacity are still counted, so the exact size needed is always known.
-#include "gss_internal.h"
+// The single-store clause test: a persistent kernel over one store's tiles, the
+// finalize kernel that turns per-wavefront record counts into totals and segment
+// offsets, the stitch that joins the segments on fetch, and the host entry points
+// gss_test, gss_fetch_reports and gss_fetch_masks.  The per-tile work is the
+// Tester of tester.h (Sections 3.4-3.5).
+#include "tester.h"
 
 #include <algorithm>
 #include <cstring>
 
 namespace gss {
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that a
-// contiguous range of logical workgroups (neighbouring tiles, sharing cache lines
-// of the literal and metadata streams) runs on one XCD and its L2.
-__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
-    constexpr uint32_t X = 8;
-    const uint32_t x = b % X, i = b / X, q = nb / X, r = nb % X;
-    return x * q + (x < r ? x : r) + i;
-}
-
-__device__ inline uint32_t lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-template <int LPC, int MODE, bool HOT>
+// Each wavefront walks the tiles t = wave, wave + N, ... (N wavefronts in the
+// grid) and prefetches the next tile's metadata and first codes while it tests
+// the current one.
+template <int LPC, int WPL, int MODE, bool HOT>
 __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDesc *__restrict__ descs,
                                                                    const TestArgs a, uint32_t early_exit,
                                                                    uint32_t dense) {
-    constexpr uint32_t T = 64 / LPC;             // clauses per wavefront (and per tile)
-    constexpr uint32_t R = (T == 64) ? 4 : LPC;  // literal rows per block load
-    constexpr uint32_t BL = (T == 64) ? R : 1;   // codes per lane per block load
-    constexpr uint32_t U = R < 4 ? R : 4;        // gathers in flight per lane between votes
+    using Ts = Tester<LPC, WPL, MODE, HOT>;
     extern __shared__ uint64_t lds_rows[];
-
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t W = a.W;
     if constexpr (HOT) {
-        const uint32_t n = a.hot_rows * W;
+        const uint32_t n = a.hot_rows * Ts::RW;
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lds_rows[i] = a.planes[i];
         __syncthreads();
     }
-    const uint32_t j = lane / LPC;  // clause of this lane within the tile
-    const uint32_t w = lane % LPC;  // word of this lane
-    const bool word_ok = w < W;
-    const uint64_t act = word_ok ? a.active[w] : 0;
+    const uint32_t lane = threadIdx.x & 63;
+    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows);
     const uint32_t waves_per_block = blockDim.x / 64;
     const uint32_t n_waves = gridDim.x * waves_per_block;
-    const uint32_t wave = xcd_remap(blockIdx.x, gridDim.x) * waves_per_block + threadIdx.x / 64;
+    // wave-uniform by construction; readfirstlane lets the compiler keep it in SGPRs
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * waves_per_block +
+                                                         threadIdx.x / 64);
     gss_report *const seg = a.reports + (uint64_t)wave * a.seg_cap;
+    uint64_t *const dense_out = dense ? a.dense : nullptr;
     uint32_t produced = 0;  // records of this wavefront (uniform)
-    uint32_t bi = 0;        // bucket of the current tile; tiles are visited in increasing order
+    uint32_t bi = 0;
 
-    auto fetch = [&](uint32_t code) -> uint64_t {
-        if constexpr (HOT) {
-            if (code < a.hot_rows) return lds_rows[code * W + w];
-        }
-        return a.planes[(uint64_t)code * W + w];
-    };
-
-    // wave-uniform description of a tile, plus this lane's metadata and first block
-    struct Tile {
-        const uint32_t *lits;
-        uint32_t s_log2;
-        uint2 meta;
-        uint32_t blk[BL];
-    };
-    auto load_block = [&](const Tile &tl, uint32_t k, uint32_t *blk) {
-        const uint32_t S = 1u << tl.s_log2;
-        if constexpr (T == 64) {
-#pragma unroll
-            for (uint32_t u = 0; u < R; ++u) blk[u] = (k + u < S) ? tl.lits[(uint64_t)(k + u) * 64 + lane] : 0u;
-        } else {
-            const uint32_t row = k + lane / T;
-            blk[0] = row < S ? tl.lits[(uint64_t)row * T + lane % T] : 0u;
-        }
-    };
-    auto open_tile = [&](uint32_t t, Tile &tl) {
-        while (bi + 1 < a.n_buckets && t >= descs[bi + 1].tile_begin) ++bi;
-        const BucketDesc &d = descs[bi];
-        const uint32_t tile = t - d.tile_begin;
-        tl.s_log2 = d.stride_log2;
-        tl.lits = d.lits + ((uint64_t)tile << d.stride_log2) * T;
-        tl.meta = d.meta[(uint64_t)tile * T + j];
-        load_block(tl, 0, tl.blk);
-    };
-
+    const uint32_t last = a.n_tiles - 1;
     uint32_t t = wave;
-    Tile cur;
-    if (t < a.n_tiles) open_tile(t, cur);
+    typename Ts::Tile cur;
+    ts.open(descs, a.n_buckets, bi, t < a.n_tiles ? t : last, cur);
     while (t < a.n_tiles) {
         const uint32_t tn = t + n_waves;
-        Tile nxt{};
-        if (tn < a.n_tiles) open_tile(tn, nxt);  // prefetch: loads in flight while this tile runs
-
-        const uint32_t len = cur.meta.x;
-        uint64_t af = (len && word_ok) ? act : 0;  // allFalse
-        uint64_t ou = 0;                           // oneUndef (trigger mode)
-        uint32_t blk[BL];
-#pragma unroll
-        for (uint32_t u = 0; u < BL; ++u) blk[u] = cur.blk[u];
-        for (uint32_t k = 0;; k += R) {
-            {
-                const bool go = k < len && word_ok && (!early_exit || (af | ou) != 0);
-                if (!__ballot(go)) break;
-            }
-            if (k) load_block(cur, k, blk);
-            bool stop = false;
-#pragma unroll
-            for (uint32_t r = 0; r < R; r += U) {
-                if (stop) continue;  // wave-uniform; keeps the loop unrollable
-                uint64_t gf[U], gt[U];
-#pragma unroll
-                for (uint32_t u = 0; u < U; ++u) {
-                    const uint32_t kk = k + r + u;
-                    uint32_t code;
-                    if constexpr (T == 64)
-                        code = blk[r + u];
-                    else
-                        code = (uint32_t)__shfl((int)blk[0], (int)((r + u) * T + j), 64);
-                    const bool live = kk < len && word_ok && (!early_exit || (af | ou) != 0);
-                    gf[u] = ~0ull;
-                    gt[u] = 0;
-                    if (live) {
-                        gf[u] = fetch(code);
-                        if constexpr (MODE == 1) gt[u] = fetch(code ^ 1u);
-                    }
-                }
-#pragma unroll
-                for (uint32_t u = 0; u < U; ++u) {
-                    if constexpr (MODE == 1) {
-                        const uint64_t is_set = gf[u] | gt[u];
-                        ou = (af & ~is_set) | (ou & gf[u]);
-                    }
-                    af &= gf[u];
-                }
-                if (early_exit) {
-                    const bool more = (k + r + U) < len && (af | ou) != 0;
-                    stop = !__ballot(more);
-                }
-            }
-            if (stop) break;
-        }
-
-        const uint64_t res = af | ou;
-        if (dense) {
-            if (len && word_ok) a.dense[(uint64_t)cur.meta.y * W + w] = res;
-        } else {
-            const bool has = res != 0;
-            const uint64_t bal = __ballot(has);
-            if (has) {
-                const uint32_t pos = produced + lanes_below(bal);
-                if (pos < a.seg_cap) {
-                    const u32x4 rec = {cur.meta.y, w, (uint32_t)res, (uint32_t)(res >> 32)};
-                    __builtin_nontemporal_store(rec, reinterpret_cast<u32x4 *>(seg) + pos);
-                }
-            }
-            produced += (uint32_t)__builtin_popcountll(bal);
-        }
+        typename Ts::Tile nxt;
+        ts.open(descs, a.n_buckets, bi, tn < a.n_tiles ? tn : last, nxt);  // prefetch, unconditionally
+        produced = ts.run(cur, seg, a.seg_cap, produced, early_exit, dense_out);
         t = tn;
         cur = nxt;
     }
     if (lane == 0) a.seg_counts[wave] = produced;
 }
 
-// One workgroup of 1024 threads: exclusive prefix of the records each segment
-// kept (min(count, cap)) into offsets[0..n], and summary = {total count, largest
-// count, records kept}.
 __global__ __launch_bounds__(1024) void k_finalize(const uint32_t *counts, uint32_t n, uint32_t cap,
                                                     uint64_t *offsets, unsigned long long *summary) {
-    __shared__ unsigned long long part[1024];
-    __shared__ unsigned long long tot[1024];
-    __shared__ unsigned int mx[1024];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (n + 1023) / 1024;
-    const uint32_t lo = tid * per, hi = min(n, lo + per);
-    unsigned long long kept = 0, all = 0;
-    unsigned int m = 0;
-    for (uint32_t i = lo; i < hi; ++i) {
-        kept += min(counts[i], cap);
-        all += counts[i];
-        m = max(m, counts[i]);
-    }
-    part[tid] = kept;
-    tot[tid] = all;
-    mx[tid] = m;
-    __syncthreads();
-    // inclusive Hillis-Steele scan of part[], reductions of tot[] and mx[]
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        unsigned long long p = tid >= off ? part[tid - off] : 0ull;
-        unsigned long long q = (tid + off < 1024) ? tot[tid + off] : 0ull;
-        unsigned int r = (tid + off < 1024) ? mx[tid + off] : 0u;
-        __syncthreads();
-        part[tid] += p;
-        if ((tid & (2 * off - 1)) == 0) {
-            tot[tid] += q;
-            mx[tid] = max(mx[tid], r);
-        }
-        __syncthreads();
-    }
-    unsigned long long base = tid ? part[tid - 1] : 0ull;
-    for (uint32_t i = lo; i < hi; ++i) {
-        offsets[i] = base;
-        base += min(counts[i], cap);
-    }
-    if (tid == 1023) offsets[n] = part[1023];
-    if (tid == 0) {
-        summary[0] = tot[0];
-        summary[1] = mx[0];
-        summary[2] = part[1023];
-    }
+    finalize_segments(counts, n, cap, offsets, summary);
 }
 
 // Copies the kept records of every segment into one list (segment order), the
@@ -259,22 +81,24 @@ __global__ void k_gather_rows(uint64_t *out, const uint64_t *dense, const uint32
 
 using KernelFn = void (*)(const BucketDesc *, const TestArgs, uint32_t, uint32_t);
 
+// row words RW (power of two) -> lanes per clause and words per lane (a lane
+// takes one 32-byte sector: 4 words, or the whole row when it is shorter)
 template <int MODE, bool HOT>
-static KernelFn pick_lpc(uint32_t lpc) {
-    switch (lpc) {
-    case 1: return k_test<1, MODE, HOT>;
-    case 2: return k_test<2, MODE, HOT>;
-    case 4: return k_test<4, MODE, HOT>;
-    case 8: return k_test<8, MODE, HOT>;
-    case 16: return k_test<16, MODE, HOT>;
-    case 32: return k_test<32, MODE, HOT>;
-    default: return k_test<64, MODE, HOT>;
+static KernelFn pick_rw(uint32_t rw) {
+    switch (rw) {
+    case 1: return k_test<1, 1, MODE, HOT>;
+    case 2: return k_test<1, 2, MODE, HOT>;
+    case 4: return k_test<1, 4, MODE, HOT>;
+    case 8: return k_test<2, 4, MODE, HOT>;
+    case 16: return k_test<4, 4, MODE, HOT>;
+    case 32: return k_test<8, 4, MODE, HOT>;
+    default: return k_test<16, 4, MODE, HOT>;
     }
 }
 
-static KernelFn pick_kernel(uint32_t lpc, int mode, bool hot) {
-    if (mode == 0) return hot ? pick_lpc<0, true>(lpc) : pick_lpc<0, false>(lpc);
-    return hot ? pick_lpc<1, true>(lpc) : pick_lpc<1, false>(lpc);
+static KernelFn pick_kernel(uint32_t rw, int mode, bool hot) {
+    if (mode == 0) return hot ? pick_rw<0, true>(rw) : pick_rw<0, false>(rw);
+    return hot ? pick_rw<1, true>(rw) : pick_rw<1, false>(rw);
 }
 
 struct Launch {
@@ -298,6 +122,8 @@ static Launch prepare(Ctx &c, uint32_t flags) {
         BucketDesc d{};
         d.lits = B.lits;
         d.meta = B.meta;
+        d.lits_bytes = B.cap_slots << B.stride_log2 << 2;
+        d.meta_bytes = B.cap_slots * 8;
         d.stride_log2 = B.stride_log2;
         d.tile_begin = tiles;
         h[nb++] = d;
@@ -316,12 +142,12 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     a.dense = c.dense;
     if (nb) GSS_HIP(hipMemcpyAsync(c.d_desc, h, nb * sizeof(BucketDesc), hipMemcpyHostToDevice, c.stream));
     L.descs = (const BucketDesc *)c.d_desc;
-    L.fn = pick_kernel(c.LPC, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot);
-    uint64_t per_cu = kTestBlocksPerCU;
-    if (hot) {
-        L.lds = (size_t)a.hot_rows * c.W * 8;
-        per_cu = std::max<uint64_t>(1, std::min<uint64_t>(per_cu, (160u * 1024u) / L.lds));
-    }
+    L.fn = pick_kernel(c.RW, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot);
+    if (hot) L.lds = (size_t)a.hot_rows * c.RW * 8;
+    // persistent: exactly as many workgroups as fit on the device at once
+    int fit = 0;
+    GSS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, L.fn, kTestWavesPerBlock * 64, L.lds));
+    const uint64_t per_cu = std::max<int>(1, std::min<int>(fit, (int)kTestBlocksPerCU));
     const uint64_t one_tile_each = (tiles + kTestWavesPerBlock - 1) / kTestWavesPerBlock;
     L.grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(one_tile_each, per_cu * c.n_cu));
     return L;
@@ -394,6 +220,7 @@ extern "C" gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_rep
                 c.dfree(c.reports);
                 c.reports = p;
                 c.seg_cap = (uint32_t)want;
+                c.version++;
                 grown = true;
             } catch (const Error &e) {
                 if (e.code != GSS_ERR_CAPACITY) throw;

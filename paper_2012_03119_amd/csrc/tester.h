@@ -1,0 +1,286 @@
+// Device side of the clause test (Sections 3.4-3.5), shared by the single-store
+// kernel (test.hip) and the batched kernel (batch.hip).
+//
+// Two forms of parallelism, as in Section 3.5: wavefront lanes work on different
+// clauses, and each lane tests up to 256 assignment slots at once with 64-bit
+// bitwise operations.  A clause is spread over LPC lanes, each lane owning WPL
+// consecutive 64-slot words of the plane row (one 32-byte sector: the unit in
+// which scattered reads are filled), so a wavefront covers T = 64 / LPC clauses.
+//
+// Falsified mode: the clause mask is the AND over its literals of the gathered
+// plane words (the allFalse half of the bitwise trigger test of Section 3.4).
+// Trigger mode (Definition 1): the same loop also carries the oneUndef words,
+// which need the row of the opposite literal as well (isSet = F-row | T-row).
+//
+// Early exit: a wavefront stops reading literals once no lane of its clauses has
+// a live bit left; a lane whose words are all dead issues no more loads.  Hot
+// rows (the first `hot_rows` plane rows; literals are kept in code order inside a
+// clause, so the first literals land there most often) can be staged in LDS.
+//
+// Reports need no atomics: every wavefront owns one segment of the report buffer
+// and appends its records at its running count + (records of lower lanes, from
+// mbcnt).  Counts beyond a segment's capacity are still counted, so the exact
+// size needed is always known.
+#pragma once
+
+#include "gss_internal.h"
+
+namespace gss {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kGroup = 4;  // literals gathered between a lane's liveness checks
+
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that a
+// contiguous range of logical workgroups (neighbouring tiles, sharing cache lines
+// of the code and metadata streams and, with clauses ordered by lead literal,
+// the plane rows of their first literals) runs on one XCD and its L2.
+__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+    constexpr uint32_t X = 8;
+    const uint32_t x = b % X, i = b / X, q = nb / X, r = nb % X;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Buffer resources for the per-tile loads: pointers read from the descriptor
+// table would otherwise become flat loads (tracked by the LDS counter too); a
+// buffer load is a plain vector-memory load with a 32-bit byte offset.
+constexpr int kBufferDword3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint64_t bytes) {
+    const int n = bytes >= 0xFFFFFFFFull ? -1 : (int)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, n, kBufferDword3);
+}
+
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <uint32_t X>
+constexpr uint32_t ilog2() {
+    return X <= 1 ? 0 : 1 + ilog2<X / 2>();
+}
+
+// Plane words of one lane: WPL consecutive 64-slot words.
+template <int WPL>
+struct Words {
+    uint64_t v[WPL];
+};
+
+template <int WPL>
+__device__ inline Words<WPL> load_words(const char *p) {
+    Words<WPL> r;
+    if constexpr (WPL == 1) {
+        r.v[0] = *reinterpret_cast<const uint64_t *>(p);
+    } else if constexpr (WPL == 2) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(p);
+        r.v[0] = ((uint64_t)a.y << 32) | a.x;
+        r.v[1] = ((uint64_t)a.w << 32) | a.z;
+    } else {
+        const uint4 a = *reinterpret_cast<const uint4 *>(p);
+        const uint4 b = *reinterpret_cast<const uint4 *>(p + 16);
+        r.v[0] = ((uint64_t)a.y << 32) | a.x;
+        r.v[1] = ((uint64_t)a.w << 32) | a.z;
+        r.v[2] = ((uint64_t)b.y << 32) | b.x;
+        r.v[3] = ((uint64_t)b.w << 32) | b.z;
+    }
+    return r;
+}
+
+// One store's clause test for one lane: LPC lanes per clause, WPL words per lane,
+// a plane row of RW = LPC * WPL words.  MODE 0 = falsified, 1 = trigger.
+template <int LPC, int WPL, int MODE, bool HOT>
+struct Tester {
+    static constexpr uint32_t T = 64 / LPC;                 // clauses per wavefront (and per tile)
+    static constexpr uint32_t RW = LPC * WPL;               // words per plane row
+    static constexpr uint32_t ROW_SHIFT = ilog2<RW>() + 3;  // bytes per plane row
+
+    // a tile: wave-uniform code resource and stride, this lane's byte offset of its
+    // clause's codes, its metadata (length, id) and its codes 0..3
+    struct Tile {
+        __amdgpu_buffer_rsrc_t lits;
+        uint32_t s_log2;
+        uint32_t code_off;
+        uint2 meta;
+        uint4 c0;
+    };
+
+    uint32_t j;    // clause of this lane within the tile
+    uint32_t w0;   // first word of this lane
+    uint32_t W;    // words in use
+    uint32_t hot_rows;
+    bool lane_ok;  // this lane owns at least one word in use
+    uint64_t act[WPL];
+    const char *pbase;
+    const uint64_t *lds;
+
+    __device__ Tester(uint32_t lane, const uint64_t *planes, const uint64_t *active, uint32_t W_, uint32_t hot_rows_,
+                      const uint64_t *lds_)
+        : j(lane / LPC), w0((lane % LPC) * WPL), W(W_), hot_rows(hot_rows_), lds(lds_) {
+        lane_ok = w0 < W;
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) act[i] = (w0 + i < W) ? active[w0 + i] : 0;
+        pbase = reinterpret_cast<const char *>(planes) + w0 * 8;
+    }
+
+    // This lane's words of plane row `code`.  Code 0 is the all-ones row, the
+    // identity of the AND: literals past a clause's end read it.
+    __device__ Words<WPL> gather(uint32_t code) const {
+        if constexpr (HOT) {
+            if (code < hot_rows) {
+                Words<WPL> r;
+#pragma unroll
+                for (int i = 0; i < WPL; ++i) r.v[i] = lds[code * RW + w0 + i];
+                return r;
+            }
+        }
+        return load_words<WPL>(pbase + (code << ROW_SHIFT));
+    }
+
+    // Locates tile t (bi: bucket cursor, only ever advanced) and issues the loads
+    // of this lane's metadata and first four codes.
+    __device__ void open(const BucketDesc *descs, uint32_t n_buckets, uint32_t &bi, uint32_t t, Tile &tl) const {
+        while (bi + 1 < n_buckets && t >= descs[bi + 1].tile_begin) ++bi;
+        const BucketDesc &d = descs[bi];
+        const uint32_t slot = (t - d.tile_begin) * T + j;
+        tl.s_log2 = d.stride_log2;
+        tl.lits = make_rsrc(d.lits, d.lits_bytes);
+        tl.code_off = slot << (d.stride_log2 + 2);
+        const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(d.meta, d.meta_bytes), slot * 8u, 0, 0);
+        tl.meta = make_uint2(m[0], m[1]);
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(tl.lits, tl.code_off, 0, 0);
+        tl.c0 = make_uint4(q[0], q[1], q[2], q[3]);
+    }
+
+    // Tests the clauses of an opened tile.  Records go to seg (capacity seg_cap)
+    // after the `produced` records already there; returns the new count.  With
+    // dense != nullptr, writes each clause's mask row there instead.
+    __device__ uint32_t run(const Tile &cur, gss_report *seg, uint32_t seg_cap, uint32_t produced, uint32_t early_exit,
+                            uint64_t *dense) const {
+        const uint32_t len = cur.meta.x;
+        const uint32_t S = 1u << cur.s_log2;
+        uint64_t af[WPL], ou[WPL];  // allFalse, oneUndef (trigger mode)
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) {
+            af[i] = len ? act[i] : 0;
+            ou[i] = 0;
+        }
+        uint4 c = cur.c0;
+        for (uint32_t k = 0;; k += 4) {
+            {
+                uint64_t any = 0;
+#pragma unroll
+                for (int i = 0; i < WPL; ++i) any |= af[i] | ou[i];
+                if (!__ballot(lane_ok && k < len && (!early_exit || any != 0))) break;
+            }
+            uint4 cn = make_uint4(0, 0, 0, 0);
+            if (k + 4 < S) {  // uniform branch: the next four codes, in flight during this group
+                const auto q = __builtin_amdgcn_raw_buffer_load_b128(cur.lits, cur.code_off + (k + 4) * 4u, 0, 0);
+                cn = make_uint4(q[0], q[1], q[2], q[3]);
+            }
+            const uint32_t cs[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (uint32_t g0 = 0; g0 < 4; g0 += kGroup) {
+                // a lane re-checks its words every kGroup literals; finished lanes issue no loads
+                uint64_t any = 0;
+#pragma unroll
+                for (int i = 0; i < WPL; ++i) any |= af[i] | ou[i];
+                const bool lane_live = lane_ok && k + g0 < len && (!early_exit || any != 0);
+                if (lane_live) {
+                    Words<WPL> gf[kGroup], gt[kGroup];
+#pragma unroll
+                    for (uint32_t u = 0; u < kGroup; ++u) {
+                        const uint32_t code = (k + g0 + u < len) ? cs[g0 + u] : 0u;
+                        gf[u] = gather(code);
+                        if constexpr (MODE == 1) gt[u] = gather(code ^ 1u);
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kGroup; ++u) {
+#pragma unroll
+                        for (int i = 0; i < WPL; ++i) {
+                            if constexpr (MODE == 1) {
+                                const uint64_t is_set = gf[u].v[i] | gt[u].v[i];
+                                ou[i] = (af[i] & ~is_set) | (ou[i] & gf[u].v[i]);
+                            }
+                            af[i] &= gf[u].v[i];
+                        }
+                    }
+                }
+            }
+            c = cn;
+        }
+
+        if (dense) {
+            if (len) {
+#pragma unroll
+                for (int i = 0; i < WPL; ++i)
+                    if (w0 + i < W) dense[(uint64_t)cur.meta.y * W + w0 + i] = af[i] | ou[i];
+            }
+            return produced;
+        }
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) {
+            const uint64_t res = af[i] | ou[i];
+            const bool has = res != 0;
+            const uint64_t bal = __ballot(has);
+            if (has) {
+                const uint32_t pos = produced + lanes_below(bal);
+                if (pos < seg_cap) {
+                    const u32x4 rec = {cur.meta.y, w0 + i, (uint32_t)res, (uint32_t)(res >> 32)};
+                    __builtin_nontemporal_store(rec, reinterpret_cast<u32x4 *>(seg) + pos);
+                }
+            }
+            produced += (uint32_t)__builtin_popcountll(bal);
+        }
+        return produced;
+    }
+};
+
+// Called by one workgroup of 1024 threads: exclusive prefix of the records each
+// segment kept (min(count, cap)) into offsets[0..n], and summary = {total count,
+// largest count, records kept}.
+__device__ inline void finalize_segments(const uint32_t *counts, uint32_t n, uint32_t cap, uint64_t *offsets,
+                                         unsigned long long *summary) {
+    __shared__ unsigned long long part[1024];
+    __shared__ unsigned long long tot[1024];
+    __shared__ unsigned int mx[1024];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t lo = tid * per, hi = min(n, lo + per);
+    unsigned long long kept = 0, all = 0;
+    unsigned int m = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        kept += min(counts[i], cap);
+        all += counts[i];
+        m = max(m, counts[i]);
+    }
+    part[tid] = kept;
+    tot[tid] = all;
+    mx[tid] = m;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of part[]; tree reductions of tot[] and mx[]
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const unsigned long long p = tid >= off ? part[tid - off] : 0ull;
+        const unsigned long long q = (tid + off < 1024) ? tot[tid + off] : 0ull;
+        const unsigned int r = (tid + off < 1024) ? mx[tid + off] : 0u;
+        __syncthreads();
+        part[tid] += p;
+        if ((tid & (2 * off - 1)) == 0) {
+            tot[tid] += q;
+            mx[tid] = max(mx[tid], r);
+        }
+        __syncthreads();
+    }
+    unsigned long long base = tid ? part[tid - 1] : 0ull;
+    for (uint32_t i = lo; i < hi; ++i) {
+        offsets[i] = base;
+        base += min(counts[i], cap);
+    }
+    if (tid == 1023) offsets[n] = part[1023];
+    if (tid == 0) {
+        summary[0] = tot[0];
+        summary[1] = mx[0];
+        summary[2] = part[1023];
+    }
+}
+
+}  // namespace gss

@@ -35,6 +35,11 @@ GSS_TEST_SORTED = 4
 GSS_TEST_DENSE = 8
 GSS_TEST_NO_REGROW = 16
 GSS_TEST_NO_HOT = 32
+GSS_TEST_GRAPH = 64
+
+GSS_ORDER_STORE = 0
+GSS_ORDER_INTERLEAVE = 1
+GSS_ORDER_LONGEST_FIRST = 2
 
 REPORT_DTYPE = np.dtype([("clause_id", "<u4"), ("word", "<u4"), ("mask", "<u8")])
 
@@ -79,6 +84,11 @@ class gss_stats(ctypes.Structure):
         ("timed_launches", ctypes.c_uint64)]
 
 
+class gss_schedule(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_uint32), ("chunk_tiles", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 _lib = None
 
 
@@ -109,6 +119,12 @@ def load_library(path: Optional[str] = None):
         "gss_get_stats": ([P, ctypes.POINTER(gss_stats)], ctypes.c_int32),
         "gss_reset_stats": ([P], ctypes.c_int32),
         "gss_get_stream": ([P, ctypes.POINTER(P)], ctypes.c_int32),
+        "gss_batch_create": ([P, u32, ctypes.POINTER(P)], ctypes.c_int32),
+        "gss_batch_destroy": ([P], None),
+        "gss_batch_last_error": ([P], ctypes.c_char_p),
+        "gss_batch_set_schedule": ([P, ctypes.POINTER(gss_schedule)], ctypes.c_int32),
+        "gss_batch_test": ([P, u32, P], ctypes.c_int32),
+        "gss_batch_info": ([P, P, P, P, P], ctypes.c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -243,6 +259,43 @@ def gss_get_stream(ctx) -> int:
     return p.value or 0
 
 
+def gss_batch_create(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    b = ctypes.c_void_p()
+    rc = load_library().gss_batch_create(arr, len(ctxs), ctypes.byref(b))
+    if rc != GSS_OK:
+        raise GssError(rc, "gss_batch_create failed")
+    return b
+
+
+def gss_batch_destroy(b) -> None:
+    load_library().gss_batch_destroy(b)
+
+
+def _check_batch(b, rc: int):
+    if rc != GSS_OK:
+        msg = load_library().gss_batch_last_error(b)
+        raise GssError(rc, msg.decode() if msg else "")
+
+
+def gss_batch_set_schedule(b, order: int, chunk_tiles: int = 0, blocks_per_cu: int = 0) -> None:
+    s = gss_schedule(order, chunk_tiles, blocks_per_cu, 0)
+    _check_batch(b, load_library().gss_batch_set_schedule(b, ctypes.byref(s)))
+
+
+def gss_batch_test(b, n: int, flags: int = 0) -> np.ndarray:
+    out = np.zeros(n, dtype=np.uint64)
+    _check_batch(b, load_library().gss_batch_test(b, flags, _np_ptr(out)))
+    return out
+
+
+def gss_batch_info(b) -> dict:
+    ms, la, ca, ti = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check_batch(b, load_library().gss_batch_info(b, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(ca),
+                                                 ctypes.byref(ti)))
+    return dict(last_ms=ms.value, launches=la.value, captures=ca.value, tiles=ti.value)
+
+
 # ---------------------------------------------------------------------------
 # convenience wrapper
 # ---------------------------------------------------------------------------
@@ -251,7 +304,7 @@ class Context:
     """One clause store plus one set of assignment slots on the current GPU."""
 
     def __init__(self, num_vars: int, max_slots: int = 64, *, hbm_budget_bytes: int = 0,
-                 report_capacity: int = 1 << 16, hot_vars: int = 0, use_torch: bool = True):
+                 report_capacity: int = 1 << 16, hot_vars: int = 0, use_torch: bool = True, stream=None):
         self.num_vars = int(num_vars)
         self.max_slots = int(max_slots)
         self.n_words = self.max_slots // 64
@@ -268,7 +321,8 @@ class Context:
             if not torch.cuda.is_available():
                 raise RuntimeError("no GPU visible to torch")
             dev = torch.cuda.current_device()
-            self.torch_stream = torch.cuda.Stream(device=dev)   # default priority
+            # a shared stream (batches need one) or a stream of its own; default priority
+            self.torch_stream = stream if stream is not None else torch.cuda.Stream(device=dev)
             cfg.stream = self.torch_stream.cuda_stream
 
             def _alloc(size, stream, user):
@@ -358,3 +412,37 @@ class Context:
 def sort_reports(r: np.ndarray) -> np.ndarray:
     """Orders records by (clause_id, word), the canonical order for comparisons."""
     return np.sort(r, order=["clause_id", "word"])
+
+
+class Batch:
+    """Several contexts (sharing one stream) tested in one persistent launch."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        self.b = gss_batch_create([c.ctx for c in self.contexts])
+
+    def set_schedule(self, order: int, chunk_tiles: int = 0, blocks_per_cu: int = 0) -> None:
+        gss_batch_set_schedule(self.b, order, chunk_tiles, blocks_per_cu)
+
+    def test(self, flags: int = 0) -> np.ndarray:
+        return gss_batch_test(self.b, len(self.contexts), flags)
+
+    def info(self) -> dict:
+        return gss_batch_info(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            gss_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,126 @@
+"""Batched test (several independent stores, one persistent launch), GPU.
+
+Per store, the batched results equal the oracle's element by element, under
+every schedule, with and without hipGraph replay (replays interleaved with
+changes of the assignments and of the stores), and equal each store's own
+gss_test.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import full_values, mismatch_summary, reports_to_dense
+from paper_2012_03119_amd import gen, gss
+
+pytestmark = pytest.mark.gpu
+
+# (clauses, vars, slots): uneven sizes, variable counts and widths, like the
+# batched workload at a scale the oracle checks in seconds
+STORES = [(1000, 4000, 1024), (2500, 500, 64), (5000, 3000, 512), (10000, 850, 128),
+          (15000, 2000, 768), (20000, 1400, 256), (25000, 4100, 384), (30000, 2400, 192)]
+
+
+def _make(seed):
+    import torch
+    stream = torch.cuda.Stream()
+    items = []
+    for i, (n, v, a) in enumerate(STORES):
+        w = gen.paper(seed * 100 + i, n_clauses=n, n_vars=v, n_slots=a, planted_rate=0.0)
+        ctx = gss.Context(v, a, stream=stream)
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, w.values)
+        items.append([w, ctx, w.values.copy()])
+    return stream, items
+
+
+def _dense(ctx, n_ids):
+    r = ctx.fetch_reports()
+    return reports_to_dense(r, n_ids, ctx.n_words)
+
+
+def _check_all(items, counts, mode="falsified"):
+    for (w, ctx, vals), n in zip(items, counts):
+        got = _dense(ctx, w.n_clauses)
+        assert int(np.count_nonzero(got)) == int(n)
+        want = oracle.masks(w.lits, w.offsets, vals, mode=mode)
+        assert np.array_equal(got, want), mismatch_summary(got, want)
+
+
+@pytest.mark.parametrize("order,chunk,bpc", [
+    (gss.GSS_ORDER_STORE, 0, 0), (gss.GSS_ORDER_INTERLEAVE, 1, 0), (gss.GSS_ORDER_INTERLEAVE, 64, 2),
+    (gss.GSS_ORDER_LONGEST_FIRST, 16, 0), (gss.GSS_ORDER_LONGEST_FIRST, 256, 1),
+])
+@pytest.mark.parametrize("mode", ["falsified", "trigger"])
+def test_batch_schedules(order, chunk, bpc, mode):
+    _, items = _make(3)
+    flags = gss.GSS_TEST_TRIGGER if mode == "trigger" else 0
+    print(f"batch order={order} chunk={chunk} bpc={bpc} mode={mode}", flush=True)
+    with gss.Batch([it[1] for it in items]) as b:
+        b.set_schedule(order, chunk, bpc)
+        counts = b.test(flags)
+        _check_all(items, counts, mode)
+    for it in items:
+        it[1].close()
+
+
+def test_batch_equals_plain_and_graph_replays():
+    _, items = _make(4)
+    plain = []
+    for w, ctx, vals in items:
+        ctx.test()
+        plain.append(_dense(ctx, w.n_clauses))
+    with gss.Batch([it[1] for it in items]) as b:
+        b.set_schedule(gss.GSS_ORDER_INTERLEAVE, 32)
+        counts = b.test(gss.GSS_TEST_GRAPH)
+        for (w, ctx, vals), ref in zip(items, plain):
+            assert np.array_equal(_dense(ctx, w.n_clauses), ref)
+        assert b.info()["captures"] == 1
+        rng = np.random.default_rng(8)
+        for rep in range(4):
+            # eager work between replays: new values for some variables of every store
+            for it in items:
+                w, ctx, vals = it
+                vs = np.sort(rng.choice(w.n_vars, max(1, w.n_vars // 20), replace=False)) + 1
+                vals[:, vs - 1] = -vals[:, vs - 1]
+                ctx.set_var_values(0, vs, np.ascontiguousarray(vals[:, vs - 1].T))
+            counts = b.test(gss.GSS_TEST_GRAPH)
+            print(f"graph replay {rep}", flush=True)
+            _check_all(items, counts)
+        assert b.info()["captures"] == 1          # replayed, not re-captured
+        # a store change forces a new capture, and results follow it
+        w, ctx, vals = items[2]
+        extra = gen.paper(77, n_clauses=3000, n_vars=w.n_vars, n_slots=w.n_slots)
+        ids = ctx.add_clauses(extra.lits, extra.offsets)
+        lits = np.concatenate([w.lits, extra.lits])
+        offs = np.concatenate([w.offsets, w.offsets[-1] + extra.offsets[1:]])
+        items[2][0] = gen.Workload("x", w.n_vars, lits, offs, vals, w.planted, 0)
+        counts = b.test(gss.GSS_TEST_GRAPH)
+        assert b.info()["captures"] == 2
+        _check_all(items, counts)
+    for it in items:
+        it[1].close()
+
+
+def test_batch_overflow_regrows():
+    _, items = _make(5)
+    with gss.Batch([it[1] for it in items]) as b:
+        counts = b.test()
+        _check_all(items, counts)
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    from paper_2012_03119_amd import autotune
+    import torch
+    _, items = _make(6)
+    shapes = [(it[0].n_clauses, it[0].n_vars, it[0].n_slots) for it in items]
+    cache = str(tmp_path / "tune.json")
+    with gss.Batch([it[1] for it in items]) as b:
+        first = autotune.autotune(b, shapes, torch.cuda.get_device_name(0), reps=1, cache_path=cache)
+        assert first["source"] == "measured" and len(first["trials"]) == len(autotune.CANDIDATES)
+        assert first["ms"] == min(t["ms"] for t in first["trials"])
+        counts = b.test()
+        _check_all(items, counts)            # the chosen schedule is still exact
+        again = autotune.autotune(b, shapes, torch.cuda.get_device_name(0), cache_path=cache)
+        assert again["source"] == "cache" and again["order"] == first["order"]
+    for it in items:
+        it[1].close()

@@ -283,10 +283,10 @@ def test_argument_errors_leave_state_unchanged():
 
 
 def test_report_overflow_and_regrow():
-    # more tiles than wavefronts, each tile full of hits: segments of 64 records overflow
+    # more tiles than wavefronts, each tile full of hits: segments of 256 records overflow
     n_vars, max_slots = 64, 1024
     rng = np.random.default_rng(17)
-    lengths = rng.integers(1, 3, 60_000)
+    lengths = rng.integers(1, 3, 250_000)
     lits, offsets = gen.random_clauses(rng, lengths, n_vars)
     vals_n = np.where(rng.random((max_slots, n_vars)) < 0.9, -1, 0).astype(np.int8)
     vals_n[:, ::2] *= -1
@@ -319,3 +319,24 @@ def test_hbm_budget():
         ctx.add_clauses(w.lits, w.offsets)             # a small batch still fits
         ctx.set_assignments(0, w.values)
         _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, w.values))
+
+
+def test_invalid_device_values_apply_nothing():
+    import torch
+    w = gen.tiny(9)
+    with new_context(w.n_vars, 64) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, w.values)
+        before = gpu_dense(ctx, w.n_clauses)
+        bad = torch.from_numpy(-w.values).cuda()
+        bad[3, 7] = 5
+        with pytest.raises(gss.GssError) as e:
+            ctx.set_assignments(0, bad)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+        vs = np.arange(1, 50, dtype=np.uint32)
+        badd = torch.zeros((len(vs), 64), dtype=torch.int8, device="cuda")
+        badd[10, 10] = -3
+        with pytest.raises(gss.GssError) as e:
+            ctx.set_var_values(0, vs, badd)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+        _check(gpu_dense(ctx, w.n_clauses), before)
