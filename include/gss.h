@@ -131,6 +131,20 @@ gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slo
 gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, uint32_t n_vars,
                               const uint32_t *vars, const int8_t *values);
 
+/* Packed delta for one 64-slot word (a solver thread that keeps its group of 64
+ * assignments as bit words sends only the changed variables): for each listed
+ * variable vars[i] (distinct, 1..num_vars), bit b of f_words[i] says slot
+ * 64*word+b has the variable F, bit b of t_words[i] that it has it T (both 0 =
+ * U; both 1 is INVALID_ARG).  Host arrays.  Other variables and words are
+ * unchanged; activity is not changed. */
+gss_status gss_update_words(gss_ctx *ctx, uint32_t word, uint32_t n_vars, const uint32_t *vars,
+                            const uint64_t *f_words, const uint64_t *t_words);
+
+/* Replaces the set of active slots (W words, host): the slots a test reports on.
+ * Plane values of inactive slots are kept, so a slot group can be switched off
+ * between runs and on again after further deltas. */
+gss_status gss_set_active(gss_ctx *ctx, const uint64_t *active);
+
 /* Makes slots first_slot .. first_slot+n_slots-1 inactive and all-Undef.  Tests
  * report nothing for inactive slots (Section 3.5 tests up to a fixed number of
  * assignments per run; a freed slot can take the next assignment). */
@@ -157,6 +171,16 @@ gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots);
  * set and device (GSS_TEST_SORTED, ordering by id and word, is reserved and
  * rejected with GSS_ERR_INVALID_ARG by this version). */
 gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_reports);
+
+/* The same test split in two: gss_test_async queues it and returns; the host may
+ * prepare the next run meanwhile (calls that change the store or the planes are
+ * queued behind the test on the context's stream).  gss_test_query sets *done
+ * once the results are in; gss_test_wait waits, then behaves as the end of
+ * gss_test (overflow handling included).  Only one test may be in flight;
+ * gss_fetch_reports before gss_test_wait is GSS_ERR_STATE. */
+gss_status gss_test_async(gss_ctx *ctx, uint32_t flags);
+gss_status gss_test_query(gss_ctx *ctx, int *done);
+gss_status gss_test_wait(gss_ctx *ctx, uint64_t *out_n_reports);
 
 /* Copies the records of the last gss_test into out (host or device, room for cap
  * records) as one list.  *out_n receives the number copied: min(cap, records

@@ -38,13 +38,25 @@ void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value) {
     GSS_HIP(hipGetLastError());
 }
 
-// Sets *bad when any byte is outside {-1, 0, +1}.
+// Sets *bad when any byte is outside {-1, 0, +1}.  Sixteen bytes per load; a byte
+// x is valid iff (x + 1) as an unsigned byte is at most 2.
 __global__ void k_check_values(const int8_t *v, uint64_t n, unsigned int *bad) {
     unsigned found = 0;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        int8_t x = v[i];
-        found |= (x < -1 || x > 1);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t head = (16 - ((uintptr_t)v & 15)) & 15;  // bytes before the first aligned block
+    for (uint64_t i = tid; i < head && i < n; i += stride) found |= (uint8_t)(v[i] + 1) > 2;
+    const uint64_t n16 = n > head ? (n - head) / 16 : 0;
+    const uint4 *q = reinterpret_cast<const uint4 *>(v + head);
+    for (uint64_t i = tid; i < n16; i += stride) {
+        const uint4 x = q[i];
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) found |= (((w[k] >> (8 * s)) + 1) & 0xFFu) > 2;
     }
+    for (uint64_t i = head + n16 * 16 + tid; i < n; i += stride) found |= (uint8_t)(v[i] + 1) > 2;
     if (found) atomicOr(bad, 1u);
 }
 
@@ -153,6 +165,38 @@ void *Ctx::host_stage(size_t bytes) {
 
 void Ctx::sync() { GSS_HIP(hipStreamSynchronize(stream)); }
 
+Ctx::Staged Ctx::stage_upload(size_t bytes) {
+    const int k = ring_next;
+    ring_next = (ring_next + 1) % kRing;
+    RingSlot &s = ring[k];
+    if (s.busy) {
+        GSS_HIP(hipEventSynchronize(s.done));
+        s.busy = false;
+    }
+    if (!s.done) GSS_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    if (bytes > s.bytes) {
+        const size_t want = std::max<size_t>({bytes, 2 * s.bytes, (size_t)1 << 16});
+        char *d = (char *)dalloc(want);  // may raise CAPACITY; the slot is unchanged then
+        char *h = nullptr;
+        if (hipHostMalloc((void **)&h, want, hipHostMallocDefault) != hipSuccess) {
+            dfree(d);
+            throw Error(GSS_ERR_DEVICE, "hipHostMalloc failed for the upload ring");
+        }
+        dfree(s.d);
+        if (s.h) (void)hipHostFree(s.h);
+        s.d = d;
+        s.h = h;
+        s.bytes = want;
+    }
+    return Staged{s.h, s.d, k};
+}
+
+void Ctx::stage_done(const Staged &st) {
+    RingSlot &s = ring[st.slot];
+    GSS_HIP(hipEventRecord(s.done, stream));
+    s.busy = true;
+}
+
 }  // namespace gss
 
 using namespace gss;
@@ -179,6 +223,11 @@ static void destroy_ctx(Ctx *c) {
     c->dfree(c->dense);
     c->dfree(c->dstage);
     if (c->hstage) (void)hipHostFree(c->hstage);
+    for (auto &s : c->ring) {
+        c->dfree(s.d);
+        if (s.h) (void)hipHostFree(s.h);
+        if (s.done) (void)hipEventDestroy(s.done);
+    }
     if (c->h_summary) (void)hipHostFree(c->h_summary);
     c->dfree(c->dsmall);
     c->dfree(c->d_desc);
@@ -187,6 +236,7 @@ static void destroy_ctx(Ctx *c) {
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
+    if (c->ev_done) (void)hipEventDestroy(c->ev_done);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -263,6 +313,7 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         GSS_HIP(hipEventCreate(&c->ev_start));
         GSS_HIP(hipEventCreate(&c->ev_stop));
         GSS_HIP(hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming));
+        GSS_HIP(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
         c->sync();
     } catch (const Error &e) {
         g_create_error = e.what();

@@ -168,6 +168,10 @@ struct Ctx {
 
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     hipEvent_t ev_stage = nullptr;  // recorded after the last queued use of the staging buffers
+    hipEvent_t ev_done = nullptr;   // recorded after a test's summary copy
+    bool pending = false;           // gss_test_async issued, gss_test_wait not yet called
+    bool pending_launched = false;
+    uint32_t pending_flags = 0;
     bool stage_pending = false;
     gss_stats stats{};
     std::string last_error;
@@ -175,13 +179,34 @@ struct Ctx {
     // device memory within the budget
     void *dalloc(size_t bytes);
     void dfree(void *p);
-    // Staging buffers: the returned memory is free to write (queued work that read
-    // it has finished).  A call that leaves work reading staging memory queued
-    // calls stage_release() instead of synchronising.
+    // Bulk staging (large uploads and downloads that synchronise): the returned
+    // memory is free to write (queued work that read it has finished).  A call
+    // that leaves work reading it queued calls stage_release().
     void *device_stage(size_t bytes);
     void *host_stage(size_t bytes);
     void stage_release();
     void sync();
+
+    // Upload ring: small uploads (deltas, inserts, removals, activity) take a slot
+    // of pinned host + device memory; the slot is released by an event recorded
+    // behind the kernels that read it, so a caller can queue uploads behind a test
+    // still running without waiting for it.
+    struct Staged {
+        char *h;
+        char *d;
+        int slot;
+    };
+    static constexpr int kRing = 8;
+    struct RingSlot {
+        char *h = nullptr;
+        char *d = nullptr;
+        size_t bytes = 0;
+        hipEvent_t done = nullptr;
+        bool busy = false;
+    } ring[kRing];
+    int ring_next = 0;
+    Staged stage_upload(size_t bytes);           // a free slot of at least `bytes`
+    void stage_done(const Staged &s);            // its consumers are queued
 };
 
 // kernels / launchers (defined in the .hip files)

@@ -60,42 +60,46 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RW,
 }
 
 // Delta update: new values of listed variables over a slot range.  One wavefront
-// per variable; lane b covers slot 64*w + b of each word w in the range, and the
-// finished words are written by lanes 0..(words-1).  vals is var-major
-// [n_vars][n_slots].
-__global__ __launch_bounds__(64) void k_set_vars(uint64_t *planes, uint32_t RW, const uint32_t *vars, uint32_t n_vars,
-                                                 const int8_t *vals, uint32_t first, uint32_t n_slots,
-                                                 const uint32_t *bad) {
+// per (variable, 64-slot word): lane b reads slot 64*w + b (coalesced across the
+// lanes), two ballots build the word, lane 0 merges it into the row.  vals is
+// var-major [n_vars][n_slots].
+__global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RW, const uint32_t *vars, uint32_t n_vars,
+                                                  const int8_t *vals, uint32_t first, uint32_t n_slots,
+                                                  const uint32_t *bad) {
     if (*bad) return;  // the inputs failed validation: apply nothing
-    const uint32_t lane = threadIdx.x;
-    const uint32_t w_lo = first / 64, w_hi = (first + n_slots - 1) / 64;
-    for (uint32_t i = blockIdx.x; i < n_vars; i += gridDim.x) {
-        const uint32_t v = vars[i];
-        uint64_t my_f = 0, my_t = 0, my_sm = 0;
-        for (uint32_t w = w_lo; w <= w_hi; ++w) {
-            const uint32_t slot = 64 * w + lane;
-            const bool in = slot >= first && slot < first + n_slots;
-            const int8_t x = in ? vals[(uint64_t)i * n_slots + (slot - first)] : (int8_t)0;
-            const uint64_t bf = __ballot(x == -1);
-            const uint64_t bt = __ballot(x == 1);
-            const uint64_t sm = __ballot(in);
-            if (lane == w - w_lo) {
-                my_f = bf;
-                my_t = bt;
-                my_sm = sm;
-            }
-        }
-        if (lane <= w_hi - w_lo) {
-            const uint32_t w = w_lo + lane;
-            const uint64_t r0 = (uint64_t)(2 * v) * RW + w, r1 = r0 + RW;
-            uint64_t f = my_f, t = my_t;
-            if (my_sm != ~0ull) {
-                f = (planes[r0] & ~my_sm) | (f & my_sm);
-                t = (planes[r1] & ~my_sm) | (t & my_sm);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w_lo = first / 64, nw = (first + n_slots - 1) / 64 - w_lo + 1;
+    const uint64_t total = (uint64_t)n_vars * nw;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+    for (uint64_t g = (uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; g < total; g += waves) {
+        const uint32_t i = (uint32_t)(g / nw), w = w_lo + (uint32_t)(g % nw);
+        const uint32_t slot = 64 * w + lane;
+        const bool in = slot >= first && slot < first + n_slots;
+        const int8_t x = in ? vals[(uint64_t)i * n_slots + (slot - first)] : (int8_t)0;
+        const uint64_t bf = __ballot(x == -1);
+        const uint64_t bt = __ballot(x == 1);
+        const uint64_t sm = __ballot(in);
+        if (lane == 0) {
+            const uint64_t r0 = (uint64_t)(2 * vars[i]) * RW + w, r1 = r0 + RW;
+            uint64_t f = bf, t = bt;
+            if (sm != ~0ull) {
+                f = (planes[r0] & ~sm) | (f & sm);
+                t = (planes[r1] & ~sm) | (t & sm);
             }
             planes[r0] = f;
             planes[r1] = t;
         }
+    }
+}
+
+// Packed delta: new plane words of listed variables in one 64-slot word.  Thread
+// per variable; f = slots where the variable is F, t = slots where it is T.
+__global__ void k_set_words(uint64_t *planes, uint32_t RW, uint32_t word, const uint32_t *vars, const uint64_t *f,
+                            const uint64_t *t, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint64_t r0 = (uint64_t)(2 * vars[i]) * RW + word;
+        planes[r0] = f[i];
+        planes[r0 + RW] = t[i];
     }
 }
 
@@ -119,10 +123,30 @@ static uint64_t slot_mask(uint32_t first, uint32_t n, uint32_t w) {
 }
 
 static void upload_active(Ctx &c) {
-    uint64_t *h = (uint64_t *)c.host_stage(c.W * 8);
-    std::memcpy(h, c.h_active.data(), c.W * 8);
-    GSS_HIP(hipMemcpyAsync(c.active, h, c.W * 8, hipMemcpyHostToDevice, c.stream));
-    c.stage_release();
+    const Ctx::Staged st = c.stage_upload(c.W * 8);
+    std::memcpy(st.h, c.h_active.data(), c.W * 8);
+    GSS_HIP(hipMemcpyAsync(c.active, st.h, c.W * 8, hipMemcpyHostToDevice, c.stream));
+    c.stage_done(st);
+}
+
+// Range and distinctness of a variable list, O(n) with a bitmap that is cleared
+// again afterwards.
+static void check_vars(Ctx &c, const uint32_t *vars, uint32_t n_vars) {
+    std::vector<uint64_t> &seen = c.var_seen;
+    if (seen.size() < (uint64_t)c.cfg.num_vars / 64 + 1) seen.assign((uint64_t)c.cfg.num_vars / 64 + 1, 0);
+    uint32_t bad = 0;  // 1: out of range, 2: repeated
+    uint32_t i = 0;
+    for (; i < n_vars; ++i) {
+        const uint32_t v = vars[i];
+        if (v < 1 || v > c.cfg.num_vars) { bad = 1; break; }
+        uint64_t &word = seen[v >> 6];
+        const uint64_t bit = 1ull << (v & 63);
+        if (word & bit) { bad = 2; break; }
+        word |= bit;
+    }
+    for (uint32_t k = 0; k < i; ++k) seen[vars[k] >> 6] = 0;
+    GSS_REQUIRE(bad != 1, GSS_ERR_BAD_LITERAL, "variable out of range");
+    GSS_REQUIRE(bad != 2, GSS_ERR_INVALID_ARG, "variable listed twice");
 }
 
 static void check_values_host(const int8_t *v, uint64_t n) {
@@ -179,24 +203,7 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
         const uint64_t sm = slot_mask(first_slot, n_slots, w);
         GSS_REQUIRE((c.h_active[w] & sm) == sm, GSS_ERR_INVALID_ARG, "slot range includes inactive slots");
     }
-    {
-        // range and distinctness, O(n) with a bitmap that is cleared again afterwards
-        std::vector<uint64_t> &seen = c.var_seen;
-        if (seen.size() < (uint64_t)c.cfg.num_vars / 64 + 1) seen.assign((uint64_t)c.cfg.num_vars / 64 + 1, 0);
-        uint32_t bad = 0;  // 1: out of range, 2: repeated
-        uint32_t i = 0;
-        for (; i < n_vars; ++i) {
-            const uint32_t v = vars[i];
-            if (v < 1 || v > c.cfg.num_vars) { bad = 1; break; }
-            uint64_t &word = seen[v >> 6];
-            const uint64_t bit = 1ull << (v & 63);
-            if (word & bit) { bad = 2; break; }
-            word |= bit;
-        }
-        for (uint32_t k = 0; k < i; ++k) seen[vars[k] >> 6] = 0;
-        GSS_REQUIRE(bad != 1, GSS_ERR_BAD_LITERAL, "variable out of range");
-        GSS_REQUIRE(bad != 2, GSS_ERR_INVALID_ARG, "variable listed twice");
-    }
+    check_vars(c, vars, n_vars);
     const uint64_t nv = (uint64_t)n_vars * n_slots;
     const bool dev = is_device_pointer(values);
     const uint32_t *bad = c.dsmall + 1;  // always zero
@@ -207,17 +214,18 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
 
     const size_t vars_bytes = ((size_t)n_vars * 4 + 255) / 256 * 256;
     const size_t bytes = vars_bytes + (dev ? 0 : nv);
-    char *h = (char *)c.host_stage(bytes);
-    char *d = (char *)c.device_stage(bytes);
+    const Ctx::Staged st = c.stage_upload(bytes);
+    char *h = st.h, *d = st.d;
     std::memcpy(h, vars, (size_t)n_vars * 4);
     if (!dev) std::memcpy(h + vars_bytes, values, nv);
     GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
     const int8_t *dvals = dev ? values : (const int8_t *)(d + vars_bytes);
-    const unsigned grid = std::min<uint32_t>(n_vars, 65536);
-    hipLaunchKernelGGL(k_set_vars, dim3(grid), dim3(64), 0, c.stream, c.planes, c.RW, (const uint32_t *)d, n_vars,
+    const uint64_t waves = (uint64_t)n_vars * ((first_slot + n_slots - 1) / 64 - first_slot / 64 + 1);
+    const unsigned grid = (unsigned)std::min<uint64_t>((waves + 3) / 4, 1u << 20);
+    hipLaunchKernelGGL(k_set_vars, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, (const uint32_t *)d, n_vars,
                        dvals, first_slot, n_slots, bad);
     GSS_HIP(hipGetLastError());
-    c.stage_release();
+    c.stage_done(st);
     if (dev) check_flag(c);  // one synchronisation: device inputs are fully read when the call returns
     GSS_API_END
 }
@@ -235,6 +243,40 @@ extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_
     GSS_HIP(hipGetLastError());
     for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w)
         c.h_active[w] &= ~slot_mask(first_slot, n_slots, w);
+    upload_active(c);
+    GSS_API_END
+}
+
+extern "C" gss_status gss_update_words(gss_ctx *ctx, uint32_t word, uint32_t n_vars, const uint32_t *vars,
+                                       const uint64_t *f_words, const uint64_t *t_words) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    if (n_vars == 0) return GSS_OK;
+    GSS_REQUIRE(vars && f_words && t_words, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE(word < c.W, GSS_ERR_CAPACITY, "word beyond max_slots / 64");
+    check_vars(c, vars, n_vars);
+    for (uint32_t i = 0; i < n_vars; ++i)
+        GSS_REQUIRE((f_words[i] & t_words[i]) == 0, GSS_ERR_INVALID_ARG, "a slot cannot be both F and T");
+    const size_t vb = ((size_t)n_vars * 4 + 255) / 256 * 256, wb = ((size_t)n_vars * 8 + 255) / 256 * 256;
+    const Ctx::Staged st = c.stage_upload(vb + 2 * wb);
+    char *h = st.h, *d = st.d;
+    std::memcpy(h, vars, (size_t)n_vars * 4);
+    std::memcpy(h + vb, f_words, (size_t)n_vars * 8);
+    std::memcpy(h + vb + wb, t_words, (size_t)n_vars * 8);
+    GSS_HIP(hipMemcpyAsync(d, h, vb + 2 * wb, hipMemcpyHostToDevice, c.stream));
+    const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>((n_vars + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, word, (const uint32_t *)d,
+                       (const uint64_t *)(d + vb), (const uint64_t *)(d + vb + wb), n_vars);
+    GSS_HIP(hipGetLastError());
+    c.stage_done(st);
+    GSS_API_END
+}
+
+extern "C" gss_status gss_set_active(gss_ctx *ctx, const uint64_t *active) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    GSS_REQUIRE(active != nullptr, GSS_ERR_INVALID_ARG, "null argument");
+    std::memcpy(c.h_active.data(), active, c.W * 8);
     upload_active(c);
     GSS_API_END
 }

@@ -230,8 +230,16 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
             p = q;
         }
     }
-    c.device_stage(stage_bytes);  // may raise CAPACITY; nothing has changed yet
-    c.host_stage(stage_bytes);
+    // one chunk goes through the upload ring (no waiting for queued tests);
+    // several use the bulk staging, one chunk at a time
+    const bool ring = cuts.size() == 2;
+    Ctx::Staged rs{nullptr, nullptr, -1};
+    if (ring) {
+        rs = c.stage_upload(stage_bytes);  // may raise CAPACITY; nothing has changed yet
+    } else {
+        c.device_stage(stage_bytes);
+        c.host_stage(stage_bytes);
+    }
 
     // ---- capacity: every bucket that must grow, checked against the budget up front
     uint64_t new_cap[kMaxBuckets] = {0};
@@ -277,8 +285,8 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         const size_t coff_bytes = round_up((uint64_t)(m + 1) * 8, 256);
         const size_t ids_bytes = round_up((uint64_t)m * 4, 256);
         const size_t bytes = codes_bytes + coff_bytes + ids_bytes;
-        char *h = (char *)c.host_stage(bytes);
-        char *d = (char *)c.device_stage(bytes);
+        char *h = ring ? rs.h : (char *)c.host_stage(bytes);
+        char *d = ring ? rs.d : (char *)c.device_stage(bytes);
         uint32_t *hcodes = (uint32_t *)h;
         uint64_t *hcoff = (uint64_t *)(h + codes_bytes);
         uint32_t *hids = (uint32_t *)(h + codes_bytes + coff_bytes);
@@ -309,7 +317,10 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         GSS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_append_meta, dim3(grid_for(m)), dim3(256), 0, c.stream, B.meta, slot0, dcoff, dids, m);
         GSS_HIP(hipGetLastError());
-        c.sync();  // the staging buffers are reused by the next chunk
+        if (ring)
+            c.stage_done(rs);
+        else
+            c.stage_release();  // the next chunk's host_stage waits for this one
         slot_cursor[b] += m;
         B.n_slots = slot_cursor[b];
         B.n_lits += nl;
@@ -333,7 +344,8 @@ extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint
         GSS_REQUIRE(i == 0 || sorted[i] != sorted[i - 1], GSS_ERR_UNKNOWN_ID,
                     "clause id " + std::to_string(sorted[i]) + " repeated");
     }
-    // ---- apply
+    // ---- apply (the upload slot first: taking it may raise CAPACITY)
+    const Ctx::Staged st = c.stage_upload((size_t)n * 8);
     std::vector<uint64_t> per[kMaxBuckets];
     for (uint32_t i = 0; i < n; ++i) {
         uint64_t loc = c.id_loc[ids[i]];
@@ -348,18 +360,26 @@ extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint
         c.id_loc[ids[i]] = kNoLoc;
     }
     c.live -= n;
-    for (int b = 0; b < kMaxBuckets; ++b) {
-        if (per[b].empty()) continue;
-        Bucket &B = c.buckets[b];
-        const size_t bytes = per[b].size() * 8;
-        void *h = c.host_stage(bytes);
-        void *d = c.device_stage(bytes);
-        std::memcpy(h, per[b].data(), bytes);
-        GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
-        hipLaunchKernelGGL(k_tombstone, dim3(grid_for(per[b].size())), dim3(256), 0, c.stream, B.meta,
-                           (const uint64_t *)d, (uint32_t)per[b].size());
-        GSS_HIP(hipGetLastError());
-        c.sync();
+    {
+        // one upload of every class's slot list, one kernel per class
+        size_t total = 0;
+        for (int b = 0; b < kMaxBuckets; ++b) total += per[b].size();
+        size_t off = 0;
+        for (int b = 0; b < kMaxBuckets; ++b) {
+            std::memcpy(st.h + off * 8, per[b].data(), per[b].size() * 8);
+            off += per[b].size();
+        }
+        GSS_HIP(hipMemcpyAsync(st.d, st.h, total * 8, hipMemcpyHostToDevice, c.stream));
+        off = 0;
+        for (int b = 0; b < kMaxBuckets; ++b) {
+            if (per[b].empty()) continue;
+            Bucket &B = c.buckets[b];
+            hipLaunchKernelGGL(k_tombstone, dim3(grid_for(per[b].size())), dim3(256), 0, c.stream, B.meta,
+                               (const uint64_t *)st.d + off, (uint32_t)per[b].size());
+            GSS_HIP(hipGetLastError());
+            off += per[b].size();
+        }
+        c.stage_done(st);
     }
     c.version++;
     // ---- reclaim: compact a class once more than a quarter of its slots are dead

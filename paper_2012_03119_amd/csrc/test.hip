@@ -153,7 +153,8 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     return L;
 }
 
-static void run(Ctx &c, const Launch &L, uint32_t flags) {
+// Queues the test kernel, the finalize kernel and the copy of the summary.
+static void launch(Ctx &c, const Launch &L, uint32_t flags) {
     GSS_HIP(hipEventRecord(c.ev_start, c.stream));
     hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(kTestWavesPerBlock * 64), L.lds, c.stream, L.descs, L.args,
                        (flags & GSS_TEST_NO_EARLY_EXIT) ? 0u : 1u, (flags & GSS_TEST_DENSE) ? 1u : 0u);
@@ -164,28 +165,28 @@ static void run(Ctx &c, const Launch &L, uint32_t flags) {
                        c.d_summary);
     GSS_HIP(hipGetLastError());
     GSS_HIP(hipMemcpyAsync(c.h_summary, c.d_summary, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream));
-    c.sync();
+    GSS_HIP(hipEventRecord(c.ev_done, c.stream));
+    c.last_waves = n_waves;
+}
+
+// Waits for a launched test and records its kernel time.
+static void complete(Ctx &c) {
+    GSS_HIP(hipEventSynchronize(c.ev_done));
     float ms = 0.f;
     GSS_HIP(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
     c.stats.last_kernel_ms = ms;
     c.stats.total_kernel_ms += ms;
     c.stats.timed_launches++;
     c.stats.kernel_launches++;
-    c.last_waves = n_waves;
 }
 
-}  // namespace gss
-
-using namespace gss;
-
-extern "C" gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_reports) {
-    GSS_API_BEGIN(ctx)
-    Ctx &c = *c_;
+// Checks flags and prepares a test; returns false when there is nothing to launch.
+static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
     const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_SORTED | GSS_TEST_DENSE |
                            GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT;
     GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "unknown gss_test flag");
     GSS_REQUIRE(!(flags & GSS_TEST_SORTED), GSS_ERR_INVALID_ARG, "GSS_TEST_SORTED is not supported by this build");
-    if (out_n_reports) *out_n_reports = 0;
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is already in flight (call gss_test_wait)");
     if (flags & GSS_TEST_DENSE) {
         const uint64_t rows = std::max<uint64_t>(c.id_loc.size(), 1);
         if (rows > c.dense_rows) {
@@ -203,12 +204,23 @@ extern "C" gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_rep
     for (const auto &B : c.buckets) lits += B.n_lits;
     c.stats.last_pairs = c.live * act;
     c.stats.last_literals = lits;
-
-    Launch L = prepare(c, flags);
-    uint64_t n = 0, kept = 0;
     c.tested = false;
-    if (L.args.n_tiles > 0) {
-        run(c, L, flags);
+    L = prepare(c, flags);
+    if (L.args.n_tiles == 0) {
+        c.last_waves = 0;
+        return false;
+    }
+    launch(c, L, flags);
+    return true;
+}
+
+// Completes a test begun by begin_test: waits, grows the report segments and
+// repeats the test once if they overflowed (unless GSS_TEST_NO_REGROW), and
+// publishes the counts.  Throws GSS_ERR_REPORT_OVERFLOW when records were lost.
+static uint64_t end_test(Ctx &c, uint32_t flags, bool launched) {
+    uint64_t n = 0, kept = 0;
+    if (launched) {
+        complete(c);
         n = c.h_summary[0];
         kept = c.h_summary[2];
         const uint64_t largest = c.h_summary[1];
@@ -227,14 +239,13 @@ extern "C" gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_rep
             }
             if (grown) {
                 c.stats.regrows++;
-                L = prepare(c, flags);
-                run(c, L, flags);
+                Launch L = prepare(c, flags);
+                launch(c, L, flags);
+                complete(c);
                 n = c.h_summary[0];
                 kept = c.h_summary[2];
             }
         }
-    } else {
-        c.last_waves = 0;
     }
     c.stats.tests_run++;
     c.tested = true;
@@ -243,16 +254,81 @@ extern "C" gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_rep
     c.n_reports = n;
     c.n_kept = kept;
     c.stats.last_reports = n;
-    if (out_n_reports) *out_n_reports = n;
     GSS_REQUIRE(kept == n, GSS_ERR_REPORT_OVERFLOW,
                 "report segments of " + std::to_string(c.seg_cap) + " records kept " + std::to_string(kept) + " of " +
                     std::to_string(n) + " records");
+    return n;
+}
+
+}  // namespace gss
+
+using namespace gss;
+
+extern "C" gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_reports) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    if (out_n_reports) *out_n_reports = 0;
+    Launch L;
+    const bool launched = begin_test(c, flags, L);
+    try {
+        const uint64_t n = end_test(c, flags, launched);
+        if (out_n_reports) *out_n_reports = n;
+    } catch (const Error &e) {
+        if (out_n_reports) *out_n_reports = c.n_reports;
+        throw;
+    }
+    GSS_API_END
+}
+
+extern "C" gss_status gss_test_async(gss_ctx *ctx, uint32_t flags) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Launch L;
+    c.pending_launched = begin_test(c, flags, L);
+    c.pending = true;
+    c.pending_flags = flags;
+    GSS_API_END
+}
+
+extern "C" gss_status gss_test_wait(gss_ctx *ctx, uint64_t *out_n_reports) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    GSS_REQUIRE(c.pending, GSS_ERR_STATE, "no test in flight");
+    c.pending = false;
+    if (out_n_reports) *out_n_reports = 0;
+    try {
+        const uint64_t n = end_test(c, c.pending_flags, c.pending_launched);
+        if (out_n_reports) *out_n_reports = n;
+    } catch (const Error &e) {
+        if (out_n_reports) *out_n_reports = c.n_reports;
+        throw;
+    }
+    GSS_API_END
+}
+
+extern "C" gss_status gss_test_query(gss_ctx *ctx, int *done) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    GSS_REQUIRE(done != nullptr, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE(c.pending, GSS_ERR_STATE, "no test in flight");
+    if (!c.pending_launched) {
+        *done = 1;
+    } else {
+        const hipError_t e = hipEventQuery(c.ev_done);
+        if (e == hipErrorNotReady) {
+            *done = 0;
+        } else {
+            GSS_HIP(e);
+            *done = 1;
+        }
+    }
     GSS_API_END
 }
 
 extern "C" gss_status gss_fetch_reports(gss_ctx *ctx, gss_report *out, uint64_t cap, uint64_t *out_n) {
     GSS_API_BEGIN(ctx)
     Ctx &c = *c_;
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight (call gss_test_wait)");
     GSS_REQUIRE(c.tested, GSS_ERR_STATE, "no test has run yet");
     GSS_REQUIRE(out_n != nullptr, GSS_ERR_INVALID_ARG, "null argument");
     const uint64_t n = std::min(c.n_kept, cap);

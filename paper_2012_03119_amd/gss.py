@@ -119,6 +119,11 @@ def load_library(path: Optional[str] = None):
         "gss_get_stats": ([P, ctypes.POINTER(gss_stats)], ctypes.c_int32),
         "gss_reset_stats": ([P], ctypes.c_int32),
         "gss_get_stream": ([P, ctypes.POINTER(P)], ctypes.c_int32),
+        "gss_update_words": ([P, u32, u32, P, P, P], ctypes.c_int32),
+        "gss_set_active": ([P, P], ctypes.c_int32),
+        "gss_test_async": ([P, u32], ctypes.c_int32),
+        "gss_test_query": ([P, P], ctypes.c_int32),
+        "gss_test_wait": ([P, P], ctypes.c_int32),
         "gss_batch_create": ([P, u32, ctypes.POINTER(P)], ctypes.c_int32),
         "gss_batch_destroy": ([P], None),
         "gss_batch_last_error": ([P], ctypes.c_char_p),
@@ -216,6 +221,37 @@ def gss_set_var_values(ctx, first_slot: int, vars_, values) -> None:
     ptr, keep, _ = _data_ptr(values, np.int8)
     _check(ctx, load_library().gss_set_var_values(ctx, first_slot, n_slots, len(vars_), _np_ptr(vars_), ptr))
     del keep
+
+
+def gss_update_words(ctx, word: int, vars_, f_words, t_words) -> None:
+    """Packed delta of one 64-slot word: f/t words per listed variable."""
+    vars_ = np.ascontiguousarray(vars_, dtype=np.uint32)
+    f = np.ascontiguousarray(f_words, dtype=np.uint64)
+    t = np.ascontiguousarray(t_words, dtype=np.uint64)
+    if not (len(vars_) == len(f) == len(t)):
+        raise ValueError("vars, f_words and t_words differ in length")
+    _check(ctx, load_library().gss_update_words(ctx, word, len(vars_), _np_ptr(vars_), _np_ptr(f), _np_ptr(t)))
+
+
+def gss_set_active(ctx, active) -> None:
+    a = np.ascontiguousarray(active, dtype=np.uint64)
+    _check(ctx, load_library().gss_set_active(ctx, _np_ptr(a)))
+
+
+def gss_test_async(ctx, flags: int = 0) -> None:
+    _check(ctx, load_library().gss_test_async(ctx, flags))
+
+
+def gss_test_query(ctx) -> bool:
+    d = ctypes.c_int()
+    _check(ctx, load_library().gss_test_query(ctx, ctypes.byref(d)))
+    return bool(d.value)
+
+
+def gss_test_wait(ctx) -> int:
+    n = ctypes.c_uint64()
+    _check(ctx, load_library().gss_test_wait(ctx, ctypes.byref(n)))
+    return n.value
 
 
 def gss_clear_slots(ctx, first_slot: int, n_slots: int) -> None:
@@ -386,6 +422,21 @@ class Context:
 
     def clear_slots(self, first_slot: int, n_slots: int) -> None:
         gss_clear_slots(self.ctx, first_slot, n_slots)
+
+    def update_words(self, word: int, vars_, f_words, t_words) -> None:
+        gss_update_words(self.ctx, word, vars_, f_words, t_words)
+
+    def set_active(self, active) -> None:
+        gss_set_active(self.ctx, active)
+
+    def test_async(self, flags: int = 0) -> None:
+        gss_test_async(self.ctx, flags)
+
+    def test_query(self) -> bool:
+        return gss_test_query(self.ctx)
+
+    def test_wait(self) -> int:
+        return gss_test_wait(self.ctx)
 
     def test(self, flags: int = 0) -> int:
         return gss_test(self.ctx, flags)

@@ -340,3 +340,52 @@ def test_invalid_device_values_apply_nothing():
             ctx.set_var_values(0, vs, badd)
         assert e.value.code == gss.GSS_ERR_INVALID_ARG
         _check(gpu_dense(ctx, w.n_clauses), before)
+
+
+def _pack_word(vals_64):
+    """[64][n_vars] int8 -> (f, t) uint64 per variable (test-side packing)."""
+    bits = (np.uint64(1) << np.arange(64, dtype=np.uint64))[:, None]
+    f = ((vals_64 == -1).astype(np.uint64) * bits).sum(axis=0, dtype=np.uint64)
+    t = ((vals_64 == 1).astype(np.uint64) * bits).sum(axis=0, dtype=np.uint64)
+    return f, t
+
+
+def test_update_words_and_active_sets():
+    w = gen.tiny(10)
+    rng = np.random.default_rng(3)
+    vals = np.concatenate([w.values, w.values[::-1]])          # 128 slots
+    with new_context(w.n_vars, 128) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, vals)
+        vs = np.sort(rng.choice(w.n_vars, 300, replace=False)) + 1
+        new = rng.integers(-1, 2, size=(64, 300)).astype(np.int8)
+        f, t = _pack_word(new)
+        ctx.update_words(1, vs, f, t)
+        vals[64:128, vs - 1] = new
+        for act in ([~0, 0], [0, ~0], [0x00FF00FF00FF00FF, 0xF0F0F0F0F0F0F0F0], [~0, ~0]):
+            a = np.array([x & (2 ** 64 - 1) for x in act], dtype=np.uint64)
+            ctx.set_active(a)
+            active = np.array([(int(a[s // 64]) >> (s % 64)) & 1 for s in range(128)], dtype=bool)
+            _check(gpu_dense(ctx, w.n_clauses), oracle_dense(w.lits, w.offsets, vals, active))
+        with pytest.raises(gss.GssError) as e:
+            ctx.update_words(0, vs[:1], np.array([1], np.uint64), np.array([1], np.uint64))  # F and T
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+
+
+def test_async_test():
+    w = gen.tiny(11)
+    with new_context(w.n_vars, 64) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, w.values)
+        ctx.test_async()
+        with pytest.raises(gss.GssError) as e:
+            ctx.fetch_reports(10)
+        assert e.value.code == gss.GSS_ERR_STATE
+        with pytest.raises(gss.GssError) as e:
+            ctx.test_async()
+        assert e.value.code == gss.GSS_ERR_STATE
+        while not ctx.test_query():
+            pass
+        n = ctx.test_wait()
+        got = reports_to_dense(ctx.fetch_reports(n), w.n_clauses, 1)
+    _check(got, oracle.masks(w.lits, w.offsets, w.values))
