@@ -77,7 +77,7 @@ typedef struct gss_config {
     uint32_t max_slots;         /* assignment capacity: multiple of 64, 64..4096 (W = max_slots/64 words) */
     uint64_t hbm_budget_bytes;  /* cap on the context's device memory; 0 = no cap */
     uint64_t report_capacity;   /* initial report buffer entries, split evenly over the test kernel's
-                                   wavefronts (at least 64 each); grown by gss_test unless GSS_TEST_NO_REGROW */
+                                   wavefronts (at least 16 each); grown by gss_test unless GSS_TEST_NO_REGROW */
     void *stream;               /* borrowed hipStream_t; NULL = the context creates its own */
     gss_dev_alloc_fn dev_alloc; /* optional, see above */
     gss_dev_free_fn dev_free;
@@ -176,8 +176,12 @@ gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_reports);
  * prepare the next run meanwhile (calls that change the store or the planes are
  * queued behind the test on the context's stream).  gss_test_query sets *done
  * once the results are in; gss_test_wait waits, then behaves as the end of
- * gss_test (overflow handling included).  Only one test may be in flight;
- * gss_fetch_reports before gss_test_wait is GSS_ERR_STATE. */
+ * gss_test, with one difference: when the report segments overflowed and a call
+ * changed the store, the planes or the active set after gss_test_async, the
+ * segments are grown but the test is not repeated (a rerun would see the new
+ * state): GSS_ERR_REPORT_OVERFLOW, with the exact count in *out_n_reports.  Only
+ * one test may be in flight; gss_fetch_reports before gss_test_wait is
+ * GSS_ERR_STATE. */
 gss_status gss_test_async(gss_ctx *ctx, uint32_t flags);
 gss_status gss_test_query(gss_ctx *ctx, int *done);
 gss_status gss_test_wait(gss_ctx *ctx, uint64_t *out_n_reports);
@@ -262,6 +266,122 @@ gss_status gss_batch_test(gss_batch *batch, uint32_t flags, uint64_t *out_n_repo
  * launches and graph captures so far, and the tiles of the last plan. */
 gss_status gss_batch_info(const gss_batch *batch, double *last_ms, uint64_t *launches, uint64_t *captures,
                           uint64_t *tiles);
+
+/* ---- Served test: a manager thread fed by solver threads ----
+ *
+ * Section 5 has one CPU thread besides the solver threads manage the GPU; per
+ * Section 3.6 the solver threads send it their assignments and export their
+ * learned clauses, and learn which clauses fire on their assignments.  A server
+ * owns a context and runs that manager in a native thread:
+ *
+ *  - producer p (0 <= p < n_producers <= W) owns the 64 slots of word p: each
+ *    gss_server_send is one snapshot of its 64 assignments, given as a packed
+ *    delta to its previous snapshot (as gss_update_words).  Deltas that arrive
+ *    while a run is on the GPU are merged and uploaded on a copy stream while
+ *    that run still executes; the next run tests every word with a new snapshot
+ *    (continuous batching).  A snapshot superseded before a run took it is
+ *    dropped, as the paper drops assignments the GPU cannot take.
+ *  - gss_server_insert queues learned clauses; they are admitted between runs
+ *    within the context's HBM budget (held back while it is full).
+ *  - a fraction of the live clauses is removed each second at random (the
+ *    simulated clause-database reduction of the solvers).
+ *  - the records of each run are routed by word to their producer, who collects
+ *    them with gss_server_poll.  Notify latency: from the send of the snapshot a
+ *    run tested until its records are in the producer's queue.
+ *
+ * While a server runs, its context must not be used directly.  send, insert and
+ * poll are thread-safe. */
+typedef struct gss_server gss_server;
+
+typedef struct gss_server_config {
+    uint32_t n_producers;     /* 1..W (max_slots / 64) */
+    uint32_t test_flags;      /* flags of every run: GSS_TEST_TRIGGER, GSS_TEST_NO_EARLY_EXIT, GSS_TEST_NO_HOT */
+    double delete_fraction;   /* fraction of the live clauses removed per second (0 = none) */
+    uint64_t seed;            /* of the removals */
+    const char *log_path;     /* NULL, or a text file receiving every change, run and record in the
+                                 order the device applies them (for replay against a reference) */
+    uint64_t max_queued_lits; /* inserts waiting for admission, in literals (0 = 1 << 26); beyond: refused */
+    uint64_t reserved[3];
+} gss_server_config;
+
+typedef struct gss_serve_result {
+    uint64_t snapshots;       /* gss_server_send calls */
+    uint64_t tested;          /* snapshots whose records reached their producer */
+    uint64_t dropped;         /* snapshots superseded before a run took them */
+    uint64_t runs;            /* test runs completed */
+    uint64_t overflowed_runs; /* runs whose records overflowed (their words are tested again) */
+    uint64_t inserted;        /* clauses admitted */
+    uint64_t refused;         /* clauses refused (insert queue full) */
+    uint64_t deleted;         /* clauses removed */
+    uint64_t reports;         /* records routed to producers */
+    uint64_t pairs;           /* clause x assignment tests: live clauses x active slots, summed over runs */
+    uint64_t live_end;        /* live clauses at the end */
+    uint64_t device_bytes_end;
+    uint64_t delta_bytes;     /* bytes of deltas uploaded */
+    double wall_s;            /* from start to stop */
+    double gpu_ms;            /* test kernel time, summed over runs */
+    double mean_ms, p50_ms, p99_ms, max_ms; /* notify latency */
+    /* manager thread time by phase, summed over the session (ms): taking and
+     * uploading deltas, waiting for runs, fetching records, routing them,
+     * inserts and removals, launching runs */
+    double admit_ms, wait_ms, fetch_ms, route_ms, store_ms, launch_ms;
+} gss_serve_result;
+
+/* Starts the manager thread on ctx (no test may be in flight).  Allocates two
+ * pinned host and device delta buffers of num_vars entries per producer. */
+gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cfg, gss_server **out);
+
+/* A snapshot of producer p: n_vars entries (vars 1..num_vars; f_words[i] and
+ * t_words[i] disjoint, as gss_update_words; a variable listed twice takes its
+ * last entry).  Host arrays, copied before returning. */
+gss_status gss_server_send(gss_server *srv, uint32_t producer, uint32_t n_vars, const uint32_t *vars,
+                           const uint64_t *f_words, const uint64_t *t_words);
+
+/* Queues n learned clauses of producer p (layout of gss_add_clauses; copied).
+ * GSS_ERR_CAPACITY when the admission queue is full (nothing queued). */
+gss_status gss_server_insert(gss_server *srv, uint32_t producer, const int32_t *lits, const uint64_t *offsets,
+                             uint32_t n);
+
+/* Moves up to cap of producer p's pending records into out (host) and sets
+ * *out_n; out NULL discards them all (*out_n = the number discarded).  *out_run
+ * (may be NULL) receives the last run whose records were routed to p (or
+ * UINT64_MAX if none). */
+gss_status gss_server_poll(gss_server *srv, uint32_t producer, gss_report *out, uint64_t cap, uint64_t *out_n,
+                           uint64_t *out_run);
+
+/* Stops the manager (the run in flight is completed and routed), fills *out (may
+ * be NULL) and releases the server; the context is usable again.  Errors met by
+ * the manager thread are returned here. */
+gss_status gss_server_stop(gss_server *srv, gss_serve_result *out);
+
+/* Message of the server's last error ("" if none). */
+const char *gss_server_last_error(const gss_server *srv);
+
+/* ---- Served workload generator ----
+ *
+ * Runs a server on ctx for duration_s with n_threads simulated solver threads.
+ * Thread i owns word i.  It sends a full snapshot at start, then a Poisson stream
+ * of snapshots at snapshot_rate per second, each redrawing redraw_fraction of
+ * the variables (in runs of 64 consecutive variables); every variable of a
+ * snapshot takes a subset of {T, F, U} with the frequencies of Table 1, then
+ * each of its 64 slots a value drawn uniformly from that subset.  It inserts
+ * insert_rate clauses per second (lengths: half in 2..10, 40% in 11..50, 10% in
+ * 51..300; distinct variables, uniform signs) and discards its records.  Seeded:
+ * the drawn values are reproducible, their timing is not. */
+typedef struct gss_sim_config {
+    uint32_t n_threads;
+    uint32_t test_flags;
+    double duration_s;
+    double snapshot_rate;
+    double redraw_fraction;
+    double insert_rate;
+    double delete_fraction;
+    uint64_t seed;
+    const char *log_path;
+    uint64_t reserved[4];
+} gss_sim_config;
+
+gss_status gss_serve_simulate(gss_ctx *ctx, const gss_sim_config *cfg, gss_serve_result *out);
 
 #ifdef __cplusplus
 }

@@ -173,6 +173,8 @@ struct Ctx {
     bool pending_launched = false;
     uint32_t pending_flags = 0;
     bool stage_pending = false;
+    uint64_t mutations = 0;         // calls that changed the store, the planes or the active set
+    uint64_t launch_mutations = 0;  // the same counter when the last test was launched
     gss_stats stats{};
     std::string last_error;
 
@@ -215,6 +217,8 @@ void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value);
 bool is_device_pointer(const void *p);
 const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n);
 void check_flag(Ctx &c);
+// queues new plane words of n variables of one 64-slot word (device arrays, checked by the caller)
+void launch_set_words(Ctx &c, uint32_t word, const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n);
 
 // Wrapper of every ABI entry point taking a context: converts exceptions into
 // status codes and records the message for gss_last_error.

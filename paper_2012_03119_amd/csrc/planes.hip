@@ -116,6 +116,14 @@ __global__ void k_clear_slots(uint64_t *planes, uint32_t RW, uint64_t n_rows, ui
     }
 }
 
+void launch_set_words(Ctx &c, uint32_t word, const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n) {
+    if (n == 0) return;
+    const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, word, vars, f, t, n);
+    GSS_HIP(hipGetLastError());
+    c.mutations++;
+}
+
 static uint64_t slot_mask(uint32_t first, uint32_t n, uint32_t w) {
     const uint32_t a = std::max(first, 64 * w), b = std::min(first + n, 64 * w + 64);
     if (b <= a) return 0;
@@ -161,6 +169,7 @@ using namespace gss;
 
 extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, const int8_t *values) {
     GSS_API_BEGIN(ctx)
+    c_->mutations++;  // a test in flight no longer sees the current state
     Ctx &c = *c_;
     if (n_slots == 0) return GSS_OK;
     GSS_REQUIRE(values != nullptr, GSS_ERR_INVALID_ARG, "null argument");
@@ -195,6 +204,7 @@ extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uin
 extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, uint32_t n_vars,
                                          const uint32_t *vars, const int8_t *values) {
     GSS_API_BEGIN(ctx)
+    c_->mutations++;  // a test in flight no longer sees the current state
     Ctx &c = *c_;
     if (n_slots == 0 || n_vars == 0) return GSS_OK;
     GSS_REQUIRE(vars && values, GSS_ERR_INVALID_ARG, "null argument");
@@ -232,6 +242,7 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
 
 extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots) {
     GSS_API_BEGIN(ctx)
+    c_->mutations++;  // a test in flight no longer sees the current state
     Ctx &c = *c_;
     if (n_slots == 0) return GSS_OK;
     GSS_REQUIRE((uint64_t)first_slot + n_slots <= c.cfg.max_slots, GSS_ERR_CAPACITY, "slot range beyond max_slots");
@@ -250,6 +261,7 @@ extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_
 extern "C" gss_status gss_update_words(gss_ctx *ctx, uint32_t word, uint32_t n_vars, const uint32_t *vars,
                                        const uint64_t *f_words, const uint64_t *t_words) {
     GSS_API_BEGIN(ctx)
+    c_->mutations++;  // a test in flight no longer sees the current state
     Ctx &c = *c_;
     if (n_vars == 0) return GSS_OK;
     GSS_REQUIRE(vars && f_words && t_words, GSS_ERR_INVALID_ARG, "null argument");
@@ -264,16 +276,14 @@ extern "C" gss_status gss_update_words(gss_ctx *ctx, uint32_t word, uint32_t n_v
     std::memcpy(h + vb, f_words, (size_t)n_vars * 8);
     std::memcpy(h + vb + wb, t_words, (size_t)n_vars * 8);
     GSS_HIP(hipMemcpyAsync(d, h, vb + 2 * wb, hipMemcpyHostToDevice, c.stream));
-    const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>((n_vars + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, word, (const uint32_t *)d,
-                       (const uint64_t *)(d + vb), (const uint64_t *)(d + vb + wb), n_vars);
-    GSS_HIP(hipGetLastError());
+    launch_set_words(c, word, (const uint32_t *)d, (const uint64_t *)(d + vb), (const uint64_t *)(d + vb + wb), n_vars);
     c.stage_done(st);
     GSS_API_END
 }
 
 extern "C" gss_status gss_set_active(gss_ctx *ctx, const uint64_t *active) {
     GSS_API_BEGIN(ctx)
+    c_->mutations++;  // a test in flight no longer sees the current state
     Ctx &c = *c_;
     GSS_REQUIRE(active != nullptr, GSS_ERR_INVALID_ARG, "null argument");
     std::memcpy(c.h_active.data(), active, c.W * 8);

@@ -1,0 +1,633 @@
+// Served clause test: a GPU-manager thread fed by solver threads.
+//
+// Section 5 of the paper runs one CPU thread besides the solver threads to drive
+// the GPU; Section 3.6 has the solvers send it their assignments and export their
+// learned clauses, and get back the clauses that fire.  Here producer p owns the
+// 64 slots of word p and sends snapshots of its 64 assignments as packed deltas.
+//
+// Data path of one snapshot:
+//   producer thread: merges the delta into its open mailbox (pinned host memory;
+//     a variable sent twice keeps its last value)
+//   manager: takes the mailbox (swapping in a free one), copies it to the device
+//     on a copy stream while the current run still executes, and queues the
+//     plane update on the context stream behind that run
+//   next run: tests every word with a new snapshot; its records are routed by
+//     word to the producers' queues, which is when the snapshot is notified.
+//
+// Runs are launched back to back (continuous batching): while run k executes,
+// the manager admits snapshots, inserts and removals for run k+1.
+#include "gss_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+namespace gss {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// Staged delta of one word: vars[cap] | f[cap] | t[cap] in pinned host memory,
+// mirrored by a device buffer of the same layout for the plane update kernel.
+struct Mail {
+    char *h = nullptr;
+    uint32_t cap = 0;
+    uint32_t n = 0;
+    char *d = nullptr;
+    uint32_t dcap = 0;
+    hipEvent_t done = nullptr;  // recorded after the kernel that read d
+    bool busy = false;
+
+    static size_t vbytes(uint32_t cap) { return ((size_t)cap * 4 + 255) / 256 * 256; }
+    static size_t bytes(uint32_t cap) { return vbytes(cap) + (size_t)cap * 16; }
+    uint32_t *vars() const { return (uint32_t *)h; }
+    uint64_t *f() const { return (uint64_t *)(h + vbytes(cap)); }
+    uint64_t *t() const { return (uint64_t *)(h + vbytes(cap)) + cap; }
+};
+
+constexpr int kMails = 3;  // the open one, and up to two queued behind runs
+
+struct Producer {
+    std::mutex mu;
+    Mail mail[kMails];
+    int open = 0;
+    std::vector<uint32_t> pos;  // variable -> its index in the open mailbox (checked against vars[])
+    uint64_t snaps = 0;         // snapshots merged into the open mailbox
+    double arrival = -1.0;      // send time of the newest of them
+
+    std::mutex omu;
+    std::vector<gss_report> outbox;
+    uint64_t last_run = UINT64_MAX;
+};
+
+double percentile(std::vector<double> v, double p) {
+    if (v.empty()) return 0.0;
+    const size_t k = std::min(v.size() - 1, (size_t)std::llround(p * (double)(v.size() - 1)));
+    std::nth_element(v.begin(), v.begin() + (ptrdiff_t)k, v.end());
+    return v[k];
+}
+
+// Splitmix64 step: the random removals.
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Grows a producer's open mailbox (not queued, so its memory is free to move).
+void ensure_host(Mail &m, uint32_t need, uint32_t limit) {
+    if (need <= m.cap) return;
+    uint32_t cap = (uint32_t)std::max<uint64_t>(need, std::min<uint64_t>(limit, 2ull * m.cap));
+    cap = std::min(cap, limit);
+    char *h = nullptr;
+    if (hipHostMalloc((void **)&h, Mail::bytes(cap), hipHostMallocDefault) != hipSuccess)
+        throw Error(GSS_ERR_DEVICE, "hipHostMalloc failed for a delta mailbox");
+    Mail old = m;
+    m.h = h;
+    m.cap = cap;
+    if (old.h) {
+        std::memcpy(m.vars(), old.vars(), (size_t)m.n * 4);
+        std::memcpy(m.f(), old.f(), (size_t)m.n * 8);
+        std::memcpy(m.t(), old.t(), (size_t)m.n * 8);
+        (void)hipHostFree(old.h);
+    }
+}
+
+}  // namespace
+}  // namespace gss
+
+using namespace gss;
+
+struct gss_server {
+    Ctx *c = nullptr;
+    gss_server_config cfg{};
+    uint32_t V = 0, P = 0;
+    Clock::time_point t0;
+    std::vector<Producer> prod;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_copied = nullptr;
+    FILE *log = nullptr;
+
+    // inserts waiting for admission
+    std::mutex imu;
+    std::vector<int32_t> q_lits;
+    std::vector<uint64_t> q_off{0};
+    uint64_t q_limit = 0;
+
+    std::atomic<bool> stop{false};
+    std::atomic<bool> failed{false};
+    std::thread manager;
+    gss_status status = GSS_OK;
+    std::string error;
+    mutable std::mutex emu;
+
+    std::atomic<uint64_t> n_snapshots{0}, n_refused{0};
+    gss_serve_result res{};
+    std::vector<double> lat;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    void fail(gss_status code, const std::string &msg) {
+        std::lock_guard<std::mutex> g(emu);
+        if (status == GSS_OK) {
+            status = code;
+            error = msg;
+        }
+        failed = true;
+    }
+    void run();
+};
+
+void gss_server::run() {
+    Ctx &C = *c;
+    gss_ctx *ctx = reinterpret_cast<gss_ctx *>(c);
+    std::vector<uint32_t> live;  // ids of live clauses, for random removal
+    live.reserve(C.live + 1024);
+    for (uint64_t id = 0; id < C.id_loc.size(); ++id)
+        if (C.id_loc[id] != kNoLoc) live.push_back((uint32_t)id);
+    uint64_t rng = cfg.seed * 0x2545F4914F6CDD1Dull + 11;
+    std::vector<double> staged(P, -1.0), inflight(P, -1.0);  // arrival of the untested / tested snapshot
+    std::vector<std::vector<gss_report>> route(P);
+    std::vector<gss_report> rec;
+    std::vector<uint64_t> act(C.W, 0);
+    struct Taken {
+        uint32_t p;
+        Mail *m;
+    };
+    std::vector<Taken> taken;
+    std::vector<int32_t> ins_lits;
+    std::vector<uint64_t> ins_off{0};
+    std::vector<uint32_t> ids;
+    bool held = false;  // inserts held back by the HBM budget until something is removed
+    bool pending = false;
+    uint64_t run_id = 0;
+    double del_due = 0.0, last = now();
+    const double kernel_ms0 = C.stats.total_kernel_ms;
+    auto timed = [&](double &acc, auto &&fn) {
+        const double a = now();
+        fn();
+        acc += (now() - a) * 1e3;
+    };
+
+    auto admit = [&]() {
+        // ---- snapshots: take every producer's open mailbox that holds any
+        taken.clear();
+        for (uint32_t p = 0; p < P; ++p) {
+            Producer &pr = prod[p];
+            Mail *m = nullptr;
+            uint64_t snaps = 0;
+            double arrival = -1.0;
+            {
+                std::lock_guard<std::mutex> g(pr.mu);
+                if (pr.snaps == 0) continue;
+                int free_k = -1;
+                for (int k = 0; k < kMails && free_k < 0; ++k) {
+                    if (k == pr.open) continue;
+                    Mail &x = pr.mail[k];
+                    if (x.busy) {
+                        const hipError_t e = hipEventQuery(x.done);
+                        if (e == hipErrorNotReady) continue;
+                        GSS_HIP(e);
+                        x.busy = false;
+                    }
+                    free_k = k;
+                }
+                if (free_k < 0) continue;  // both queued: keep merging into the open one
+                m = &pr.mail[pr.open];
+                pr.open = free_k;
+                pr.mail[free_k].n = 0;
+                snaps = pr.snaps;
+                arrival = pr.arrival;
+                pr.snaps = 0;
+            }
+            res.dropped += snaps - 1 + (staged[p] >= 0 ? 1 : 0);
+            staged[p] = arrival;
+            if (m->n == 0) continue;
+            if (m->n > m->dcap) {  // the device mirror is idle: the mailbox was open
+                C.dfree(m->d);
+                m->d = nullptr;
+                m->dcap = 0;
+                m->d = (char *)C.dalloc(Mail::bytes(m->cap));
+                m->dcap = m->cap;
+            }
+            const size_t vb = Mail::vbytes(m->dcap);
+            GSS_HIP(hipMemcpyAsync(m->d, m->h, (size_t)m->n * 4, hipMemcpyHostToDevice, copy_stream));
+            GSS_HIP(hipMemcpyAsync(m->d + vb, m->f(), (size_t)m->n * 8, hipMemcpyHostToDevice, copy_stream));
+            GSS_HIP(hipMemcpyAsync(m->d + vb + (size_t)m->dcap * 8, m->t(), (size_t)m->n * 8, hipMemcpyHostToDevice,
+                                   copy_stream));
+            res.delta_bytes += (uint64_t)m->n * 20;
+            m->busy = true;
+            taken.push_back({p, m});
+        }
+        if (!taken.empty()) {
+            // the plane updates wait for the copies, and run after the test in flight
+            GSS_HIP(hipEventRecord(ev_copied, copy_stream));
+            GSS_HIP(hipStreamWaitEvent(C.stream, ev_copied, 0));
+            for (const Taken &x : taken) {
+                Mail &m = *x.m;
+                const size_t vb = Mail::vbytes(m.dcap);
+                launch_set_words(C, x.p, (const uint32_t *)m.d, (const uint64_t *)(m.d + vb),
+                                 (const uint64_t *)(m.d + vb) + m.dcap, m.n);
+                GSS_HIP(hipEventRecord(m.done, C.stream));
+                if (log) {
+                    std::fprintf(log, "W %u %u\n", x.p, m.n);
+                    const uint32_t *v = m.vars();
+                    const uint64_t *f = m.f(), *t = m.t();
+                    for (uint32_t i = 0; i < m.n; ++i)
+                        std::fprintf(log, "%u %llx %llx\n", v[i], (unsigned long long)f[i], (unsigned long long)t[i]);
+                }
+            }
+        }
+    };
+
+    // Store changes are queued once per run, behind the run just launched, so
+    // their host work overlaps it (and the upload ring is not drained).
+    auto change_store = [&]() {
+        // ---- removals: a fraction of the live clauses per second
+        const double t = now();
+        del_due += cfg.delete_fraction * (double)live.size() * std::max(0.0, t - last);
+        last = t;
+        const uint32_t n_del = (uint32_t)std::min<double>(std::floor(del_due), (double)live.size());
+        if (n_del) {
+            del_due -= n_del;
+            ids.resize(n_del);
+            for (uint32_t i = 0; i < n_del; ++i) {
+                const uint64_t k = splitmix(rng) % live.size();
+                ids[i] = live[k];
+                live[k] = live.back();
+                live.pop_back();
+            }
+            const gss_status rc = gss_remove_clauses(ctx, ids.data(), n_del);
+            if (rc != GSS_OK) throw Error(rc, C.last_error);
+            res.deleted += n_del;
+            held = false;
+            if (log) {
+                std::fprintf(log, "R %u", n_del);
+                for (uint32_t id : ids) std::fprintf(log, " %u", id);
+                std::fputc('\n', log);
+            }
+        }
+        // ---- inserts, admitted within the HBM budget
+        if (!held) {
+            {
+                std::lock_guard<std::mutex> g(imu);
+                ins_lits.swap(q_lits);
+                ins_off.swap(q_off);
+                q_lits.clear();
+                q_off.assign(1, 0);
+            }
+            const uint32_t n = (uint32_t)ins_off.size() - 1;
+            if (n) {
+                ids.resize(n);
+                const gss_status rc = gss_add_clauses(ctx, ins_lits.data(), ins_off.data(), n, ids.data());
+                if (rc == GSS_OK) {
+                    res.inserted += n;
+                    live.insert(live.end(), ids.begin(), ids.end());
+                    if (log)
+                        for (uint32_t i = 0; i < n; ++i) {
+                            std::fprintf(log, "A %u %llu", ids[i], (unsigned long long)(ins_off[i + 1] - ins_off[i]));
+                            for (uint64_t k = ins_off[i]; k < ins_off[i + 1]; ++k) std::fprintf(log, " %d", ins_lits[k]);
+                            std::fputc('\n', log);
+                        }
+                } else if (rc == GSS_ERR_CAPACITY) {
+                    // budget full: back in front of what arrived since, until a removal
+                    held = true;
+                    std::lock_guard<std::mutex> g(imu);
+                    const uint64_t base = ins_lits.size();
+                    ins_lits.insert(ins_lits.end(), q_lits.begin(), q_lits.end());
+                    for (size_t k = 1; k < q_off.size(); ++k) ins_off.push_back(base + q_off[k]);
+                    q_lits.swap(ins_lits);
+                    q_off.swap(ins_off);
+                } else {
+                    throw Error(rc, C.last_error);
+                }
+                ins_lits.clear();
+                ins_off.assign(1, 0);
+            }
+        }
+    };
+
+    auto finish = [&]() {
+        uint64_t n = 0;
+        gss_status rc = GSS_OK;
+        timed(res.wait_ms, [&] { rc = gss_test_wait(ctx, &n); });
+        pending = false;
+        const bool overflow = rc == GSS_ERR_REPORT_OVERFLOW;
+        if (rc != GSS_OK && !overflow) throw Error(rc, C.last_error);
+        const uint64_t this_run = run_id - 1;
+        res.runs++;
+        if (overflow) {
+            // records were lost (the segments are grown now): the words are tested
+            // again, with a newer snapshot where one is staged
+            res.overflowed_runs++;
+            if (log) std::fprintf(log, "X %llu %llu\n", (unsigned long long)this_run, (unsigned long long)n);
+            for (uint32_t p = 0; p < P; ++p)
+                if (inflight[p] >= 0) {
+                    if (staged[p] < 0)
+                        staged[p] = inflight[p];
+                    else
+                        res.dropped++;
+                    inflight[p] = -1.0;
+                }
+            return;
+        }
+        rec.resize(std::max<uint64_t>(n, 1));
+        uint64_t got = 0;
+        gss_status rf = GSS_OK;
+        timed(res.fetch_ms, [&] { rf = gss_fetch_reports(ctx, rec.data(), n, &got); });
+        if (rf != GSS_OK) throw Error(rf, C.last_error);
+        const double route_t0 = now();
+        for (auto &r : route) r.clear();
+        for (uint64_t i = 0; i < got; ++i) route[rec[i].word].push_back(rec[i]);
+        if (log) {
+            for (uint64_t i = 0; i < got; ++i)
+                std::fprintf(log, "P %llu %u %u %llx\n", (unsigned long long)this_run, rec[i].clause_id, rec[i].word,
+                             (unsigned long long)rec[i].mask);
+            std::fprintf(log, "E %llu %llu\n", (unsigned long long)this_run, (unsigned long long)got);
+        }
+        const double t = now();
+        for (uint32_t p = 0; p < P; ++p) {
+            if (inflight[p] < 0) continue;
+            {
+                Producer &pr = prod[p];
+                std::lock_guard<std::mutex> g(pr.omu);
+                if (pr.outbox.empty())
+                    pr.outbox.swap(route[p]);
+                else
+                    pr.outbox.insert(pr.outbox.end(), route[p].begin(), route[p].end());
+                pr.last_run = this_run;
+            }
+            lat.push_back((t - inflight[p]) * 1e3);
+            res.tested++;
+            inflight[p] = -1.0;
+        }
+        res.reports += got;
+        res.route_ms += (now() - route_t0) * 1e3;
+    };
+
+    try {
+        GSS_HIP(hipSetDevice(C.device));
+        double last_change = now();
+        for (;;) {
+            const bool stopping = stop.load();
+            if (!stopping) timed(res.admit_ms, admit);
+            if (pending) {
+                int done = 0;
+                const gss_status rq = gss_test_query(ctx, &done);
+                if (rq != GSS_OK) throw Error(rq, C.last_error);
+                if (!done && !stopping) {
+                    std::this_thread::sleep_for(std::chrono::microseconds(20));
+                    continue;
+                }
+                finish();
+            }
+            if (stopping) break;
+            // ---- next run: every word with an untested snapshot
+            uint32_t n_act = 0;
+            std::fill(act.begin(), act.end(), 0);
+            for (uint32_t p = 0; p < P; ++p)
+                if (staged[p] >= 0) {
+                    act[p] = ~0ull;
+                    inflight[p] = staged[p];
+                    staged[p] = -1.0;
+                    ++n_act;
+                }
+            if (!n_act) {
+                if (now() - last_change > 0.005) {
+                    timed(res.store_ms, change_store);
+                    last_change = now();
+                }
+                std::this_thread::sleep_for(std::chrono::microseconds(50));
+                continue;
+            }
+            const double launch_t0 = now();
+            gss_status rc = gss_set_active(ctx, act.data());
+            if (rc != GSS_OK) throw Error(rc, C.last_error);
+            if (log) {
+                std::fprintf(log, "T %llu", (unsigned long long)run_id);
+                for (uint64_t x : act) std::fprintf(log, " %llx", (unsigned long long)x);
+                std::fputc('\n', log);
+            }
+            res.pairs += C.live * 64ull * n_act;
+            rc = gss_test_async(ctx, cfg.test_flags);
+            if (rc != GSS_OK) throw Error(rc, C.last_error);
+            pending = true;
+            run_id++;
+            res.launch_ms += (now() - launch_t0) * 1e3;
+            timed(res.store_ms, change_store);
+            last_change = now();
+        }
+    } catch (const Error &e) {
+        fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        fail(GSS_ERR_CAPACITY, "host out of memory");
+    } catch (const std::exception &e) {
+        fail(GSS_ERR_DEVICE, e.what());
+    }
+    if (pending) {  // an error left a run in flight: complete it so the context is usable
+        uint64_t n = 0;
+        (void)gss_test_wait(ctx, &n);
+    }
+    (void)hipStreamSynchronize(C.stream);
+    res.gpu_ms = C.stats.total_kernel_ms - kernel_ms0;
+}
+
+extern "C" gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cfg, gss_server **out) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    GSS_REQUIRE(cfg && out, GSS_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    GSS_REQUIRE(cfg->n_producers >= 1 && cfg->n_producers <= c.W, GSS_ERR_INVALID_ARG,
+                "n_producers must be in 1..max_slots/64 (one 64-slot word each)");
+    const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_HOT;
+    GSS_REQUIRE((cfg->test_flags & ~known) == 0, GSS_ERR_INVALID_ARG, "test flag not allowed for served runs");
+    GSS_REQUIRE(cfg->delete_fraction >= 0 && cfg->delete_fraction <= 1, GSS_ERR_INVALID_ARG,
+                "delete_fraction must be in [0, 1]");
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    auto s = std::make_unique<gss_server>();
+    s->c = &c;
+    s->cfg = *cfg;
+    s->cfg.log_path = nullptr;
+    s->V = c.cfg.num_vars;
+    s->P = cfg->n_producers;
+    s->q_limit = cfg->max_queued_lits ? cfg->max_queued_lits : (1ull << 26);
+    if (cfg->log_path) {
+        s->log = std::fopen(cfg->log_path, "w");
+        GSS_REQUIRE(s->log, GSS_ERR_INVALID_ARG, std::string("cannot open the log file ") + cfg->log_path);
+    }
+    s->prod = std::vector<Producer>(s->P);
+    try {
+        GSS_HIP(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
+        GSS_HIP(hipEventCreateWithFlags(&s->ev_copied, hipEventDisableTiming));
+        const uint32_t first = std::min<uint32_t>(s->V, 1u << 16);
+        for (Producer &p : s->prod) {
+            p.pos.assign((size_t)s->V + 1, 0);
+            for (Mail &m : p.mail) {
+                GSS_HIP(hipEventCreateWithFlags(&m.done, hipEventDisableTiming));
+                ensure_host(m, first, s->V);
+            }
+        }
+        // every word starts untested and inactive
+        std::vector<uint64_t> none(c.W, 0);
+        const gss_status rc = gss_set_active(ctx, none.data());
+        if (rc != GSS_OK) throw Error(rc, c.last_error);
+        c.sync();
+    } catch (...) {
+        for (Producer &p : s->prod)
+            for (Mail &m : p.mail) {
+                if (m.h) (void)hipHostFree(m.h);
+                if (m.done) (void)hipEventDestroy(m.done);
+            }
+        if (s->ev_copied) (void)hipEventDestroy(s->ev_copied);
+        if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+        if (s->log) std::fclose(s->log);
+        throw;
+    }
+    s->t0 = Clock::now();
+    gss_server *raw = s.release();
+    raw->manager = std::thread([raw] { raw->run(); });
+    *out = raw;
+    GSS_API_END
+}
+
+// Wrapper of the server entry points: exceptions become status codes.
+#define GSS_SRV_BEGIN(sp)                     \
+    if (!(sp)) return GSS_ERR_INVALID_ARG;    \
+    try {
+#define GSS_SRV_END(sp)                       \
+    }                                         \
+    catch (const ::gss::Error &e) {           \
+        std::lock_guard<std::mutex> g_((sp)->emu); \
+        (sp)->error = e.what();               \
+        return e.code;                        \
+    }                                         \
+    catch (const std::bad_alloc &) {          \
+        return GSS_ERR_CAPACITY;              \
+    }                                         \
+    return GSS_OK;
+
+extern "C" gss_status gss_server_send(gss_server *s, uint32_t producer, uint32_t n_vars, const uint32_t *vars,
+                                      const uint64_t *f_words, const uint64_t *t_words) {
+    GSS_SRV_BEGIN(s)
+    GSS_REQUIRE(!s->failed.load(), GSS_ERR_STATE, "the server's manager stopped on an error");
+    GSS_REQUIRE(producer < s->P, GSS_ERR_INVALID_ARG, "producer out of range");
+    GSS_REQUIRE(n_vars == 0 || (vars && f_words && t_words), GSS_ERR_INVALID_ARG, "null argument");
+    for (uint32_t i = 0; i < n_vars; ++i) {
+        GSS_REQUIRE(vars[i] >= 1 && vars[i] <= s->V, GSS_ERR_BAD_LITERAL, "variable out of range");
+        GSS_REQUIRE((f_words[i] & t_words[i]) == 0, GSS_ERR_INVALID_ARG, "a slot cannot be both F and T");
+    }
+    Producer &p = s->prod[producer];
+    std::lock_guard<std::mutex> g(p.mu);
+    Mail &m = p.mail[p.open];
+    ensure_host(m, (uint32_t)std::min<uint64_t>((uint64_t)m.n + n_vars, s->V), s->V);
+    uint32_t *mv = m.vars();
+    uint64_t *mf = m.f(), *mt = m.t();
+    for (uint32_t i = 0; i < n_vars; ++i) {
+        const uint32_t v = vars[i];
+        uint32_t q = p.pos[v];
+        if (!(q < m.n && mv[q] == v)) {
+            q = m.n++;
+            mv[q] = v;
+            p.pos[v] = q;
+        }
+        mf[q] = f_words[i];
+        mt[q] = t_words[i];
+    }
+    p.snaps++;
+    p.arrival = s->now();
+    s->n_snapshots++;
+    GSS_SRV_END(s)
+}
+
+extern "C" gss_status gss_server_insert(gss_server *s, uint32_t producer, const int32_t *lits, const uint64_t *offsets,
+                                        uint32_t n) {
+    GSS_SRV_BEGIN(s)
+    GSS_REQUIRE(!s->failed.load(), GSS_ERR_STATE, "the server's manager stopped on an error");
+    GSS_REQUIRE(producer < s->P, GSS_ERR_INVALID_ARG, "producer out of range");
+    if (n == 0) return GSS_OK;
+    GSS_REQUIRE(lits && offsets, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE(offsets[0] == 0, GSS_ERR_INVALID_ARG, "offsets[0] must be 0");
+    const int64_t V = s->V;
+    for (uint32_t i = 0; i < n; ++i) {
+        GSS_REQUIRE(offsets[i + 1] > offsets[i] && offsets[i + 1] - offsets[i] <= kMaxClauseLen, GSS_ERR_INVALID_ARG,
+                    "clause length must be 1..65536");
+        for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k)
+            GSS_REQUIRE(lits[k] != 0 && lits[k] >= -V && lits[k] <= V, GSS_ERR_BAD_LITERAL, "literal out of range");
+    }
+    std::lock_guard<std::mutex> g(s->imu);
+    if (s->q_lits.size() + offsets[n] > s->q_limit) {
+        s->n_refused += n;
+        throw Error(GSS_ERR_CAPACITY, "insert queue full");
+    }
+    const uint64_t base = s->q_lits.size();
+    s->q_lits.insert(s->q_lits.end(), lits, lits + offsets[n]);
+    for (uint32_t i = 1; i <= n; ++i) s->q_off.push_back(base + offsets[i]);
+    GSS_SRV_END(s)
+}
+
+extern "C" gss_status gss_server_poll(gss_server *s, uint32_t producer, gss_report *out, uint64_t cap, uint64_t *out_n,
+                                      uint64_t *out_run) {
+    GSS_SRV_BEGIN(s)
+    GSS_REQUIRE(producer < s->P, GSS_ERR_INVALID_ARG, "producer out of range");
+    GSS_REQUIRE(out_n, GSS_ERR_INVALID_ARG, "null argument");
+    Producer &p = s->prod[producer];
+    std::lock_guard<std::mutex> g(p.omu);
+    if (out_run) *out_run = p.last_run;
+    if (!out) {
+        *out_n = p.outbox.size();
+        p.outbox.clear();
+        return GSS_OK;
+    }
+    const uint64_t k = std::min<uint64_t>(cap, p.outbox.size());
+    std::memcpy(out, p.outbox.data(), k * sizeof(gss_report));
+    p.outbox.erase(p.outbox.begin(), p.outbox.begin() + (ptrdiff_t)k);
+    *out_n = k;
+    GSS_SRV_END(s)
+}
+
+extern "C" gss_status gss_server_stop(gss_server *s, gss_serve_result *out) {
+    if (!s) return GSS_ERR_INVALID_ARG;
+    s->stop = true;
+    if (s->manager.joinable()) s->manager.join();
+    Ctx &c = *s->c;
+    gss_serve_result r = s->res;
+    r.snapshots = s->n_snapshots.load();
+    r.refused = s->n_refused.load();
+    r.live_end = c.live;
+    r.wall_s = s->now();
+    double sum = 0;
+    for (double x : s->lat) sum += x;
+    r.mean_ms = s->lat.empty() ? 0.0 : sum / (double)s->lat.size();
+    r.p50_ms = percentile(s->lat, 0.50);
+    r.p99_ms = percentile(s->lat, 0.99);
+    r.max_ms = s->lat.empty() ? 0.0 : *std::max_element(s->lat.begin(), s->lat.end());
+    (void)hipStreamSynchronize(s->copy_stream);
+    (void)hipStreamSynchronize(c.stream);
+    for (Producer &p : s->prod)
+        for (Mail &m : p.mail) {
+            if (m.h) (void)hipHostFree(m.h);
+            c.dfree(m.d);
+            if (m.done) (void)hipEventDestroy(m.done);
+        }
+    r.device_bytes_end = c.device_bytes;
+    (void)hipEventDestroy(s->ev_copied);
+    (void)hipStreamDestroy(s->copy_stream);
+    if (s->log) std::fclose(s->log);
+    if (out) *out = r;
+    const gss_status st = s->status;
+    c.last_error = s->error;
+    delete s;
+    return st;
+}
+
+extern "C" const char *gss_server_last_error(const gss_server *s) {
+    if (!s) return "";
+    std::lock_guard<std::mutex> g(s->emu);
+    return s->error.c_str();
+}

@@ -161,6 +161,7 @@ using namespace gss;
 extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const uint64_t *offsets, uint32_t n,
                                       uint32_t *out_ids) {
     GSS_API_BEGIN(ctx)
+    c_->mutations++;  // a test in flight no longer sees the current state
     Ctx &c = *c_;
     if (n == 0) return GSS_OK;
     GSS_REQUIRE(lits && offsets && out_ids, GSS_ERR_INVALID_ARG, "null argument");
@@ -332,6 +333,7 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
 
 extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint32_t n) {
     GSS_API_BEGIN(ctx)
+    c_->mutations++;  // a test in flight no longer sees the current state
     Ctx &c = *c_;
     if (n == 0) return GSS_OK;
     GSS_REQUIRE(ids != nullptr, GSS_ERR_INVALID_ARG, "null argument");

@@ -167,6 +167,7 @@ static void launch(Ctx &c, const Launch &L, uint32_t flags) {
     GSS_HIP(hipMemcpyAsync(c.h_summary, c.d_summary, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream));
     GSS_HIP(hipEventRecord(c.ev_done, c.stream));
     c.last_waves = n_waves;
+    c.launch_mutations = c.mutations;
 }
 
 // Waits for a launched test and records its kernel time.
@@ -237,7 +238,9 @@ static uint64_t end_test(Ctx &c, uint32_t flags, bool launched) {
             } catch (const Error &e) {
                 if (e.code != GSS_ERR_CAPACITY) throw;
             }
-            if (grown) {
+            // Repeating the test is only right while the state it saw is unchanged:
+            // changes queued behind an asynchronous test would be in the rerun.
+            if (grown && c.mutations == c.launch_mutations) {
                 c.stats.regrows++;
                 Launch L = prepare(c, flags);
                 launch(c, L, flags);

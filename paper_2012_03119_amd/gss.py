@@ -89,6 +89,34 @@ class gss_schedule(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class gss_server_config(ctypes.Structure):
+    _fields_ = [("n_producers", ctypes.c_uint32), ("test_flags", ctypes.c_uint32),
+                ("delete_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("log_path", ctypes.c_char_p), ("max_queued_lits", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 3)]
+
+
+SERVE_RESULT_COUNTS = ("snapshots", "tested", "dropped", "runs", "overflowed_runs", "inserted", "refused",
+                       "deleted", "reports", "pairs", "live_end", "device_bytes_end", "delta_bytes")
+SERVE_RESULT_TIMES = ("wall_s", "gpu_ms", "mean_ms", "p50_ms", "p99_ms", "max_ms", "admit_ms", "wait_ms",
+                      "fetch_ms", "route_ms", "store_ms", "launch_ms")
+
+
+class gss_serve_result(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in SERVE_RESULT_COUNTS] + [(n, ctypes.c_double) for n in SERVE_RESULT_TIMES]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class gss_sim_config(ctypes.Structure):
+    _fields_ = [("n_threads", ctypes.c_uint32), ("test_flags", ctypes.c_uint32),
+                ("duration_s", ctypes.c_double), ("snapshot_rate", ctypes.c_double),
+                ("redraw_fraction", ctypes.c_double), ("insert_rate", ctypes.c_double),
+                ("delete_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("log_path", ctypes.c_char_p), ("reserved", ctypes.c_uint64 * 4)]
+
+
 _lib = None
 
 
@@ -130,6 +158,13 @@ def load_library(path: Optional[str] = None):
         "gss_batch_set_schedule": ([P, ctypes.POINTER(gss_schedule)], ctypes.c_int32),
         "gss_batch_test": ([P, u32, P], ctypes.c_int32),
         "gss_batch_info": ([P, P, P, P, P], ctypes.c_int32),
+        "gss_server_start": ([P, ctypes.POINTER(gss_server_config), ctypes.POINTER(P)], ctypes.c_int32),
+        "gss_server_send": ([P, u32, u32, P, P, P], ctypes.c_int32),
+        "gss_server_insert": ([P, u32, P, P, u32], ctypes.c_int32),
+        "gss_server_poll": ([P, u32, P, u64, P, P], ctypes.c_int32),
+        "gss_server_stop": ([P, ctypes.POINTER(gss_serve_result)], ctypes.c_int32),
+        "gss_server_last_error": ([P], ctypes.c_char_p),
+        "gss_serve_simulate": ([P, ctypes.POINTER(gss_sim_config), ctypes.POINTER(gss_serve_result)], ctypes.c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -332,6 +367,62 @@ def gss_batch_info(b) -> dict:
     return dict(last_ms=ms.value, launches=la.value, captures=ca.value, tiles=ti.value)
 
 
+def gss_server_start(ctx, n_producers: int, *, test_flags: int = 0, delete_fraction: float = 0.0, seed: int = 0,
+                     log_path: Optional[str] = None, max_queued_lits: int = 0):
+    cfg = gss_server_config(n_producers, test_flags, delete_fraction, seed,
+                            log_path.encode() if log_path else None, max_queued_lits)
+    srv = ctypes.c_void_p()
+    _check(ctx, load_library().gss_server_start(ctx, ctypes.byref(cfg), ctypes.byref(srv)))
+    return srv
+
+
+def _check_server(srv, rc: int):
+    if rc != GSS_OK:
+        msg = load_library().gss_server_last_error(srv)
+        raise GssError(rc, msg.decode() if msg else "")
+
+
+def gss_server_send(srv, producer: int, vars_, f_words, t_words) -> None:
+    v = np.ascontiguousarray(vars_, dtype=np.uint32)
+    f = np.ascontiguousarray(f_words, dtype=np.uint64)
+    t = np.ascontiguousarray(t_words, dtype=np.uint64)
+    if not (v.size == f.size == t.size):
+        raise ValueError("vars, f_words and t_words differ in length")
+    _check_server(srv, load_library().gss_server_send(srv, producer, v.size, _np_ptr(v), _np_ptr(f), _np_ptr(t)))
+
+
+def gss_server_insert(srv, producer: int, lits, offsets) -> None:
+    lits = np.ascontiguousarray(lits, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    _check_server(srv, load_library().gss_server_insert(srv, producer, _np_ptr(lits), _np_ptr(offsets),
+                                                        offsets.size - 1))
+
+
+def gss_server_poll(srv, producer: int, cap: int = 1 << 20):
+    """(records, last run routed to the producer or None)."""
+    out = np.zeros(max(cap, 1), dtype=REPORT_DTYPE)
+    n, run = ctypes.c_uint64(), ctypes.c_uint64()
+    _check_server(srv, load_library().gss_server_poll(srv, producer, _np_ptr(out), cap, ctypes.byref(n),
+                                                      ctypes.byref(run)))
+    return out[:n.value].copy(), (None if run.value == 2**64 - 1 else run.value)
+
+
+def gss_server_stop(ctx, srv) -> dict:
+    r = gss_serve_result()
+    _check(ctx, load_library().gss_server_stop(srv, ctypes.byref(r)))
+    return r.as_dict()
+
+
+def gss_serve_simulate(ctx, *, n_threads: int, duration_s: float, snapshot_rate: float, redraw_fraction: float,
+                       insert_rate: float, delete_fraction: float, seed: int, test_flags: int = 0,
+                       log_path: Optional[str] = None) -> dict:
+    cfg = gss_sim_config(n_threads, test_flags, duration_s, snapshot_rate, redraw_fraction, insert_rate,
+                         delete_fraction, seed, log_path.encode() if log_path else None)
+    r = gss_serve_result()
+    _check(ctx, load_library().gss_serve_simulate(ctx, ctypes.byref(cfg), ctypes.byref(r)))
+    return r.as_dict()
+
+
 # ---------------------------------------------------------------------------
 # convenience wrapper
 # ---------------------------------------------------------------------------
@@ -458,6 +549,39 @@ class Context:
     @property
     def stream(self) -> int:
         return gss_get_stream(self.ctx)
+
+    def serve_simulate(self, **kw) -> dict:
+        """Runs the served workload generator on this context (gss_serve_simulate)."""
+        return gss_serve_simulate(self.ctx, **kw)
+
+
+class Server:
+    """A manager thread serving producers on one context (gss_server_*).  The
+    context must not be used directly until stop()."""
+
+    def __init__(self, context: "Context", n_producers: int, **kw):
+        self.context = context
+        self.srv = gss_server_start(context.ctx, n_producers, **kw)
+
+    def send(self, producer: int, vars_, f_words, t_words) -> None:
+        gss_server_send(self.srv, producer, vars_, f_words, t_words)
+
+    def insert(self, producer: int, lits, offsets) -> None:
+        gss_server_insert(self.srv, producer, lits, offsets)
+
+    def poll(self, producer: int, cap: int = 1 << 20):
+        return gss_server_poll(self.srv, producer, cap)
+
+    def stop(self) -> dict:
+        srv, self.srv = self.srv, None
+        return gss_server_stop(self.context.ctx, srv)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        if self.srv is not None:
+            self.stop()
 
 
 def sort_reports(r: np.ndarray) -> np.ndarray:

@@ -71,3 +71,43 @@ def test_create_rejects_bad_config_without_device(lib_path):
         assert lib.gss_create(ctypes.byref(cfg), ctypes.byref(out)) == gss.GSS_ERR_INVALID_ARG
         assert out.value is None
         assert lib.gss_last_error(None)
+
+
+STRUCTS = ["gss_config", "gss_stats", "gss_schedule", "gss_server_config", "gss_serve_result", "gss_sim_config"]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the ctypes binding equals what a C
+    compiler makes of include/gss.h."""
+    import subprocess
+    from paper_2012_03119_amd import gss
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gss.h"', "int main(void) {"]
+    for s in STRUCTS:
+        cls = getattr(gss, s)
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for name, _ in cls._fields_:
+            lines.append(f'printf("{s}.{name} %zu\\n", offsetof({s}, {name}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    c_side = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                     text=True).stdout.splitlines())
+    for s in STRUCTS:
+        cls = getattr(gss, s)
+        assert int(c_side[s]) == ctypes.sizeof(cls), s
+        for name, _ in cls._fields_:
+            assert int(c_side[f"{s}.{name}"]) == getattr(cls, name).offset, f"{s}.{name}"
+
+
+def test_null_server_is_rejected(lib_path):
+    from paper_2012_03119_amd import gss
+    lib = gss.load_library(lib_path)
+    n = ctypes.c_uint64()
+    assert lib.gss_server_send(None, 0, 0, None, None, None) == gss.GSS_ERR_INVALID_ARG
+    assert lib.gss_server_insert(None, 0, None, None, 0) == gss.GSS_ERR_INVALID_ARG
+    assert lib.gss_server_poll(None, 0, None, 0, ctypes.byref(n), None) == gss.GSS_ERR_INVALID_ARG
+    assert lib.gss_server_stop(None, None) == gss.GSS_ERR_INVALID_ARG
+    assert lib.gss_server_start(None, None, None) == gss.GSS_ERR_INVALID_ARG
+    assert lib.gss_serve_simulate(None, None, None) == gss.GSS_ERR_INVALID_ARG

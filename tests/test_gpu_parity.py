@@ -389,3 +389,36 @@ def test_async_test():
         n = ctx.test_wait()
         got = reports_to_dense(ctx.fetch_reports(n), w.n_clauses, 1)
     _check(got, oracle.masks(w.lits, w.offsets, w.values))
+
+
+def test_async_overflow_after_a_change_is_reported_not_repeated():
+    """An overflowing asynchronous test is not repeated once the state changed
+    behind it (a rerun would test the new state): the exact count is reported,
+    the segments are grown, and the next test is whole."""
+    rng = np.random.default_rng(12)
+    V, n = 200, 20_000
+    lits, offsets = gen.random_clauses(rng, np.full(n, 2, dtype=np.int64), V)
+    values = gen.assignments_bernoulli(rng, 64, V, 0.6)
+    with new_context(V, 64, report_capacity=1) as ctx:
+        ctx.add_clauses(lits, offsets)
+        ctx.set_assignments(0, values)
+        want = oracle.masks(lits, offsets, values)
+        n_want = int(np.count_nonzero(want))
+        # far more records than the smallest segments of the launch can hold
+        assert n_want > 16 * (n // 64 + 64)
+        ctx.test_async()
+        # a change queued behind the test: the same values again, as a delta
+        f = np.zeros(V, dtype=np.uint64)
+        t = np.zeros(V, dtype=np.uint64)
+        for b in range(64):
+            f |= (values[b] == -1).astype(np.uint64) << np.uint64(b)
+            t |= (values[b] == 1).astype(np.uint64) << np.uint64(b)
+        ctx.update_words(0, np.arange(1, V + 1, dtype=np.uint32), f, t)
+        with pytest.raises(gss.GssError) as e:
+            ctx.test_wait()
+        assert e.value.code == gss.GSS_ERR_REPORT_OVERFLOW
+        assert ctx.stats()["last_reports"] == n_want
+        assert ctx.stats()["regrows"] == 0
+        k = ctx.test()
+        got = reports_to_dense(ctx.fetch_reports(k), n, 1)
+    _check(got, want)
