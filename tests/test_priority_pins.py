@@ -1,0 +1,107 @@
+"""Pins of the learned-priority oracle (CPU): the gradient against central
+finite differences and against torch's autograd in float64, closed forms of the
+network and of the loss, the first Adam step in closed form, and the feature and
+schedule definitions on hand-checked cases."""
+import numpy as np
+import pytest
+
+from oracle import priority as P
+
+
+def _random_problem(seed, n=24, scale=0.5):
+    rng = np.random.default_rng(seed)
+    params = rng.normal(0, scale, P.N_PARAMS)
+    x = rng.normal(0, 1, (n, P.N_FEATURES))
+    y = (rng.random(n) < 0.4).astype(np.float64)
+    return params, x, y
+
+
+def test_parameter_count_and_layout():
+    assert P.N_PARAMS == 12 * 64 + 64 + 64 * 64 + 64 + 64 + 1 == 5057
+    params = np.arange(P.N_PARAMS, dtype=np.float64)
+    parts = P.unpack(params)
+    assert parts["W1"][0, 1] == 1 and parts["W1"][1, 0] == 64  # input-major
+    assert parts["b1"][0] == 768 and parts["W2"][0, 0] == 832 and parts["b2"][0] == 4928
+    assert parts["w3"][0] == 4992 and parts["b3"][0] == 5056
+    np.testing.assert_array_equal(P.pack(parts), params)
+
+
+def test_gradient_matches_central_differences():
+    params, x, y = _random_problem(1)
+    _, g = P.loss_grad(params, x, y)
+    h = 1e-6
+    num = np.empty(P.N_PARAMS)
+    for i in range(P.N_PARAMS):
+        e = np.zeros(P.N_PARAMS)
+        e[i] = h
+        num[i] = (P.loss(params + e, x, y) - P.loss(params - e, x, y)) / (2 * h)
+    assert np.max(np.abs(num - g)) < 1e-7 * max(1.0, np.max(np.abs(g))) + 1e-9
+
+
+def test_forward_and_gradient_match_torch_autograd():
+    torch = pytest.importorskip("torch")
+    params, x, y = _random_problem(2, n=40)
+    t = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in P.unpack(params).items()}
+    xt, yt = torch.tensor(x), torch.tensor(y)
+    h1 = torch.relu(xt @ t["W1"] + t["b1"])
+    h2 = torch.relu(h1 @ t["W2"] + t["b2"])
+    z3 = h2 @ t["w3"] + t["b3"][0]
+    lt = torch.nn.functional.binary_cross_entropy_with_logits(z3, yt)
+    lt.backward()
+    value, g = P.loss_grad(params, x, y)
+    np.testing.assert_allclose(P.forward(params, x)["prob"], torch.sigmoid(z3).detach().numpy(), rtol=1e-12)
+    assert abs(value - lt.item()) < 1e-12
+    np.testing.assert_allclose(g, P.pack({k: v.grad.numpy() for k, v in t.items()}), atol=1e-12)
+
+
+def test_closed_forms():
+    x = np.random.default_rng(3).normal(size=(7, 12))
+    zero = np.zeros(P.N_PARAMS)
+    np.testing.assert_allclose(P.forward(zero, x)["prob"], 0.5)
+    assert abs(P.loss(zero, x, np.array([0, 1, 1, 0, 1, 0, 0.0])) - np.log(2)) < 1e-15
+    only_b3 = zero.copy()
+    only_b3[-1] = 1.3
+    np.testing.assert_allclose(P.forward(only_b3, x)["prob"], 1 / (1 + np.exp(-1.3)))
+    # softplus form equals the textbook cross-entropy
+    y = np.array([1, 0, 1, 0, 1, 0, 1.0])
+    p = 1 / (1 + np.exp(-1.3))
+    want = -np.mean(y * np.log(p) + (1 - y) * np.log(1 - p))
+    assert abs(P.loss(only_b3, x, y) - want) < 1e-14
+    # the gradient of the last bias alone is mean(p - y)
+    _, g = P.loss_grad(only_b3, x, y)
+    assert abs(g[-1] - np.mean(p - y)) < 1e-15
+    assert np.all(g[:-1] == 0)  # relu(0) = 0 and its derivative is taken as 0
+
+
+def test_first_adam_step_closed_form():
+    params, x, y = _random_problem(4)
+    _, g = P.loss_grad(params, x, y)
+    lr, eps = 1e-2, 1e-8
+    theta, losses = P.adam(params, x, y, [np.arange(len(y))], lr=lr, eps=eps)
+    # bias-corrected moments of one step are g and g^2
+    np.testing.assert_allclose(theta, params - lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+    assert losses.shape == (1,)
+
+
+def test_features_by_hand():
+    x = P.features([3], [2], [0], [5], 11, [[0, 1, 0, 0, 0, 0, 0, 3]])
+    want = [np.log(4), np.log(3), 0.0, 0.5, 0.0, np.log(2), 0, 0, 0, 0, 0, np.log(4)]
+    np.testing.assert_allclose(x[0], want)
+    assert P.features([3], [2], [0], [0], 1, [[0] * 8])[0, 3] == 0.0  # a single source
+
+
+def test_schedule_by_enumeration():
+    ids = np.arange(40)
+    low = (ids % 3) == 0
+    for run in range(8):
+        got = P.tested(ids, low, run)
+        for i in ids:
+            assert got[i] == ((not low[i]) or ((run + i) % 4 == 0))
+    # over any 4 consecutive runs a low clause is tested exactly once
+    counts = sum(P.tested(ids, low, r).astype(int) for r in range(5, 9))
+    assert (counts[low] == 1).all() and (counts[~low] == 4).all()
+
+
+def test_hit_counts():
+    dense = np.array([[0, 1], [2**64 - 1, 3], [0, 0]], dtype=np.uint64)
+    np.testing.assert_array_equal(P.hit_counts(dense), [1, 66, 0])
