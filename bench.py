@@ -213,6 +213,7 @@ def bench_served(args, torch, gss):
         "latency_ms": {k: res[k + "_ms"] for k in ("p50", "p99", "mean", "max")},
         "served": {k: res[k] for k in ("snapshots", "tested", "dropped", "runs", "overflowed_runs", "inserted",
                                        "refused", "deleted", "reports", "live_end", "delta_bytes", "gpu_ms")},
+        "manager_ms": {k: round(res[k + "_ms"], 1) for k in ("admit", "wait", "fetch", "route", "store", "launch")},
         "dropped_ratio": res["dropped"] / max(res["snapshots"], 1),
         "gpu_busy": res["gpu_ms"] / (res["wall_s"] * 1e3),
         "plain": {"value": st["last_pairs"] / t_plain, "ms_per_test": t_plain * 1e3,
@@ -222,12 +223,180 @@ def bench_served(args, torch, gss):
     print(json.dumps(out), flush=True)
 
 
+def table1_words(rng, n):
+    """(F, T) words of n variables in one 64-slot word: each variable draws a value
+    subset with the Table 1 ratios, then every slot a value inside the subset."""
+    from paper_2012_03119_amd import gen
+    subsets = [sub for sub, _ in gen.TABLE1_SUBSETS]
+    p = np.array([w for _, w in gen.TABLE1_SUBSETS], dtype=np.float64)
+    pick = rng.choice(len(subsets), size=n, p=p / p.sum())
+    x = rng.integers(0, 2**63, size=n, dtype=np.int64).astype(np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, size=n, dtype=np.int64).astype(np.uint64)
+    y = rng.integers(0, 2**63, size=n, dtype=np.int64).astype(np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, size=n, dtype=np.int64).astype(np.uint64)
+    f = np.zeros(n, dtype=np.uint64)
+    t = np.zeros(n, dtype=np.uint64)
+    for k, sub in enumerate(subsets):
+        m = pick == k
+        vals = set(sub)
+        if vals == {1}:
+            t[m] = ~np.uint64(0)
+        elif vals == {-1}:
+            f[m] = ~np.uint64(0)
+        elif vals == {1, -1}:
+            f[m], t[m] = x[m], ~x[m]
+        elif vals == {1, 0}:
+            t[m] = x[m]
+        elif vals == {-1, 0}:
+            f[m] = x[m]
+        elif vals == {1, -1, 0}:  # two random bits per slot, redrawn where both are set
+            a, b = x[m].copy(), y[m].copy()
+            both = a & b
+            while both.any():
+                a = np.where(both != 0, (a & ~both) | (rng.integers(0, 2**63, size=len(a), dtype=np.int64)
+                             .astype(np.uint64) & both), a)
+                b = np.where(both != 0, (b & ~both) | (rng.integers(0, 2**63, size=len(b), dtype=np.int64)
+                             .astype(np.uint64) & both), b)
+                both = a & b
+            f[m], t[m] = a, b
+    return f, t
+
+
+def bench_learned(args, torch, gss):
+    """The learned schedule against the plain test on one stream: 32 words of
+    Table 1 snapshots, 5% of the variables of each word redrawn per run, over an
+    8M-clause store on 2M variables.  The network trains on the hit logs of the
+    first runs; its threshold is the score under which at most 0.4% of the
+    training positives fall.  On later runs each schedule (learned, hit recency,
+    random with the learned one's budget) runs beside the plain test, which judges
+    the hits each one misses."""
+    from paper_2012_03119_amd import gen
+    V, P, n0 = args.learn_vars, 32, args.learn_clauses
+    rng = np.random.default_rng(args.seed + 500)
+    t0 = time.perf_counter()
+    lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, n0), V)
+    lens = np.diff(offs)
+    ctx = gss.Context(V, P * 64, hbm_budget_bytes=64 << 30, report_capacity=1 << 22)
+    ids = ctx.add_clauses(lits, offs)
+    del lits, offs
+    ctx.priority_enable(n_sources=P, sample_period=args.learn_sample_period, sample_capacity=1 << 22,
+                        seed=args.seed + 501)
+    ctx.priority_set_clause_info(ids, (2 + rng.random(n0) * (np.maximum(lens, 2) - 2)).astype(np.float32),
+                                 rng.integers(0, P, n0).astype(np.uint32))
+    all_vars = np.arange(1, V + 1, dtype=np.uint32)
+    for w in range(P):
+        f, t = table1_words(rng, V)
+        ctx.update_words(w, all_vars, f, t)
+    ctx.set_active(np.full(P, 2**64 - 1, dtype=np.uint64))
+    log(f"learned: store and snapshots ready in {time.perf_counter() - t0:.1f} s")
+    blocks = (V + 63) // 64
+
+    def advance():  # every word redraws 5% of its variables, in runs of 64
+        for w in range(P):
+            b = rng.choice(blocks, size=max(1, int(0.05 * blocks)), replace=False)
+            vs = (b[:, None] * 64 + np.arange(1, 65)[None, :]).ravel()
+            vs = vs[vs <= V].astype(np.uint32)
+            f, t = table1_words(rng, len(vs))
+            ctx.update_words(w, vs, f, t)
+
+    def run_test(flags):
+        torch.cuda.synchronize()
+        n = ctx.test(flags)
+        r = ctx.fetch_reports(n)
+        st = ctx.stats()
+        bits = int(np.unpackbits(np.ascontiguousarray(r["mask"]).view(np.uint8)).sum()) if len(r) else 0
+        return bits, st["last_kernel_ms"], st["last_pairs"]
+
+    for r in range(args.learn_train_runs):
+        run_test(0)
+        ctx.priority_observe()
+        advance()
+    t1 = time.perf_counter()
+    loss = ctx.priority_train(args.learn_epochs, batch=4096, lr=3e-3, seed=args.seed + 502)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    info = ctx.priority_info()
+    sx, sy = ctx.priority_samples(1 << 22)
+    learned = ctx.priority_params()
+    p = gss.gss_mlp_forward(ctx.ctx, learned, sx)
+    pos = np.sort(p[sy > 0.5])
+    tau = float(pos[int(0.004 * len(pos))]) if len(pos) else 0.5
+    log(f"learned: {info['samples']} samples ({sy.mean():.3f} positive), trained in {t_train:.2f} s "
+        f"(loss {loss:.4f}), threshold {tau:.4f}")
+    # hit recency as a network: any hit in the last 8 tested runs scores ~1, none scores 0.27
+    recency = np.zeros(gss.MLP_PARAMS, dtype=np.float32)
+    recency[4 * 64:12 * 64:64] = 1.0      # W1[4..11][0] = 1
+    recency[832] = 1.0                    # W2[0][0] = 1
+    recency[4992] = 100.0                 # w3[0]
+    recency[5056] = -1.0                  # b3
+    sums = {k: [0, 0.0] for k in ("plain", "learned", "recency", "random")}
+    low_frac = []
+    n_low_learned = None
+    for r in range(args.learn_eval_runs):
+        ctx.priority_params(set_to=recency)
+        ctx.priority_score(0.5)
+        b, ms, _ = run_test(gss.GSS_TEST_SCHEDULED)
+        sums["recency"][0] += b
+        sums["recency"][1] += ms
+        if n_low_learned is not None:  # random, with the learned schedule's budget
+            low = np.zeros(n0, dtype=np.uint8)
+            low[rng.choice(n0, size=n_low_learned, replace=False)] = 1
+            ctx.priority_mark(low)
+            b, ms, _ = run_test(gss.GSS_TEST_SCHEDULED)
+            sums["random"][0] += b
+            sums["random"][1] += ms
+        b, ms, pairs = run_test(0)
+        sums["plain"][0] += b
+        sums["plain"][1] += ms
+        ctx.priority_params(set_to=learned)
+        n_low_learned = ctx.priority_score(tau)
+        low_frac.append(n_low_learned / n0)
+        b, ms, _ = run_test(gss.GSS_TEST_SCHEDULED)
+        sums["learned"][0] += b
+        sums["learned"][1] += ms
+        ctx.priority_observe()
+        advance()
+    R = args.learn_eval_runs
+    plain_ms = sums["plain"][1] / R
+    out_sched = {}
+    for k in ("learned", "recency", "random"):
+        runs = R if k != "random" else R - 1
+        hits_plain = sums["plain"][0] if k != "random" else sums["plain"][0] * (R - 1) / R
+        ms = sums[k][1] / max(runs, 1)
+        out_sched[k] = {"kernel_ms": ms, "speedup_vs_plain": plain_ms / ms if ms else None,
+                        "missed_hit_rate": 1 - sums[k][0] / hits_plain if hits_plain else None}
+    ctx.close()
+    value = pairs / (out_sched["learned"]["kernel_ms"] * 1e-3)
+    out = {
+        "metric": "clause x assignment tests/sec (learned schedule; missed-hit rate judged by the plain test)",
+        "value": value, "unit": "tests/s", "n_gpus": 1, "steps": R, "warmup": args.learn_train_runs,
+        "ms_per_step": out_sched["learned"]["kernel_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64+f32", "data": "synthetic",
+        "config": {"workload": f"learned: {n0} clauses (length mix) over {V} variables, 32 words of Table 1 "
+                               f"snapshots, 5% redrawn per run; MLP 12-64-64-1 fp32 trained on "
+                               f"{args.learn_train_runs} runs of hit logs", "threshold": tau,
+                   "low_fraction": float(np.mean(low_frac)), "train_s": t_train, "samples": info["samples"]},
+        "plain_kernel_ms": plain_ms, "schedules": out_sched,
+        "missed_hit_rate": out_sched["learned"]["missed_hit_rate"],
+        "speedup_vs_plain": out_sched["learned"]["speedup_vs_plain"],
+    }
+    log(f"learned: plain {plain_ms:.3f} ms, " + ", ".join(
+        f"{k} {v['kernel_ms']:.3f} ms missed {v['missed_hit_rate']:.4f}" for k, v in out_sched.items()))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["paper", "tiny", "batched", "served"], default="paper")
+    ap.add_argument("--workload", choices=["paper", "tiny", "batched", "served", "learned"], default="paper")
+    ap.add_argument("--learn-clauses", type=int, default=8_000_000)
+    ap.add_argument("--learn-vars", type=int, default=2_000_000)
+    ap.add_argument("--learn-train-runs", type=int, default=24)
+    ap.add_argument("--learn-eval-runs", type=int, default=16)
+    ap.add_argument("--learn-epochs", type=int, default=2)
+    ap.add_argument("--learn-sample-period", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-clauses", type=int, default=8_000_000)
     ap.add_argument("--clauses", type=int, default=4_000_000)
@@ -274,6 +443,9 @@ def main():
         return
     if args.workload == "served":
         bench_served(args, torch, gss)
+        return
+    if args.workload == "learned":
+        bench_learned(args, torch, gss)
         return
 
     t0 = time.perf_counter()

@@ -267,6 +267,88 @@ gss_status gss_batch_test(gss_batch *batch, uint32_t flags, uint64_t *out_n_repo
 gss_status gss_batch_info(const gss_batch *batch, double *last_ms, uint64_t *launches, uint64_t *captures,
                           uint64_t *tiles);
 
+/* ---- Learned clause priority ----
+ *
+ * The paper measures (Section 3.2) that a clause used recently is likely to be
+ * used again soon, and deletes clauses on the GPU by MiniSat-style activity
+ * (Section 3.7).  This extension learns a priority instead: a 12 -> 64 -> 64 -> 1
+ * perceptron (ReLU, sigmoid output, fp32) scores each clause from its length,
+ * LBD, age in runs, source thread and the hit counts (slots where it was
+ * falsified) of the last 8 runs that tested it; clauses scoring below a
+ * threshold are tested only in runs where (run + id) % 4 == 0.  The plain test
+ * stays available and judges what the schedule misses.
+ *
+ * Network parameters, 5057 floats: W1[12][64] (input major), b1[64], W2[64][64],
+ * b2[64], w3[64], b3.  Features, in order: log1p(length), log1p(LBD),
+ * log1p(age), source / max(1, n_sources - 1), log1p(hits of the last 8 tested
+ * runs), most recent first. */
+#define GSS_MLP_FEATURES 12
+#define GSS_MLP_PARAMS 5057
+
+/* Flag of gss_test: follow the priority schedule of the current run (needs
+ * gss_priority_score first). */
+#define GSS_TEST_SCHEDULED 128u
+
+typedef struct gss_adam_config {
+    float lr, beta1, beta2, eps; /* Adam (Kingma and Ba): step size, moment decays, epsilon */
+    uint32_t batch;              /* samples per step (the last step may be smaller) */
+    uint32_t reserved[3];
+} gss_adam_config;
+
+/* The network's kernels on their own (for checking them and for other callers).
+ * params: host [5057].  x: [n][12] fp32, y: [n] labels in {0, 1}, host or device.
+ * out_prob: [n] probabilities, out_grad: [5057] gradient of the mean binary
+ * cross-entropy, host or device; out_loss: host scalar. */
+gss_status gss_mlp_forward(gss_ctx *ctx, const float *params, const float *x, uint32_t n, float *out_prob);
+gss_status gss_mlp_loss_grad(gss_ctx *ctx, const float *params, const float *x, const float *y, uint32_t n,
+                             float *out_loss, float *out_grad);
+/* Adam from fresh moments over the minibatches order[0..batch), order[batch..2
+ * batch), ... (order: host array of row indices < n).  params (host) is updated in
+ * place; out_losses (host, may be NULL) receives each step's loss. */
+gss_status gss_mlp_train(gss_ctx *ctx, float *params, const float *x, const float *y, uint32_t n,
+                         const uint32_t *order, uint64_t n_order, const gss_adam_config *cfg, float *out_losses);
+
+typedef struct gss_priority_config {
+    uint32_t n_sources;       /* solver threads that export clauses (>= 1) */
+    uint32_t sample_period;   /* a tested clause becomes a training sample of a run when a hash of
+                                 (seed, id, run) is 0 modulo the period; 0 = no samples */
+    uint64_t sample_capacity; /* rows of the sample buffer */
+    uint64_t seed;            /* sampling and weight initialisation */
+    uint64_t reserved[4];
+} gss_priority_config;
+
+/* Enables the priority on a context: per-clause state for every issued id (LBD
+ * defaults to the length, source to 0), a seeded He-uniform network. */
+gss_status gss_priority_enable(gss_ctx *ctx, const gss_priority_config *cfg);
+/* LBD (>= 0) and source thread (< n_sources) of n live clauses (host arrays). */
+gss_status gss_priority_set_clause_info(gss_ctx *ctx, const uint32_t *ids, uint32_t n, const float *lbd,
+                                        const uint32_t *source);
+/* After a test (plain or scheduled, not dense, no records lost): counts each
+ * clause's hits from the test's records, takes the run's samples (features
+ * before the run, label = hit in it), shifts the hit history of every clause the
+ * test ran, and advances the run counter.  Once per test. */
+gss_status gss_priority_observe(gss_ctx *ctx);
+/* Trains the network on the samples taken so far: epochs of seeded shuffles,
+ * Adam from fresh moments.  *out_loss (may be NULL): the last step's loss. */
+gss_status gss_priority_train(gss_ctx *ctx, uint32_t epochs, const gss_adam_config *cfg, uint64_t seed,
+                              float *out_loss);
+gss_status gss_priority_clear_samples(gss_ctx *ctx);
+/* Scores every live clause; scores below threshold are low priority.
+ * *out_n_low (may be NULL): how many. */
+gss_status gss_priority_score(gss_ctx *ctx, float threshold, uint64_t *out_n_low);
+/* Sets the low flags directly, one byte per issued id (host array of next_id
+ * entries; nonzero = low), in place of a scoring: schedules of other policies. */
+gss_status gss_priority_mark(gss_ctx *ctx, const uint8_t *low, uint64_t n);
+/* Copies the network's parameters out (get) and/or in (set); host [5057] each, either may be NULL. */
+gss_status gss_priority_params(gss_ctx *ctx, float *get, const float *set);
+/* Features ([n][12]), last scores and low flags of n issued ids (host arrays). */
+gss_status gss_priority_fetch(gss_ctx *ctx, const uint32_t *ids, uint32_t n, float *out_features, float *out_scores,
+                              uint8_t *out_low);
+/* Copies up to cap samples ([cap][12] features, [cap] labels; host, either may be NULL). */
+gss_status gss_priority_samples(gss_ctx *ctx, float *out_x, float *out_y, uint64_t cap, uint64_t *out_n);
+/* Run counter, samples held, low clauses of the last scoring. */
+gss_status gss_priority_info(const gss_ctx *ctx, uint32_t *out_run, uint64_t *out_samples, uint64_t *out_n_low);
+
 /* ---- Served test: a manager thread fed by solver threads ----
  *
  * Section 5 has one CPU thread besides the solver threads manage the GPU; per

@@ -210,9 +210,12 @@ static thread_local std::string g_create_error;
 static void destroy_ctx(Ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    priority_release(*c);
+    mlp_release(*c);
     for (auto &b : c->buckets) {
         c->dfree(b.lits);
         c->dfree(b.meta);
+        c->dfree(b.low);
     }
     c->dfree(c->planes);
     c->dfree(c->active);

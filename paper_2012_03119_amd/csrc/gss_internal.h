@@ -82,6 +82,8 @@ struct BucketDesc {
     uint64_t meta_bytes;
     uint32_t stride_log2;  // S = 1 << stride_log2 codes per slot
     uint32_t tile_begin;   // global index of the bucket's first tile
+    const uint32_t *low;   // schedule: bit per slot, set for low-priority clauses (null: no schedule)
+    uint64_t low_bytes;
 };
 
 struct TestArgs {
@@ -96,6 +98,7 @@ struct TestArgs {
     uint32_t *seg_counts;     // [n_waves]: records produced by each wavefront (beyond seg_cap: counted only)
     uint32_t seg_cap;
     uint64_t *dense;          // GSS_TEST_DENSE: [n_ids][W]
+    uint32_t sched_run;       // schedule: a low-priority clause is tested when (sched_run + id) % 4 == 0
 };
 
 // ---------------------------------------------------------------------------
@@ -112,7 +115,12 @@ struct Bucket {
     uint2 *meta = nullptr;        // per slot (length, id)
     std::vector<uint32_t> h_ids;  // mirror of ids (kDeadId = removed)
     std::vector<uint32_t> h_len;  // mirror of len
+    uint32_t *low = nullptr;      // schedule bits (one per slot), built from the priority scores
+    uint64_t low_words = 0;
 };
+
+struct MlpWork;
+struct Priority;
 
 struct Ctx {
     gss_config cfg{};
@@ -152,6 +160,7 @@ struct Ctx {
     uint32_t *hsmall = nullptr;              // 256 B pinned host
     void *d_desc = nullptr;                  // device copy of the test kernel's bucket descriptors
     void *hsmall_desc = nullptr;             // pinned host staging of the same
+    uint64_t test_serial = 0;  // tests completed by this context
     uint64_t n_reports = 0;  // records found by the last test
     uint64_t n_kept = 0;     // records stored (fewer on overflow)
     bool tested = false;
@@ -177,6 +186,8 @@ struct Ctx {
     uint64_t launch_mutations = 0;  // the same counter when the last test was launched
     gss_stats stats{};
     std::string last_error;
+    MlpWork *mlp = nullptr;    // workspace of the priority network's kernels
+    Priority *prio = nullptr;  // learned clause priority (null until enabled)
 
     // device memory within the budget
     void *dalloc(size_t bytes);
@@ -217,6 +228,14 @@ void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value);
 bool is_device_pointer(const void *p);
 const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n);
 void check_flag(Ctx &c);
+// learned priority hooks: clauses added (ids first..first+n, lengths from offsets),
+// clauses removed (host ids), the schedule bits of every class (for a scheduled
+// test; returns the run number), and release of everything
+void priority_added(Ctx &c, uint64_t first, uint32_t n, const uint64_t *offsets);
+void priority_removed(Ctx &c, const uint32_t *ids, uint32_t n);
+uint32_t priority_schedule(Ctx &c);
+void priority_release(Ctx &c);
+void mlp_release(Ctx &c);
 // queues new plane words of n variables of one 64-slot word (device arrays, checked by the caller)
 void launch_set_words(Ctx &c, uint32_t word, const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n);
 

@@ -59,37 +59,48 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RW,
     }
 }
 
-// Delta update: new values of listed variables over a slot range.  One wavefront
-// per (variable, 64-slot word): lane b reads slot 64*w + b (coalesced across the
-// lanes), two ballots build the word, lane 0 merges it into the row.  vals is
-// var-major [n_vars][n_slots].
+// Delta update: thread per (variable, 64-slot word), grid (variables, words).
+// The thread reads the word's 64 values of its variable (four 16-byte loads when
+// the word is whole and aligned) and builds the F and T words; a word only partly
+// inside [first, first + n_slots) keeps its other slots.  vals is var-major
+// [n_vars][n_slots].
 __global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RW, const uint32_t *vars, uint32_t n_vars,
                                                   const int8_t *vals, uint32_t first, uint32_t n_slots,
                                                   const uint32_t *bad) {
     if (*bad) return;  // the inputs failed validation: apply nothing
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t w_lo = first / 64, nw = (first + n_slots - 1) / 64 - w_lo + 1;
-    const uint64_t total = (uint64_t)n_vars * nw;
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
-    for (uint64_t g = (uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; g < total; g += waves) {
-        const uint32_t i = (uint32_t)(g / nw), w = w_lo + (uint32_t)(g % nw);
-        const uint32_t slot = 64 * w + lane;
-        const bool in = slot >= first && slot < first + n_slots;
-        const int8_t x = in ? vals[(uint64_t)i * n_slots + (slot - first)] : (int8_t)0;
-        const uint64_t bf = __ballot(x == -1);
-        const uint64_t bt = __ballot(x == 1);
-        const uint64_t sm = __ballot(in);
-        if (lane == 0) {
-            const uint64_t r0 = (uint64_t)(2 * vars[i]) * RW + w, r1 = r0 + RW;
-            uint64_t f = bf, t = bt;
-            if (sm != ~0ull) {
-                f = (planes[r0] & ~sm) | (f & sm);
-                t = (planes[r1] & ~sm) | (t & sm);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_vars) return;
+    const uint32_t w = first / 64 + blockIdx.y;
+    const uint32_t lo = max(first, 64 * w), hi = min(first + n_slots, 64 * w + 64);
+    const int8_t *src = vals + (uint64_t)i * n_slots + (lo - first);
+    uint64_t f = 0, t = 0;
+    if (hi - lo == 64 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 v = reinterpret_cast<const uint4 *>(src)[q];
+            const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t b = (u[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                f |= (uint64_t)(b == 0xFFu) << (16 * q + k);
+                t |= (uint64_t)(b == 0x01u) << (16 * q + k);
             }
-            planes[r0] = f;
-            planes[r1] = t;
+        }
+    } else {
+        for (uint32_t s = lo; s < hi; ++s) {
+            const int8_t x = src[s - lo];
+            f |= (uint64_t)(x == -1) << (s - 64 * w);
+            t |= (uint64_t)(x == 1) << (s - 64 * w);
         }
     }
+    const uint64_t r0 = (uint64_t)(2 * vars[i]) * RW + w, r1 = r0 + RW;
+    if (hi - lo != 64) {
+        const uint64_t sm = ((1ull << (hi - lo)) - 1) << (lo - 64 * w);  // hi - lo < 64 here
+        f = (planes[r0] & ~sm) | (f & sm);
+        t = (planes[r1] & ~sm) | (t & sm);
+    }
+    planes[r0] = f;
+    planes[r1] = t;
 }
 
 // Packed delta: new plane words of listed variables in one 64-slot word.  Thread
@@ -230,10 +241,9 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
     if (!dev) std::memcpy(h + vars_bytes, values, nv);
     GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
     const int8_t *dvals = dev ? values : (const int8_t *)(d + vars_bytes);
-    const uint64_t waves = (uint64_t)n_vars * ((first_slot + n_slots - 1) / 64 - first_slot / 64 + 1);
-    const unsigned grid = (unsigned)std::min<uint64_t>((waves + 3) / 4, 1u << 20);
-    hipLaunchKernelGGL(k_set_vars, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, (const uint32_t *)d, n_vars,
-                       dvals, first_slot, n_slots, bad);
+    const uint32_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
+    hipLaunchKernelGGL(k_set_vars, dim3((n_vars + 255) / 256, nw), dim3(256), 0, c.stream, c.planes, c.RW,
+                       (const uint32_t *)d, n_vars, dvals, first_slot, n_slots, bad);
     GSS_HIP(hipGetLastError());
     c.stage_done(st);
     if (dev) check_flag(c);  // one synchronisation: device inputs are fully read when the call returns

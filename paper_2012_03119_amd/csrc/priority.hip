@@ -1,0 +1,577 @@
+// Learned clause priority: per-clause statistics, training samples, scoring by
+// the network of mlp.h, and the schedule the test kernel follows.
+//
+// Section 3.2 of the paper finds that a clause used recently is likely to be used
+// again soon, and Section 3.7 keeps the GPU's store small with activity-based
+// deletion.  Here that history feeds a network instead: after each run, every
+// clause the run tested shifts its last-8 hit counts; a seeded fraction of the
+// tested clauses become training samples (features before the run, label = hit
+// in the run).  Scoring marks clauses below a threshold as low priority, and a
+// scheduled test runs a low clause only when (run + id) % 4 == 0.
+//
+// State is kept per clause id (structure of arrays, grown with the id space):
+// length, LBD, birth run, source thread, alive flag, 8 hit counts, this run's
+// hit count, score and low flag.  The schedule bits the test kernel reads are
+// per slot of each length class, rebuilt from the low flags when the store or
+// the scores changed.
+#include "mlp.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <type_traits>
+
+namespace gss {
+
+struct Priority {
+    gss_priority_config cfg{};
+    uint64_t cap = 0;    // ids with state
+    uint64_t n_ids = 0;  // ids issued so far (state valid below)
+    uint32_t *len = nullptr, *birth = nullptr, *src = nullptr, *hits = nullptr;
+    uint32_t *hist = nullptr;  // [kHist][cap], most recent first
+    float *lbd = nullptr, *score = nullptr;
+    uint8_t *alive = nullptr, *low = nullptr;
+    float *sx = nullptr, *sy = nullptr;  // samples [sample_cap][kFeat], [sample_cap]
+    uint32_t *counters = nullptr;        // [0] samples taken, [1] low clauses of the last scoring
+    uint32_t *h_counters = nullptr;      // pinned copy
+    float *params = nullptr;             // [kParams]
+    uint32_t run = 0;
+    uint64_t observed_serial = ~0ull;
+    uint64_t score_epoch = 0;
+    uint64_t built_version = ~0ull, built_epoch = ~0ull;
+    float threshold = 0.f;
+};
+
+namespace {
+
+__device__ inline uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct ProbeArgs {  // per-id arrays as the kernels see them
+    uint32_t *len, *birth, *src, *hits, *hist;
+    float *lbd, *score;
+    uint8_t *alive, *low;
+    uint64_t cap;
+};
+
+ProbeArgs args_of(const Priority &p) {
+    return ProbeArgs{p.len, p.birth, p.src, p.hits, p.hist, p.lbd, p.score, p.alive, p.low, p.cap};
+}
+
+__device__ inline void load_features(const ProbeArgs &a, uint64_t id, uint32_t run, float src_scale,
+                                     float (&x)[kFeat]) {
+    uint32_t h[kHist];
+#pragma unroll
+    for (int k = 0; k < kHist; ++k) h[k] = a.hist[(uint64_t)k * a.cap + id];
+    clause_features(x, a.len[id], a.lbd[id], run - a.birth[id], a.src[id], src_scale, h);
+}
+
+__global__ void k_prio_init(ProbeArgs a, uint64_t first, uint32_t n, const uint32_t *lens, uint32_t run) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t id = first + i;
+    a.len[id] = lens[i];
+    a.lbd[id] = (float)lens[i];
+    a.birth[id] = run;
+    a.src[id] = 0;
+    a.hits[id] = 0;
+#pragma unroll
+    for (int k = 0; k < kHist; ++k) a.hist[(uint64_t)k * a.cap + id] = 0;
+    a.alive[id] = 1;
+    a.low[id] = 0;
+    a.score[id] = 1.f;
+}
+
+__global__ void k_prio_kill(ProbeArgs a, const uint32_t *ids, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    a.alive[ids[i]] = 0;
+    a.low[ids[i]] = 0;
+}
+
+__global__ void k_prio_info(ProbeArgs a, const uint32_t *ids, uint32_t n, const float *lbd, const uint32_t *src) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    a.lbd[ids[i]] = lbd[i];
+    a.src[ids[i]] = src[i];
+}
+
+// Hit counts of the last run: one workgroup per report segment.
+__global__ void k_prio_hits(ProbeArgs a, const gss_report *reports, const uint32_t *counts, uint32_t seg_cap,
+                            uint32_t n_segments) {
+    for (uint32_t s = blockIdx.x; s < n_segments; s += gridDim.x) {
+        const uint32_t n = min(counts[s], seg_cap);
+        const gss_report *seg = reports + (uint64_t)s * seg_cap;
+        for (uint32_t r = threadIdx.x; r < n; r += blockDim.x)
+            atomicAdd(&a.hits[seg[r].clause_id], (uint32_t)__popcll(seg[r].mask));
+    }
+}
+
+// After a run: samples, history shift, hit counter reset.
+__global__ void k_prio_observe(ProbeArgs a, uint64_t n_ids, uint32_t run, uint32_t scheduled, float src_scale,
+                               uint32_t period, uint64_t seed, float *sx, float *sy, uint64_t sample_cap,
+                               uint32_t *counters) {
+    const uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (id >= n_ids || !a.alive[id]) return;
+    const uint32_t h = a.hits[id];
+    const bool tested = !(scheduled && a.low[id] && ((run + (uint32_t)id) & 3u) != 0);
+    if (tested && period && mix64(seed ^ (id << 32) ^ run) % period == 0) {
+        const uint32_t pos = atomicAdd(&counters[0], 1u);
+        if (pos < sample_cap) {
+            float x[kFeat];
+            load_features(a, id, run, src_scale, x);
+#pragma unroll
+            for (int k = 0; k < kFeat; ++k) sx[(uint64_t)pos * kFeat + k] = x[k];
+            sy[pos] = h ? 1.f : 0.f;
+        }
+    }
+    if (tested) {
+#pragma unroll
+        for (int k = kHist - 1; k > 0; --k) a.hist[(uint64_t)k * a.cap + id] = a.hist[(uint64_t)(k - 1) * a.cap + id];
+        a.hist[id] = h;
+    }
+    a.hits[id] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_prio_score(ProbeArgs a, const float *__restrict__ params, uint64_t n_ids,
+                                                    uint32_t run, float src_scale, float threshold,
+                                                    uint32_t *counters) {
+    const uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (id >= n_ids) return;
+    if (!a.alive[id]) {
+        a.score[id] = 0.f;
+        a.low[id] = 0;
+        return;
+    }
+    float x[kFeat];
+    load_features(a, id, run, src_scale, x);
+    const float p = sigmoidf_(mlp_logit(params, x));
+    a.score[id] = p;
+    const bool lo = p < threshold;
+    a.low[id] = lo;
+    const uint64_t b = __ballot(lo);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[1], (uint32_t)__popcll(b));
+}
+
+// Schedule bits of one length class: bit s of word s / 32 set when slot s holds
+// a live low-priority clause.  Grid over 64-slot groups.
+__global__ void k_sched_bits(const uint2 *meta, uint64_t n_slots, const uint8_t *low, uint32_t *bits,
+                             uint64_t n_words) {
+    const uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    bool b = false;
+    if (s < n_slots) {
+        const uint2 m = meta[s];
+        b = m.x != 0 && low[m.y];
+    }
+    const uint64_t bal = __ballot(b);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t w = (s - lane) / 32;
+    if (lane == 0 && w < n_words) bits[w] = (uint32_t)bal;
+    if (lane == 32 && w + 1 < n_words) bits[w + 1] = (uint32_t)(bal >> 32);
+}
+
+__global__ void k_prio_mark(ProbeArgs a, const uint8_t *low, uint64_t n, uint32_t *counters) {
+    const uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const bool lo = a.alive[id] && low[id];
+    a.low[id] = lo;
+    const uint64_t b = __ballot(lo);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[1], (uint32_t)__popcll(b));
+}
+
+__global__ void k_prio_fetch(ProbeArgs a, const uint32_t *ids, uint32_t n, uint32_t run, float src_scale, float *x,
+                             float *score, uint8_t *low) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float f[kFeat];
+    load_features(a, ids[i], run, src_scale, f);
+#pragma unroll
+    for (int k = 0; k < kFeat; ++k) x[(uint64_t)i * kFeat + k] = f[k];
+    score[i] = a.score[ids[i]];
+    low[i] = a.low[ids[i]];
+}
+
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+unsigned grid_of(uint64_t n, unsigned block = 256) { return (unsigned)std::max<uint64_t>(1, (n + block - 1) / block); }
+
+float src_scale(const Priority &p) { return 1.f / (float)std::max<uint32_t>(1, p.cfg.n_sources - 1); }
+
+// Grows the per-id arrays to hold `need` ids (contents kept).
+void grow(Ctx &c, Priority &p, uint64_t need) {
+    if (need <= p.cap) return;
+    const uint64_t cap = std::max<uint64_t>({need, p.cap + p.cap / 2, 1u << 16});
+    c.sync();
+    auto move = [&](auto *&arr, size_t elem, uint64_t rows) {
+        using T = std::remove_reference_t<decltype(*arr)>;
+        T *q = (T *)c.dalloc(cap * elem * rows);
+        for (uint64_t r = 0; r < rows && arr; ++r)
+            GSS_HIP(hipMemcpyAsync((char *)q + r * cap * elem, (char *)arr + r * p.cap * elem, p.n_ids * elem,
+                                   hipMemcpyDeviceToDevice, c.stream));
+        c.sync();
+        c.dfree(arr);
+        arr = q;
+    };
+    move(p.len, 4, 1);
+    move(p.birth, 4, 1);
+    move(p.src, 4, 1);
+    move(p.hits, 4, 1);
+    move(p.hist, 4, kHist);
+    move(p.lbd, 4, 1);
+    move(p.score, 4, 1);
+    move(p.alive, 1, 1);
+    move(p.low, 1, 1);
+    p.cap = cap;
+}
+
+Priority &need_prio(Ctx &c) {
+    GSS_REQUIRE(c.prio, GSS_ERR_STATE, "the learned priority is not enabled (gss_priority_enable)");
+    return *c.prio;
+}
+
+}  // namespace
+
+void priority_added(Ctx &c, uint64_t first, uint32_t n, const uint64_t *offsets) {
+    if (!c.prio || n == 0) return;
+    Priority &p = *c.prio;
+    grow(c, p, first + n);
+    const Ctx::Staged st = c.stage_upload((size_t)n * 4);
+    uint32_t *h = (uint32_t *)st.h;
+    for (uint32_t i = 0; i < n; ++i) h[i] = (uint32_t)(offsets[i + 1] - offsets[i]);
+    GSS_HIP(hipMemcpyAsync(st.d, st.h, (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
+    hipLaunchKernelGGL(k_prio_init, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), first, n,
+                       (const uint32_t *)st.d, p.run);
+    GSS_HIP(hipGetLastError());
+    c.stage_done(st);
+    p.n_ids = std::max<uint64_t>(p.n_ids, first + n);
+}
+
+void priority_removed(Ctx &c, const uint32_t *ids, uint32_t n) {
+    if (!c.prio || n == 0) return;
+    Priority &p = *c.prio;
+    const Ctx::Staged st = c.stage_upload((size_t)n * 4);
+    std::memcpy(st.h, ids, (size_t)n * 4);
+    GSS_HIP(hipMemcpyAsync(st.d, st.h, (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
+    hipLaunchKernelGGL(k_prio_kill, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), (const uint32_t *)st.d, n);
+    GSS_HIP(hipGetLastError());
+    c.stage_done(st);
+}
+
+uint32_t priority_schedule(Ctx &c) {
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(p.score_epoch > 0, GSS_ERR_STATE, "a scheduled test needs a scoring first (gss_priority_score)");
+    bool fresh = p.built_version == c.version && p.built_epoch == p.score_epoch;
+    for (int b = 0; b < kMaxBuckets && fresh; ++b)
+        fresh = c.buckets[b].low_words >= (c.buckets[b].cap_slots + 31) / 32;
+    if (!fresh) {
+        for (int b = 0; b < kMaxBuckets; ++b) {
+            Bucket &B = c.buckets[b];
+            if (B.cap_slots == 0) continue;
+            const uint64_t words = (B.cap_slots + 31) / 32;
+            if (B.low_words < words) {
+                c.sync();
+                c.dfree(B.low);
+                B.low = nullptr;
+                B.low_words = 0;
+                B.low = (uint32_t *)c.dalloc(words * 4);
+                B.low_words = words;
+            }
+            hipLaunchKernelGGL(k_sched_bits, dim3(grid_of(B.low_words * 32)), dim3(256), 0, c.stream, B.meta,
+                               B.n_slots, p.low, B.low, B.low_words);
+            GSS_HIP(hipGetLastError());
+        }
+        p.built_version = c.version;
+        p.built_epoch = p.score_epoch;
+    }
+    return p.run;
+}
+
+void priority_release(Ctx &c) {
+    Priority *p = c.prio;
+    if (!p) return;
+    for (void *q : {(void *)p->len, (void *)p->birth, (void *)p->src, (void *)p->hits, (void *)p->hist, (void *)p->lbd,
+                    (void *)p->score, (void *)p->alive, (void *)p->low, (void *)p->sx, (void *)p->sy,
+                    (void *)p->counters, (void *)p->params})
+        c.dfree(q);
+    if (p->h_counters) (void)hipHostFree(p->h_counters);
+    delete p;
+    c.prio = nullptr;
+}
+
+}  // namespace gss
+
+using namespace gss;
+
+extern "C" gss_status gss_priority_enable(gss_ctx *ctx, const gss_priority_config *cfg) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    GSS_REQUIRE(cfg, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE(!c.prio, GSS_ERR_STATE, "the learned priority is already enabled");
+    GSS_REQUIRE(cfg->n_sources >= 1, GSS_ERR_INVALID_ARG, "n_sources must be at least 1");
+    GSS_REQUIRE(cfg->sample_period == 0 || cfg->sample_capacity >= 1, GSS_ERR_INVALID_ARG,
+                "sampling needs a sample capacity");
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    auto p = std::make_unique<Priority>();
+    p->cfg = *cfg;
+    c.prio = p.get();
+    try {
+        Priority &q = *p;
+        q.counters = (uint32_t *)c.dalloc(256);
+        GSS_HIP(hipHostMalloc((void **)&q.h_counters, 256, hipHostMallocDefault));
+        launch_fill_u32(c, q.counters, 64, 0);
+        q.params = (float *)c.dalloc(kParams * 4);
+        if (cfg->sample_capacity) {
+            q.sx = (float *)c.dalloc(cfg->sample_capacity * kFeat * 4);
+            q.sy = (float *)c.dalloc(cfg->sample_capacity * 4);
+        }
+        // He-uniform weights (bound sqrt(6 / fan_in)), zero biases, from the seed
+        std::vector<float> w(kParams, 0.f);
+        uint64_t s = cfg->seed * 0x9E3779B97F4A7C15ull + 1;
+        auto uni = [&](float bound) { return (float)((splitmix(s) >> 11) * (1.0 / 9007199254740992.0) * 2 - 1) * bound; };
+        for (int i = 0; i < kFeat * kHid; ++i) w[kOffW1 + i] = uni(std::sqrt(6.f / kFeat));
+        for (int i = 0; i < kHid * kHid; ++i) w[kOffW2 + i] = uni(std::sqrt(6.f / kHid));
+        for (int i = 0; i < kHid; ++i) w[kOffW3 + i] = uni(std::sqrt(6.f / kHid));
+        GSS_HIP(hipMemcpy(q.params, w.data(), kParams * 4, hipMemcpyHostToDevice));
+        // clauses already in the store get their lengths now; LBD defaults to the length
+        std::vector<uint64_t> offs(c.id_loc.size() + 1, 0);
+        for (uint64_t id = 0; id < c.id_loc.size(); ++id) {
+            uint32_t L = 0;
+            if (c.id_loc[id] != kNoLoc) {
+                const uint64_t loc = c.id_loc[id];
+                L = c.buckets[loc >> 40].h_len[loc & ((1ull << 40) - 1)];
+            }
+            offs[id + 1] = offs[id] + L;
+        }
+        const uint64_t n = c.id_loc.size();
+        for (uint64_t first = 0; first < n; first += 1u << 22) {
+            const uint32_t m = (uint32_t)std::min<uint64_t>(n - first, 1u << 22);
+            std::vector<uint64_t> o(offs.begin() + first, offs.begin() + first + m + 1);
+            priority_added(c, first, m, o.data());
+        }
+        std::vector<uint32_t> dead;
+        for (uint64_t id = 0; id < n; ++id)
+            if (c.id_loc[id] == kNoLoc) dead.push_back((uint32_t)id);
+        for (size_t k = 0; k < dead.size(); k += 1u << 20)
+            priority_removed(c, dead.data() + k, (uint32_t)std::min<size_t>(dead.size() - k, 1u << 20));
+        c.sync();
+    } catch (...) {
+        priority_release(c);
+        p.release();
+        throw;
+    }
+    p.release();
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_set_clause_info(gss_ctx *ctx, const uint32_t *ids, uint32_t n, const float *lbd,
+                                                   const uint32_t *source) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    if (n == 0) return GSS_OK;
+    GSS_REQUIRE(ids && lbd && source, GSS_ERR_INVALID_ARG, "null argument");
+    for (uint32_t i = 0; i < n; ++i) {
+        GSS_REQUIRE(ids[i] < c.id_loc.size() && c.id_loc[ids[i]] != kNoLoc, GSS_ERR_UNKNOWN_ID, "clause id not live");
+        GSS_REQUIRE(source[i] < p.cfg.n_sources, GSS_ERR_INVALID_ARG, "source beyond n_sources");
+        GSS_REQUIRE(lbd[i] >= 0 && std::isfinite(lbd[i]), GSS_ERR_INVALID_ARG, "LBD must be finite and >= 0");
+    }
+    const Ctx::Staged st = c.stage_upload((size_t)n * 12);
+    std::memcpy(st.h, ids, (size_t)n * 4);
+    std::memcpy(st.h + (size_t)n * 4, lbd, (size_t)n * 4);
+    std::memcpy(st.h + (size_t)n * 8, source, (size_t)n * 4);
+    GSS_HIP(hipMemcpyAsync(st.d, st.h, (size_t)n * 12, hipMemcpyHostToDevice, c.stream));
+    hipLaunchKernelGGL(k_prio_info, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), (const uint32_t *)st.d, n,
+                       (const float *)(st.d + (size_t)n * 4), (const uint32_t *)(st.d + (size_t)n * 8));
+    GSS_HIP(hipGetLastError());
+    c.stage_done(st);
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_observe(gss_ctx *ctx) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    GSS_REQUIRE(c.tested, GSS_ERR_STATE, "no test to observe");
+    GSS_REQUIRE(p.observed_serial != c.test_serial, GSS_ERR_STATE, "this test was already observed");
+    GSS_REQUIRE(!(c.last_flags & GSS_TEST_DENSE), GSS_ERR_STATE, "a dense test has no records to observe");
+    GSS_REQUIRE(c.n_kept == c.n_reports, GSS_ERR_REPORT_OVERFLOW, "the test lost records: its hits are incomplete");
+    if (c.last_waves)
+        hipLaunchKernelGGL(k_prio_hits, dim3(std::min<uint32_t>(c.last_waves, 65535)), dim3(256), 0, c.stream,
+                           args_of(p), c.reports, c.seg_counts, c.seg_cap, c.last_waves);
+    GSS_HIP(hipGetLastError());
+    if (p.n_ids)
+        hipLaunchKernelGGL(k_prio_observe, dim3(grid_of(p.n_ids)), dim3(256), 0, c.stream, args_of(p), p.n_ids, p.run,
+                           (c.last_flags & GSS_TEST_SCHEDULED) ? 1u : 0u, src_scale(p), p.cfg.sample_period,
+                           p.cfg.seed, p.sx, p.sy, p.cfg.sample_capacity, p.counters);
+    GSS_HIP(hipGetLastError());
+    p.observed_serial = c.test_serial;
+    p.run++;
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_train(gss_ctx *ctx, uint32_t epochs, const gss_adam_config *cfg, uint64_t seed,
+                                         float *out_loss) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(cfg && epochs >= 1 && cfg->batch >= 1 && cfg->lr > 0, GSS_ERR_INVALID_ARG, "bad training settings");
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    GSS_HIP(hipMemcpyAsync(p.h_counters, p.counters, 8, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    const uint64_t n = std::min<uint64_t>(p.h_counters[0], p.cfg.sample_capacity);
+    GSS_REQUIRE(n >= 1, GSS_ERR_STATE, "no training samples yet");
+    // epochs of seeded Fisher-Yates permutations
+    const uint64_t n_order = n * epochs;
+    std::vector<uint32_t> order(n_order);
+    uint64_t s = seed * 0xD1B54A32D192ED03ull + 7;
+    for (uint32_t e = 0; e < epochs; ++e) {
+        uint32_t *o = order.data() + (uint64_t)e * n;
+        for (uint64_t i = 0; i < n; ++i) o[i] = (uint32_t)i;
+        for (uint64_t i = n - 1; i > 0; --i) std::swap(o[i], o[splitmix(s) % (i + 1)]);
+    }
+    MlpWork &w = mlp_work(c);
+    c.sync();
+    char *st = mlp_stage(c, w, n_order * 4);
+    GSS_HIP(hipMemcpyAsync(st, order.data(), n_order * 4, hipMemcpyHostToDevice, c.stream));
+    GSS_HIP(hipMemcpyAsync(w.params, p.params, kParams * 4, hipMemcpyDeviceToDevice, c.stream));
+    launch_fill_u32(c, (uint32_t *)w.m, kParams, 0);
+    launch_fill_u32(c, (uint32_t *)w.v, kParams, 0);
+    w.step = 0;
+    for (uint64_t first = 0; first < n_order; first += cfg->batch) {
+        const uint32_t nb = (uint32_t)std::min<uint64_t>(cfg->batch, n_order - first);
+        mlp_queue_grad(c, w, p.sx, p.sy, (const uint32_t *)st, first, nb);
+        mlp_queue_adam(c, w, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps);
+    }
+    GSS_HIP(hipMemcpyAsync(p.params, w.params, kParams * 4, hipMemcpyDeviceToDevice, c.stream));
+    GSS_HIP(hipMemcpyAsync(w.h_loss, w.loss, 4, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    if (out_loss) *out_loss = *w.h_loss;
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_clear_samples(gss_ctx *ctx) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    launch_fill_u32(c, p.counters, 1, 0);
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_score(gss_ctx *ctx, float threshold, uint64_t *out_n_low) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(std::isfinite(threshold), GSS_ERR_INVALID_ARG, "threshold must be finite");
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    launch_fill_u32(c, p.counters + 1, 1, 0);
+    if (p.n_ids)
+        hipLaunchKernelGGL(k_prio_score, dim3(grid_of(p.n_ids)), dim3(256), 0, c.stream, args_of(p), p.params, p.n_ids,
+                           p.run, src_scale(p), threshold, p.counters);
+    GSS_HIP(hipGetLastError());
+    p.threshold = threshold;
+    p.score_epoch++;
+    if (out_n_low) {
+        GSS_HIP(hipMemcpyAsync(p.h_counters, p.counters, 8, hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+        *out_n_low = p.h_counters[1];
+    }
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_mark(gss_ctx *ctx, const uint8_t *low, uint64_t n) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(low, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE(n == p.n_ids, GSS_ERR_INVALID_ARG, "low must hold one flag per issued id");
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    launch_fill_u32(c, p.counters + 1, 1, 0);
+    if (n) {
+        MlpWork &w = mlp_work(c);
+        c.sync();
+        char *st = mlp_stage(c, w, n);
+        GSS_HIP(hipMemcpyAsync(st, low, n, hipMemcpyHostToDevice, c.stream));
+        hipLaunchKernelGGL(k_prio_mark, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), (const uint8_t *)st, n,
+                           p.counters);
+        GSS_HIP(hipGetLastError());
+        c.sync();
+    }
+    p.score_epoch++;
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_params(gss_ctx *ctx, float *get, const float *set) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    if (set) GSS_HIP(hipMemcpyAsync(p.params, set, kParams * 4, hipMemcpyHostToDevice, c.stream));
+    if (get) GSS_HIP(hipMemcpyAsync(get, p.params, kParams * 4, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_fetch(gss_ctx *ctx, const uint32_t *ids, uint32_t n, float *out_features,
+                                         float *out_scores, uint8_t *out_low) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    if (n == 0) return GSS_OK;
+    GSS_REQUIRE(ids && out_features && out_scores && out_low, GSS_ERR_INVALID_ARG, "null argument");
+    for (uint32_t i = 0; i < n; ++i)
+        GSS_REQUIRE(ids[i] < p.n_ids, GSS_ERR_UNKNOWN_ID, "clause id never issued");
+    MlpWork &w = mlp_work(c);
+    const size_t ib = ((size_t)n * 4 + 255) / 256 * 256, xb = ((size_t)n * kFeat * 4 + 255) / 256 * 256,
+                 sb = ((size_t)n * 4 + 255) / 256 * 256;
+    c.sync();
+    char *st = mlp_stage(c, w, ib + xb + sb + n);
+    GSS_HIP(hipMemcpyAsync(st, ids, (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
+    hipLaunchKernelGGL(k_prio_fetch, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), (const uint32_t *)st, n,
+                       p.run, src_scale(p), (float *)(st + ib), (float *)(st + ib + xb), (uint8_t *)(st + ib + xb + sb));
+    GSS_HIP(hipGetLastError());
+    GSS_HIP(hipMemcpyAsync(out_features, st + ib, (size_t)n * kFeat * 4, hipMemcpyDeviceToHost, c.stream));
+    GSS_HIP(hipMemcpyAsync(out_scores, st + ib + xb, (size_t)n * 4, hipMemcpyDeviceToHost, c.stream));
+    GSS_HIP(hipMemcpyAsync(out_low, st + ib + xb + sb, n, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_samples(gss_ctx *ctx, float *out_x, float *out_y, uint64_t cap, uint64_t *out_n) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(out_n, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_HIP(hipMemcpyAsync(p.h_counters, p.counters, 8, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    const uint64_t n = std::min<uint64_t>({(uint64_t)p.h_counters[0], p.cfg.sample_capacity, cap});
+    if (n && out_x) GSS_HIP(hipMemcpyAsync(out_x, p.sx, n * kFeat * 4, hipMemcpyDeviceToHost, c.stream));
+    if (n && out_y) GSS_HIP(hipMemcpyAsync(out_y, p.sy, n * 4, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    *out_n = n;
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_info(const gss_ctx *ctx, uint32_t *out_run, uint64_t *out_samples,
+                                        uint64_t *out_n_low) {
+    const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+    if (!c) return GSS_ERR_INVALID_ARG;
+    if (!c->prio) return GSS_ERR_STATE;
+    const Priority &p = *c->prio;
+    if (hipMemcpyAsync(p.h_counters, p.counters, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return GSS_ERR_DEVICE;
+    if (out_run) *out_run = p.run;
+    if (out_samples) *out_samples = std::min<uint64_t>(p.h_counters[0], p.cfg.sample_capacity);
+    if (out_n_low) *out_n_low = p.h_counters[1];
+    return GSS_OK;
+}

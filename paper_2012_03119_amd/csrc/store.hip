@@ -328,6 +328,7 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
     }
     c.live += n;
     c.version++;
+    priority_added(c, next, n, offsets);
     GSS_API_END
 }
 
@@ -384,6 +385,7 @@ extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint
         c.stage_done(st);
     }
     c.version++;
+    priority_removed(c, ids, n);
     // ---- reclaim: compact a class once more than a quarter of its slots are dead
     for (int b = 0; b < kMaxBuckets; ++b) {
         Bucket &B = c.buckets[b];

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
         __syncthreads();
     }
     const uint32_t lane = threadIdx.x & 63;
-    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows);
+    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, a.sched_run);
     const uint32_t waves_per_block = blockDim.x / 64;
     const uint32_t n_waves = gridDim.x * waves_per_block;
     // wave-uniform by construction; readfirstlane lets the compiler keep it in SGPRs
@@ -116,6 +116,8 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     TestArgs &a = L.args;
     BucketDesc *h = (BucketDesc *)c.hsmall_desc;
     uint32_t nb = 0, tiles = 0;
+    const bool sched = (flags & GSS_TEST_SCHEDULED) != 0;
+    a.sched_run = sched ? priority_schedule(c) : 0u;
     for (int b = 0; b < kMaxBuckets; ++b) {
         const Bucket &B = c.buckets[b];
         if (B.n_slots == 0 || B.n_dead == B.n_slots) continue;
@@ -126,6 +128,10 @@ static Launch prepare(Ctx &c, uint32_t flags) {
         d.meta_bytes = B.cap_slots * 8;
         d.stride_log2 = B.stride_log2;
         d.tile_begin = tiles;
+        if (sched) {
+            d.low = B.low;
+            d.low_bytes = B.low_words * 4;
+        }
         h[nb++] = d;
         tiles += (uint32_t)((B.n_slots + c.T - 1) / c.T);
     }
@@ -184,7 +190,7 @@ static void complete(Ctx &c) {
 // Checks flags and prepares a test; returns false when there is nothing to launch.
 static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
     const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_SORTED | GSS_TEST_DENSE |
-                           GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT;
+                           GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT | GSS_TEST_SCHEDULED;
     GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "unknown gss_test flag");
     GSS_REQUIRE(!(flags & GSS_TEST_SORTED), GSS_ERR_INVALID_ARG, "GSS_TEST_SORTED is not supported by this build");
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is already in flight (call gss_test_wait)");
@@ -251,6 +257,7 @@ static uint64_t end_test(Ctx &c, uint32_t flags, bool launched) {
         }
     }
     c.stats.tests_run++;
+    c.test_serial++;
     c.tested = true;
     c.last_flags = flags;
     if (flags & GSS_TEST_DENSE) n = kept = 0;

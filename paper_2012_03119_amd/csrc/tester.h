@@ -102,20 +102,23 @@ struct Tester {
         uint32_t code_off;
         uint2 meta;
         uint4 c0;
+        uint32_t lowword;   // schedule bits of the slot's 32-slot group (0: no schedule)
+        uint32_t lowshift;  // this slot's bit in it
     };
 
     uint32_t j;    // clause of this lane within the tile
     uint32_t w0;   // first word of this lane
     uint32_t W;    // words in use
     uint32_t hot_rows;
+    uint32_t sched_run;
     bool lane_ok;  // this lane owns at least one word in use
     uint64_t act[WPL];
     const char *pbase;
     const uint64_t *lds;
 
     __device__ Tester(uint32_t lane, const uint64_t *planes, const uint64_t *active, uint32_t W_, uint32_t hot_rows_,
-                      const uint64_t *lds_)
-        : j(lane / LPC), w0((lane % LPC) * WPL), W(W_), hot_rows(hot_rows_), lds(lds_) {
+                      const uint64_t *lds_, uint32_t sched_run_)
+        : j(lane / LPC), w0((lane % LPC) * WPL), W(W_), hot_rows(hot_rows_), sched_run(sched_run_), lds(lds_) {
         lane_ok = w0 < W;
 #pragma unroll
         for (int i = 0; i < WPL; ++i) act[i] = (w0 + i < W) ? active[w0 + i] : 0;
@@ -149,6 +152,9 @@ struct Tester {
         tl.meta = make_uint2(m[0], m[1]);
         const auto q = __builtin_amdgcn_raw_buffer_load_b128(tl.lits, tl.code_off, 0, 0);
         tl.c0 = make_uint4(q[0], q[1], q[2], q[3]);
+        tl.lowshift = slot & 31u;
+        tl.lowword = d.low ? __builtin_amdgcn_raw_buffer_load_b32(make_rsrc(d.low, d.low_bytes), (slot >> 5) * 4u, 0, 0)
+                           : 0u;
     }
 
     // Tests the clauses of an opened tile.  Records go to seg (capacity seg_cap)
@@ -156,7 +162,9 @@ struct Tester {
     // dense != nullptr, writes each clause's mask row there instead.
     __device__ uint32_t run(const Tile &cur, gss_report *seg, uint32_t seg_cap, uint32_t produced, uint32_t early_exit,
                             uint64_t *dense) const {
-        const uint32_t len = cur.meta.x;
+        // a low-priority clause sits out the runs where (run + id) % 4 != 0
+        const bool skip = ((cur.lowword >> cur.lowshift) & 1u) && ((sched_run + cur.meta.y) & 3u) != 0;
+        const uint32_t len = skip ? 0u : cur.meta.x;
         const uint32_t S = 1u << cur.s_log2;
         uint64_t af[WPL], ou[WPL];  // allFalse, oneUndef (trigger mode)
 #pragma unroll

@@ -89,6 +89,21 @@ class gss_schedule(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class gss_adam_config(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("batch", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+
+class gss_priority_config(ctypes.Structure):
+    _fields_ = [("n_sources", ctypes.c_uint32), ("sample_period", ctypes.c_uint32),
+                ("sample_capacity", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 4)]
+
+
+MLP_FEATURES = 12
+MLP_PARAMS = 5057
+GSS_TEST_SCHEDULED = 128
+
+
 class gss_server_config(ctypes.Structure):
     _fields_ = [("n_producers", ctypes.c_uint32), ("test_flags", ctypes.c_uint32),
                 ("delete_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
@@ -158,6 +173,20 @@ def load_library(path: Optional[str] = None):
         "gss_batch_set_schedule": ([P, ctypes.POINTER(gss_schedule)], ctypes.c_int32),
         "gss_batch_test": ([P, u32, P], ctypes.c_int32),
         "gss_batch_info": ([P, P, P, P, P], ctypes.c_int32),
+        "gss_mlp_forward": ([P, P, P, u32, P], ctypes.c_int32),
+        "gss_mlp_loss_grad": ([P, P, P, P, u32, P, P], ctypes.c_int32),
+        "gss_mlp_train": ([P, P, P, P, u32, P, u64, ctypes.POINTER(gss_adam_config), P], ctypes.c_int32),
+        "gss_priority_enable": ([P, ctypes.POINTER(gss_priority_config)], ctypes.c_int32),
+        "gss_priority_set_clause_info": ([P, P, u32, P, P], ctypes.c_int32),
+        "gss_priority_observe": ([P], ctypes.c_int32),
+        "gss_priority_train": ([P, u32, ctypes.POINTER(gss_adam_config), u64, P], ctypes.c_int32),
+        "gss_priority_clear_samples": ([P], ctypes.c_int32),
+        "gss_priority_score": ([P, ctypes.c_float, P], ctypes.c_int32),
+        "gss_priority_params": ([P, P, P], ctypes.c_int32),
+        "gss_priority_mark": ([P, P, u64], ctypes.c_int32),
+        "gss_priority_fetch": ([P, P, u32, P, P, P], ctypes.c_int32),
+        "gss_priority_samples": ([P, P, P, u64, P], ctypes.c_int32),
+        "gss_priority_info": ([P, P, P, P], ctypes.c_int32),
         "gss_server_start": ([P, ctypes.POINTER(gss_server_config), ctypes.POINTER(P)], ctypes.c_int32),
         "gss_server_send": ([P, u32, u32, P, P, P], ctypes.c_int32),
         "gss_server_insert": ([P, u32, P, P, u32], ctypes.c_int32),
@@ -367,6 +396,55 @@ def gss_batch_info(b) -> dict:
     return dict(last_ms=ms.value, launches=la.value, captures=ca.value, tiles=ti.value)
 
 
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def gss_mlp_forward(ctx, params, x) -> np.ndarray:
+    p = _f32(params, (MLP_PARAMS,))
+    x = _f32(x)
+    n = x.shape[0]
+    if x.shape != (n, MLP_FEATURES):
+        raise ValueError("x must be [n][12]")
+    out = np.zeros(n, dtype=np.float32)
+    _check(ctx, load_library().gss_mlp_forward(ctx, _np_ptr(p), _np_ptr(x), n, _np_ptr(out)))
+    return out
+
+
+def gss_mlp_loss_grad(ctx, params, x, y):
+    p = _f32(params, (MLP_PARAMS,))
+    x, y = _f32(x), _f32(y)
+    n = x.shape[0]
+    if x.shape != (n, MLP_FEATURES) or y.shape != (n,):
+        raise ValueError("x must be [n][12] and y [n]")
+    loss = ctypes.c_float()
+    g = np.zeros(MLP_PARAMS, dtype=np.float32)
+    _check(ctx, load_library().gss_mlp_loss_grad(ctx, _np_ptr(p), _np_ptr(x), _np_ptr(y), n, ctypes.byref(loss),
+                                                 _np_ptr(g)))
+    return loss.value, g
+
+
+def _adam(lr, beta1, beta2, eps, batch):
+    return gss_adam_config(lr, beta1, beta2, eps, batch)
+
+
+def gss_mlp_train(ctx, params, x, y, order, *, batch: int, lr: float = 1e-3, beta1: float = 0.9,
+                  beta2: float = 0.999, eps: float = 1e-8):
+    """(trained parameters, per-step losses)."""
+    p = _f32(params, (MLP_PARAMS,)).copy()
+    x, y = _f32(x), _f32(y)
+    order = np.ascontiguousarray(order, dtype=np.uint32)
+    cfg = _adam(lr, beta1, beta2, eps, batch)
+    steps = (order.size + batch - 1) // batch
+    losses = np.zeros(max(steps, 1), dtype=np.float32)
+    _check(ctx, load_library().gss_mlp_train(ctx, _np_ptr(p), _np_ptr(x), _np_ptr(y), x.shape[0], _np_ptr(order),
+                                             order.size, ctypes.byref(cfg), _np_ptr(losses)))
+    return p, losses[:steps]
+
+
 def gss_server_start(ctx, n_producers: int, *, test_flags: int = 0, delete_fraction: float = 0.0, seed: int = 0,
                      log_path: Optional[str] = None, max_queued_lits: int = 0):
     cfg = gss_server_config(n_producers, test_flags, delete_fraction, seed,
@@ -549,6 +627,71 @@ class Context:
     @property
     def stream(self) -> int:
         return gss_get_stream(self.ctx)
+
+    # -- learned priority
+    def priority_enable(self, *, n_sources: int = 1, sample_period: int = 0, sample_capacity: int = 0,
+                        seed: int = 0) -> None:
+        cfg = gss_priority_config(n_sources, sample_period, sample_capacity, seed)
+        _check(self.ctx, load_library().gss_priority_enable(self.ctx, ctypes.byref(cfg)))
+
+    def priority_set_clause_info(self, ids, lbd, source) -> None:
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        lbd = _f32(lbd, ids.shape)
+        source = np.ascontiguousarray(source, dtype=np.uint32)
+        _check(self.ctx, load_library().gss_priority_set_clause_info(self.ctx, _np_ptr(ids), ids.size, _np_ptr(lbd),
+                                                                     _np_ptr(source)))
+
+    def priority_observe(self) -> None:
+        _check(self.ctx, load_library().gss_priority_observe(self.ctx))
+
+    def priority_train(self, epochs: int, *, batch: int = 1024, lr: float = 1e-3, beta1: float = 0.9,
+                       beta2: float = 0.999, eps: float = 1e-8, seed: int = 0) -> float:
+        cfg = _adam(lr, beta1, beta2, eps, batch)
+        loss = ctypes.c_float()
+        _check(self.ctx, load_library().gss_priority_train(self.ctx, epochs, ctypes.byref(cfg), seed,
+                                                           ctypes.byref(loss)))
+        return loss.value
+
+    def priority_clear_samples(self) -> None:
+        _check(self.ctx, load_library().gss_priority_clear_samples(self.ctx))
+
+    def priority_score(self, threshold: float) -> int:
+        n = ctypes.c_uint64()
+        _check(self.ctx, load_library().gss_priority_score(self.ctx, ctypes.c_float(threshold), ctypes.byref(n)))
+        return n.value
+
+    def priority_mark(self, low) -> None:
+        low = np.ascontiguousarray(low, dtype=np.uint8)
+        _check(self.ctx, load_library().gss_priority_mark(self.ctx, _np_ptr(low), low.size))
+
+    def priority_params(self, set_to=None) -> np.ndarray:
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        src = _f32(set_to, (MLP_PARAMS,)) if set_to is not None else None
+        _check(self.ctx, load_library().gss_priority_params(self.ctx, _np_ptr(out),
+                                                            _np_ptr(src) if src is not None else None))
+        return out
+
+    def priority_fetch(self, ids):
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        x = np.zeros((ids.size, MLP_FEATURES), dtype=np.float32)
+        sc = np.zeros(ids.size, dtype=np.float32)
+        low = np.zeros(ids.size, dtype=np.uint8)
+        _check(self.ctx, load_library().gss_priority_fetch(self.ctx, _np_ptr(ids), ids.size, _np_ptr(x), _np_ptr(sc),
+                                                           _np_ptr(low)))
+        return x, sc, low.astype(bool)
+
+    def priority_samples(self, cap: int):
+        x = np.zeros((max(cap, 1), MLP_FEATURES), dtype=np.float32)
+        y = np.zeros(max(cap, 1), dtype=np.float32)
+        n = ctypes.c_uint64()
+        _check(self.ctx, load_library().gss_priority_samples(self.ctx, _np_ptr(x), _np_ptr(y), cap, ctypes.byref(n)))
+        return x[:n.value], y[:n.value]
+
+    def priority_info(self) -> dict:
+        r, s_, lo = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.ctx, load_library().gss_priority_info(self.ctx, ctypes.byref(r), ctypes.byref(s_),
+                                                          ctypes.byref(lo)))
+        return dict(run=r.value, samples=s_.value, n_low=lo.value)
 
     def serve_simulate(self, **kw) -> dict:
         """Runs the served workload generator on this context (gss_serve_simulate)."""

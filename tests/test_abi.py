@@ -73,7 +73,8 @@ def test_create_rejects_bad_config_without_device(lib_path):
         assert lib.gss_last_error(None)
 
 
-STRUCTS = ["gss_config", "gss_stats", "gss_schedule", "gss_server_config", "gss_serve_result", "gss_sim_config"]
+STRUCTS = ["gss_config", "gss_stats", "gss_schedule", "gss_server_config", "gss_serve_result", "gss_sim_config",
+           "gss_adam_config", "gss_priority_config"]
 
 
 def test_struct_layouts_match_header(tmp_path):
