@@ -154,7 +154,8 @@ void gss_server::run() {
     uint64_t rng = cfg.seed * 0x2545F4914F6CDD1Dull + 11;
     std::vector<double> staged(P, -1.0), inflight(P, -1.0);  // arrival of the untested / tested snapshot
     std::vector<std::vector<gss_report>> route(P);
-    std::vector<gss_report> rec;
+    gss_report *rec = nullptr;  // pinned: the records of a run come back at full link speed
+    uint64_t rec_cap = 0;
     std::vector<uint64_t> act(C.W, 0);
     struct Taken {
         uint32_t p;
@@ -337,10 +338,17 @@ void gss_server::run() {
                 }
             return;
         }
-        rec.resize(std::max<uint64_t>(n, 1));
+        if (n > rec_cap) {
+            if (rec) (void)hipHostFree(rec);
+            rec = nullptr;
+            rec_cap = 0;
+            const uint64_t want = n + n / 4 + 1024;
+            GSS_HIP(hipHostMalloc((void **)&rec, want * sizeof(gss_report), hipHostMallocDefault));
+            rec_cap = want;
+        }
         uint64_t got = 0;
         gss_status rf = GSS_OK;
-        timed(res.fetch_ms, [&] { rf = gss_fetch_reports(ctx, rec.data(), n, &got); });
+        timed(res.fetch_ms, [&] { rf = gss_fetch_reports(ctx, rec, n, &got); });
         if (rf != GSS_OK) throw Error(rf, C.last_error);
         const double route_t0 = now();
         for (auto &r : route) r.clear();
@@ -435,6 +443,7 @@ void gss_server::run() {
         (void)gss_test_wait(ctx, &n);
     }
     (void)hipStreamSynchronize(C.stream);
+    if (rec) (void)hipHostFree(rec);
     res.gpu_ms = C.stats.total_kernel_ms - kernel_ms0;
 }
 

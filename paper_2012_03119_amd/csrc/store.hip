@@ -12,6 +12,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <thread>
 
 namespace gss {
 
@@ -79,6 +81,22 @@ static uint64_t bucket_bytes(uint64_t cap_slots, uint32_t stride_log2) {
 }
 
 static uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+
+// Runs fn(begin, end) over [0, n) split across host threads when the work
+// (weight: literals) is large enough to pay for them.
+template <typename F>
+static void host_parallel(uint64_t n, uint64_t weight, F fn) {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned k = (unsigned)std::min<uint64_t>({hw, n, weight / (1u << 16) + 1});
+    if (k <= 1) {
+        fn((uint64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(k);
+    for (unsigned t = 0; t < k; ++t) th.emplace_back(fn, n * t / k, n * (t + 1) / k);
+    for (auto &x : th) x.join();
+}
 
 // Fills a meta array with empty slots (length 0, dead id).
 static void fill_meta(Ctx &c, uint2 *meta, uint64_t n) {
@@ -178,17 +196,41 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         const uint64_t L = offsets[i + 1] - offsets[i];
         GSS_REQUIRE(L >= 1, GSS_ERR_INVALID_ARG, "empty clause at index " + std::to_string(i));
         GSS_REQUIRE(L <= kMaxClauseLen, GSS_ERR_INVALID_ARG, "clause longer than 65536 literals at index " + std::to_string(i));
-        uint32_t lo = ~0u;
-        for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
-            int64_t l = lits[k];
-            int64_t v = l < 0 ? -l : l;
-            GSS_REQUIRE(v >= 1 && v <= V, GSS_ERR_BAD_LITERAL,
-                        "literal " + std::to_string(l) + " of clause " + std::to_string(i) + " is 0 or beyond num_vars");
-            lo = std::min(lo, lit_code((int32_t)l));
-        }
-        lead[i] = lo;
         cls[i] = (uint8_t)length_class((uint32_t)L);
         add[cls[i]]++;
+    }
+    {
+        // literals: in range, and the lead code; the first bad clause wins
+        std::vector<uint64_t> first_bad(n ? 1 : 0, ~0ull);
+        std::mutex mu;
+        host_parallel(n, offsets[n] - offsets[0], [&](uint64_t b, uint64_t e) {
+            for (uint64_t i = b; i < e; ++i) {
+                uint32_t lo = ~0u;
+                bool ok = true;
+                for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+                    const int64_t l = lits[k];
+                    const int64_t v = l < 0 ? -l : l;
+                    ok &= v >= 1 && v <= V;
+                    lo = std::min(lo, lit_code((int32_t)l));
+                }
+                lead[i] = lo;
+                if (!ok) {
+                    std::lock_guard<std::mutex> g(mu);
+                    first_bad[0] = std::min<uint64_t>(first_bad[0], i);
+                    return;
+                }
+            }
+        });
+        if (n && first_bad[0] != ~0ull) {
+            const uint64_t i = first_bad[0];
+            for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+                const int64_t l = lits[k];
+                const int64_t v = l < 0 ? -l : l;
+                GSS_REQUIRE(v >= 1 && v <= V, GSS_ERR_BAD_LITERAL,
+                            "literal " + std::to_string(l) + " of clause " + std::to_string(i) +
+                                " is 0 or beyond num_vars");
+            }
+        }
     }
 
     // ---- order the batch by bucket, and inside a bucket by lead code: clauses a
@@ -297,9 +339,6 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
             const uint32_t i = order[p + r];
             const uint64_t L = offsets[i + 1] - offsets[i];
             hcoff[r] = off;
-            uint32_t *dst = hcodes + off;
-            for (uint64_t k = 0; k < L; ++k) dst[k] = lit_code(lits[offsets[i] + k]);
-            std::sort(dst, dst + L);
             off += L;
             const uint32_t id = (uint32_t)(next + i);
             hids[r] = id;
@@ -309,6 +348,16 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
             B.h_len[slot] = (uint32_t)L;
         }
         hcoff[m] = off;
+        // codes of every clause, sorted ascending
+        host_parallel(m, nl, [&](uint64_t rb, uint64_t re) {
+            for (uint64_t r = rb; r < re; ++r) {
+                const uint32_t i = order[p + r];
+                const uint64_t L = offsets[i + 1] - offsets[i];
+                uint32_t *dst = hcodes + hcoff[r];
+                for (uint64_t k = 0; k < L; ++k) dst[k] = lit_code(lits[offsets[i] + k]);
+                std::sort(dst, dst + L);
+            }
+        });
         GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
         const uint32_t *dcodes = (const uint32_t *)d;
         const uint64_t *dcoff = (const uint64_t *)(d + codes_bytes);
