@@ -72,7 +72,7 @@ inline int length_class(uint32_t len) {
 // ---------------------------------------------------------------------------
 
 // One length class of the clause store as the test kernel sees it.  Slot s holds
-// its clause's codes at lits[s * S + k] (k < S, sorted, padded with code 0), so a
+// its clause's codes at lits[s * S + k] (k < S, lead first, padded with code 0), so a
 // lane reads four codes with one 16-byte load.  A tile is T consecutive slots
 // (T = 64 / lanes-per-clause): the clauses one wavefront tests together.
 struct BucketDesc {
@@ -228,6 +228,28 @@ void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value);
 bool is_device_pointer(const void *p);
 const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n);
 void check_flag(Ctx &c);
+// Clause ingest in two parts.  prepare_clauses validates DIMACS clauses and
+// encodes them (codes 2v+neg, the lead -- smallest code -- first, the length
+// class and lead of each clause); it touches no context and may run on any
+// thread.  commit_clauses assigns ids in batch order and uploads the batch, laid
+// out by length class and lead.  Both throw Error.
+struct Prepared {
+    std::vector<uint32_t> codes;
+    std::vector<uint64_t> offs{0};
+    std::vector<uint32_t> lead;
+    std::vector<uint8_t> cls;
+    uint32_t size() const { return (uint32_t)lead.size(); }
+    void clear() {
+        codes.clear();
+        offs.assign(1, 0);
+        lead.clear();
+        cls.clear();
+    }
+    void append(const Prepared &o);
+};
+void prepare_clauses(int64_t num_vars, const int32_t *lits, const uint64_t *offsets, uint32_t n, Prepared &out);
+void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids);
+
 // learned priority hooks: clauses added (ids first..first+n, lengths from offsets),
 // clauses removed (host ids), the schedule bits of every class (for a scheduled
 // test; returns the run number), and release of everything

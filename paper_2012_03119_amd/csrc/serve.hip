@@ -8,9 +8,10 @@
 // Data path of one snapshot:
 //   producer thread: merges the delta into its open mailbox (pinned host memory;
 //     a variable sent twice keeps its last value)
-//   manager: takes the mailbox (swapping in a free one), copies it to the device
-//     on a copy stream while the current run still executes, and queues the
-//     plane update on the context stream behind that run
+//   manager: takes the mailbox (swapping in a free one) and copies it to the
+//     device on a copy stream while the current run still executes; once that
+//     run's records are fetched, it queues the plane update (behind the copy) and
+//     launches the next run
 //   next run: tests every word with a new snapshot; its records are routed by
 //     word to the producers' queues, which is when the snapshot is notified.
 //
@@ -42,7 +43,8 @@ struct Mail {
     char *d = nullptr;
     uint32_t dcap = 0;
     hipEvent_t done = nullptr;  // recorded after the kernel that read d
-    bool busy = false;
+    bool busy = false;          // uploaded or applied, until `done` completes
+    bool queued = false;        // uploaded, plane update not queued yet (`done` not recorded)
 
     static size_t vbytes(uint32_t cap) { return ((size_t)cap * 4 + 255) / 256 * 256; }
     static size_t bytes(uint32_t cap) { return vbytes(cap) + (size_t)cap * 16; }
@@ -115,10 +117,10 @@ struct gss_server {
     hipEvent_t ev_copied = nullptr;
     FILE *log = nullptr;
 
-    // inserts waiting for admission
+    // inserts waiting for admission, already validated and encoded by the
+    // producer threads that sent them
     std::mutex imu;
-    std::vector<int32_t> q_lits;
-    std::vector<uint64_t> q_off{0};
+    Prepared queue;
     uint64_t q_limit = 0;
 
     std::atomic<bool> stop{false};
@@ -162,8 +164,7 @@ void gss_server::run() {
         Mail *m;
     };
     std::vector<Taken> taken;
-    std::vector<int32_t> ins_lits;
-    std::vector<uint64_t> ins_off{0};
+    Prepared ins;
     std::vector<uint32_t> ids;
     bool held = false;  // inserts held back by the HBM budget until something is removed
     bool pending = false;
@@ -177,8 +178,8 @@ void gss_server::run() {
     };
 
     auto admit = [&]() {
-        // ---- snapshots: take every producer's open mailbox that holds any
-        taken.clear();
+        // ---- snapshots: take every producer's open mailbox that holds any and
+        //      start its upload (the plane update itself waits for the next launch)
         for (uint32_t p = 0; p < P; ++p) {
             Producer &pr = prod[p];
             Mail *m = nullptr;
@@ -191,6 +192,7 @@ void gss_server::run() {
                 for (int k = 0; k < kMails && free_k < 0; ++k) {
                     if (k == pr.open) continue;
                     Mail &x = pr.mail[k];
+                    if (x.queued) continue;
                     if (x.busy) {
                         const hipError_t e = hipEventQuery(x.done);
                         if (e == hipErrorNotReady) continue;
@@ -199,7 +201,7 @@ void gss_server::run() {
                     }
                     free_k = k;
                 }
-                if (free_k < 0) continue;  // both queued: keep merging into the open one
+                if (free_k < 0) continue;  // both in use: keep merging into the open one
                 m = &pr.mail[pr.open];
                 pr.open = free_k;
                 pr.mail[free_k].n = 0;
@@ -224,10 +226,16 @@ void gss_server::run() {
                                    copy_stream));
             res.delta_bytes += (uint64_t)m->n * 20;
             m->busy = true;
+            m->queued = true;
             taken.push_back({p, m});
         }
+    };
+
+    // Plane updates of the uploaded deltas, queued right before a launch: queued
+    // earlier, they would sit behind the copies between the running test and the
+    // fetch of its records.
+    auto apply_deltas = [&]() {
         if (!taken.empty()) {
-            // the plane updates wait for the copies, and run after the test in flight
             GSS_HIP(hipEventRecord(ev_copied, copy_stream));
             GSS_HIP(hipStreamWaitEvent(C.stream, ev_copied, 0));
             for (const Taken &x : taken) {
@@ -236,6 +244,7 @@ void gss_server::run() {
                 launch_set_words(C, x.p, (const uint32_t *)m.d, (const uint64_t *)(m.d + vb),
                                  (const uint64_t *)(m.d + vb) + m.dcap, m.n);
                 GSS_HIP(hipEventRecord(m.done, C.stream));
+                m.queued = false;
                 if (log) {
                     std::fprintf(log, "W %u %u\n", x.p, m.n);
                     const uint32_t *v = m.vars();
@@ -244,6 +253,7 @@ void gss_server::run() {
                         std::fprintf(log, "%u %llx %llx\n", v[i], (unsigned long long)f[i], (unsigned long long)t[i]);
                 }
             }
+            taken.clear();
         }
     };
 
@@ -278,38 +288,40 @@ void gss_server::run() {
         if (!held) {
             {
                 std::lock_guard<std::mutex> g(imu);
-                ins_lits.swap(q_lits);
-                ins_off.swap(q_off);
-                q_lits.clear();
-                q_off.assign(1, 0);
+                std::swap(ins, queue);
+                queue.clear();
             }
-            const uint32_t n = (uint32_t)ins_off.size() - 1;
+            const uint32_t n = ins.size();
             if (n) {
                 ids.resize(n);
-                const gss_status rc = gss_add_clauses(ctx, ins_lits.data(), ins_off.data(), n, ids.data());
-                if (rc == GSS_OK) {
+                bool admitted = true;
+                try {
+                    commit_clauses(C, ins, ids.data());
+                } catch (const Error &e) {
+                    if (e.code != GSS_ERR_CAPACITY) throw;
+                    admitted = false;
+                }
+                if (admitted) {
                     res.inserted += n;
                     live.insert(live.end(), ids.begin(), ids.end());
                     if (log)
                         for (uint32_t i = 0; i < n; ++i) {
-                            std::fprintf(log, "A %u %llu", ids[i], (unsigned long long)(ins_off[i + 1] - ins_off[i]));
-                            for (uint64_t k = ins_off[i]; k < ins_off[i + 1]; ++k) std::fprintf(log, " %d", ins_lits[k]);
+                            std::fprintf(log, "A %u %llu", ids[i], (unsigned long long)(ins.offs[i + 1] - ins.offs[i]));
+                            for (uint64_t k = ins.offs[i]; k < ins.offs[i + 1]; ++k) {
+                                const uint32_t code = ins.codes[k];
+                                std::fprintf(log, " %d", (code & 1) ? -(int32_t)(code >> 1) : (int32_t)(code >> 1));
+                            }
                             std::fputc('\n', log);
                         }
-                } else if (rc == GSS_ERR_CAPACITY) {
+                    ins.clear();
+                } else {
                     // budget full: back in front of what arrived since, until a removal
                     held = true;
                     std::lock_guard<std::mutex> g(imu);
-                    const uint64_t base = ins_lits.size();
-                    ins_lits.insert(ins_lits.end(), q_lits.begin(), q_lits.end());
-                    for (size_t k = 1; k < q_off.size(); ++k) ins_off.push_back(base + q_off[k]);
-                    q_lits.swap(ins_lits);
-                    q_off.swap(ins_off);
-                } else {
-                    throw Error(rc, C.last_error);
+                    ins.append(queue);
+                    std::swap(ins, queue);
+                    ins.clear();
                 }
-                ins_lits.clear();
-                ins_off.assign(1, 0);
             }
         }
     };
@@ -415,6 +427,7 @@ void gss_server::run() {
                 continue;
             }
             const double launch_t0 = now();
+            apply_deltas();
             gss_status rc = gss_set_active(ctx, act.data());
             if (rc != GSS_OK) throw Error(rc, C.last_error);
             if (log) {
@@ -563,20 +576,14 @@ extern "C" gss_status gss_server_insert(gss_server *s, uint32_t producer, const 
     GSS_REQUIRE(lits && offsets, GSS_ERR_INVALID_ARG, "null argument");
     GSS_REQUIRE(offsets[0] == 0, GSS_ERR_INVALID_ARG, "offsets[0] must be 0");
     const int64_t V = s->V;
-    for (uint32_t i = 0; i < n; ++i) {
-        GSS_REQUIRE(offsets[i + 1] > offsets[i] && offsets[i + 1] - offsets[i] <= kMaxClauseLen, GSS_ERR_INVALID_ARG,
-                    "clause length must be 1..65536");
-        for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k)
-            GSS_REQUIRE(lits[k] != 0 && lits[k] >= -V && lits[k] <= V, GSS_ERR_BAD_LITERAL, "literal out of range");
-    }
+    Prepared p;  // validation and encoding here, on the producer's thread
+    prepare_clauses(V, lits, offsets, n, p);
     std::lock_guard<std::mutex> g(s->imu);
-    if (s->q_lits.size() + offsets[n] > s->q_limit) {
+    if (s->queue.codes.size() + p.codes.size() > s->q_limit) {
         s->n_refused += n;
         throw Error(GSS_ERR_CAPACITY, "insert queue full");
     }
-    const uint64_t base = s->q_lits.size();
-    s->q_lits.insert(s->q_lits.end(), lits, lits + offsets[n]);
-    for (uint32_t i = 1; i <= n; ++i) s->q_off.push_back(base + offsets[i]);
+    s->queue.append(p);
     GSS_SRV_END(s)
 }
 

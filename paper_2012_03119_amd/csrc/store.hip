@@ -2,12 +2,12 @@
 // deletion and compaction.
 //
 // Layout (per length class b, stride S = 2^b codes, S >= 4): slot s holds its
-// clause at lits[s * S .. s * S + S), codes sorted and padded with code 0, so the
-// test kernel reads four codes per 16-byte load; a tile is T consecutive slots (T
-// = 64 / lanes-per-clause), one wavefront's share.  Literals of a clause are kept
-// sorted by code (variable order):
-// the order does not change the result, and it concentrates the first literals of
-// long clauses -- the ones the early exit actually reads -- on low variable rows.
+// clause at lits[s * S .. s * S + S), padded with code 0, so the test kernel reads
+// four codes per 16-byte load; a tile is T consecutive slots (T = 64 /
+// lanes-per-clause), one wavefront's share.  A clause's smallest code (its lead)
+// comes first and the clauses of a batch are laid out by lead, so neighbouring
+// clauses start on the same plane row; the order of the other codes does not
+// change the result (a full sort measured no faster and costs O(L log L)).
 #include "gss_internal.h"
 
 #include <algorithm>
@@ -87,7 +87,7 @@ static uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 template <typename F>
 static void host_parallel(uint64_t n, uint64_t weight, F fn) {
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    const unsigned k = (unsigned)std::min<uint64_t>({hw, n, weight / (1u << 16) + 1});
+    const unsigned k = (unsigned)std::min<uint64_t>({hw, n, weight / (1u << 20) + 1});
     if (k <= 1) {
         fn((uint64_t)0, n);
         return;
@@ -172,67 +172,79 @@ static bool compact_bucket(Ctx &c, int bi) {
     return true;
 }
 
-}  // namespace gss
-
-using namespace gss;
-
-extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const uint64_t *offsets, uint32_t n,
-                                      uint32_t *out_ids) {
-    GSS_API_BEGIN(ctx)
-    c_->mutations++;  // a test in flight no longer sees the current state
-    Ctx &c = *c_;
-    if (n == 0) return GSS_OK;
-    GSS_REQUIRE(lits && offsets && out_ids, GSS_ERR_INVALID_ARG, "null argument");
-    const uint64_t next = c.id_loc.size();
-    GSS_REQUIRE(next + n < (uint64_t)kDeadId, GSS_ERR_CAPACITY, "clause id space exhausted");
-
-    // ---- validate everything first
-    std::vector<uint8_t> cls(n);
-    std::vector<uint32_t> lead(n);  // smallest literal code of each clause
-    uint64_t add[kMaxBuckets] = {0};
-    const int64_t V = c.cfg.num_vars;
+// ---- ingest, part 1: validation and encoding (no context state; any thread)
+void prepare_clauses(int64_t num_vars, const int32_t *lits, const uint64_t *offsets, uint32_t n, Prepared &p) {
+    p.clear();
+    if (n == 0) return;
+    GSS_REQUIRE(lits && offsets, GSS_ERR_INVALID_ARG, "null argument");
+    p.cls.resize(n);
+    p.lead.resize(n);
+    p.offs.resize((size_t)n + 1);
+    p.offs[0] = 0;
     for (uint32_t i = 0; i < n; ++i) {
         GSS_REQUIRE(offsets[i + 1] >= offsets[i], GSS_ERR_INVALID_ARG, "offsets must be non-decreasing");
         const uint64_t L = offsets[i + 1] - offsets[i];
         GSS_REQUIRE(L >= 1, GSS_ERR_INVALID_ARG, "empty clause at index " + std::to_string(i));
-        GSS_REQUIRE(L <= kMaxClauseLen, GSS_ERR_INVALID_ARG, "clause longer than 65536 literals at index " + std::to_string(i));
-        cls[i] = (uint8_t)length_class((uint32_t)L);
-        add[cls[i]]++;
+        GSS_REQUIRE(L <= kMaxClauseLen, GSS_ERR_INVALID_ARG,
+                    "clause longer than 65536 literals at index " + std::to_string(i));
+        p.cls[i] = (uint8_t)length_class((uint32_t)L);
+        p.offs[i + 1] = p.offs[i] + L;
     }
-    {
-        // literals: in range, and the lead code; the first bad clause wins
-        std::vector<uint64_t> first_bad(n ? 1 : 0, ~0ull);
-        std::mutex mu;
-        host_parallel(n, offsets[n] - offsets[0], [&](uint64_t b, uint64_t e) {
-            for (uint64_t i = b; i < e; ++i) {
-                uint32_t lo = ~0u;
-                bool ok = true;
-                for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
-                    const int64_t l = lits[k];
-                    const int64_t v = l < 0 ? -l : l;
-                    ok &= v >= 1 && v <= V;
-                    lo = std::min(lo, lit_code((int32_t)l));
-                }
-                lead[i] = lo;
-                if (!ok) {
-                    std::lock_guard<std::mutex> g(mu);
-                    first_bad[0] = std::min<uint64_t>(first_bad[0], i);
-                    return;
-                }
-            }
-        });
-        if (n && first_bad[0] != ~0ull) {
-            const uint64_t i = first_bad[0];
-            for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
-                const int64_t l = lits[k];
+    p.codes.resize(p.offs[n]);
+    // literals in range; codes with the lead (smallest) first; the first bad clause wins
+    uint64_t first_bad = ~0ull;
+    std::mutex mu;
+    host_parallel(n, p.offs[n], [&](uint64_t b, uint64_t e) {
+        for (uint64_t i = b; i < e; ++i) {
+            const uint64_t L = offsets[i + 1] - offsets[i];
+            uint32_t *dst = p.codes.data() + p.offs[i];
+            bool ok = true;
+            for (uint64_t k = 0; k < L; ++k) {
+                const int64_t l = lits[offsets[i] + k];
                 const int64_t v = l < 0 ? -l : l;
-                GSS_REQUIRE(v >= 1 && v <= V, GSS_ERR_BAD_LITERAL,
-                            "literal " + std::to_string(l) + " of clause " + std::to_string(i) +
-                                " is 0 or beyond num_vars");
+                ok &= v >= 1 && v <= num_vars;
+                dst[k] = lit_code((int32_t)l);
             }
+            if (!ok) {
+                std::lock_guard<std::mutex> g(mu);
+                first_bad = std::min<uint64_t>(first_bad, i);
+                return;
+            }
+            std::nth_element(dst, dst, dst + L);
+            p.lead[i] = dst[0];
+        }
+    });
+    if (first_bad != ~0ull) {
+        const uint64_t i = first_bad;
+        for (uint64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            const int64_t l = lits[k];
+            const int64_t v = l < 0 ? -l : l;
+            GSS_REQUIRE(v >= 1 && v <= num_vars, GSS_ERR_BAD_LITERAL,
+                        "literal " + std::to_string(l) + " of clause " + std::to_string(i) + " is 0 or beyond num_vars");
         }
     }
+}
 
+void Prepared::append(const Prepared &o) {
+    const uint64_t base = codes.size();
+    codes.insert(codes.end(), o.codes.begin(), o.codes.end());
+    for (size_t i = 1; i < o.offs.size(); ++i) offs.push_back(base + o.offs[i]);
+    lead.insert(lead.end(), o.lead.begin(), o.lead.end());
+    cls.insert(cls.end(), o.cls.begin(), o.cls.end());
+}
+
+// ---- ingest, part 2: ids, order, growth and upload
+void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
+    const uint32_t n = p.size();
+    if (n == 0) return;
+    c.mutations++;  // a test in flight no longer sees the current state
+    const uint64_t next = c.id_loc.size();
+    GSS_REQUIRE(next + n < (uint64_t)kDeadId, GSS_ERR_CAPACITY, "clause id space exhausted");
+    const std::vector<uint8_t> &cls = p.cls;
+    const std::vector<uint32_t> &lead = p.lead;
+    const std::vector<uint64_t> &offsets = p.offs;
+    uint64_t add[kMaxBuckets] = {0};
+    for (uint32_t i = 0; i < n; ++i) add[cls[i]]++;
     // ---- order the batch by bucket, and inside a bucket by lead code: clauses a
     //      wavefront (and an XCD) tests at the same time then share the plane row
     //      of their first literal, the one every clause reads in full.  Then cut
@@ -254,23 +266,23 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
     std::vector<uint64_t> chunk_lits;
     size_t stage_bytes = 0;
     {
-        uint32_t p = 0;
-        while (p < n) {
-            const int b = cls[order[p]];
-            uint32_t q = p;
+        uint32_t a = 0;
+        while (a < n) {
+            const int b = cls[order[a]];
+            uint32_t q = a;
             uint64_t nl = 0;
-            while (q < n && cls[order[q]] == b && (q - p) < kChunkClauses) {
+            while (q < n && cls[order[q]] == b && (q - a) < kChunkClauses) {
                 const uint32_t i = order[q];
                 const uint64_t L = offsets[i + 1] - offsets[i];
-                if (q > p && nl + L > kChunkLits) break;
+                if (q > a && nl + L > kChunkLits) break;
                 nl += L;
                 ++q;
             }
             cuts.push_back(q);
             chunk_lits.push_back(nl);
-            stage_bytes = std::max<size_t>(stage_bytes, round_up(nl * 4, 256) + round_up((uint64_t)(q - p + 1) * 8, 256) +
-                                                            round_up((uint64_t)(q - p) * 4, 256));
-            p = q;
+            stage_bytes = std::max<size_t>(stage_bytes, round_up(nl * 4, 256) + round_up((uint64_t)(q - a + 1) * 8, 256) +
+                                                            round_up((uint64_t)(q - a) * 4, 256));
+            a = q;
         }
     }
     // one chunk goes through the upload ring (no waiting for queued tests);
@@ -318,11 +330,11 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
     c.id_loc.resize(next + n, kNoLoc);
 
     for (size_t ch = 0; ch + 1 < cuts.size(); ++ch) {
-        const uint32_t p = cuts[ch], q = cuts[ch + 1];
+        const uint32_t q0 = cuts[ch], q = cuts[ch + 1];
         const uint64_t nl = chunk_lits[ch];
-        const int b = cls[order[p]];
+        const int b = cls[order[q0]];
         Bucket &B = c.buckets[b];
-        const uint32_t m = q - p;
+        const uint32_t m = q - q0;
         // host staging: codes | coff[m+1] | ids[m]
         const size_t codes_bytes = round_up(nl * 4, 256);
         const size_t coff_bytes = round_up((uint64_t)(m + 1) * 8, 256);
@@ -336,7 +348,7 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
         uint64_t off = 0;
         const uint64_t slot0 = slot_cursor[b];
         for (uint32_t r = 0; r < m; ++r) {
-            const uint32_t i = order[p + r];
+            const uint32_t i = order[q0 + r];
             const uint64_t L = offsets[i + 1] - offsets[i];
             hcoff[r] = off;
             off += L;
@@ -348,16 +360,10 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
             B.h_len[slot] = (uint32_t)L;
         }
         hcoff[m] = off;
-        // codes of every clause, sorted ascending
-        host_parallel(m, nl, [&](uint64_t rb, uint64_t re) {
-            for (uint64_t r = rb; r < re; ++r) {
-                const uint32_t i = order[p + r];
-                const uint64_t L = offsets[i + 1] - offsets[i];
-                uint32_t *dst = hcodes + hcoff[r];
-                for (uint64_t k = 0; k < L; ++k) dst[k] = lit_code(lits[offsets[i] + k]);
-                std::sort(dst, dst + L);
-            }
-        });
+        for (uint32_t r = 0; r < m; ++r) {  // the prepared codes, in slot order
+            const uint32_t i = order[q0 + r];
+            std::memcpy(hcodes + hcoff[r], p.codes.data() + offsets[i], (offsets[i + 1] - offsets[i]) * 4);
+        }
         GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
         const uint32_t *dcodes = (const uint32_t *)d;
         const uint64_t *dcoff = (const uint64_t *)(d + codes_bytes);
@@ -377,7 +383,23 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
     }
     c.live += n;
     c.version++;
-    priority_added(c, next, n, offsets);
+    priority_added(c, next, n, offsets.data());
+}
+
+}  // namespace gss
+
+using namespace gss;
+
+extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const uint64_t *offsets, uint32_t n,
+                                      uint32_t *out_ids) {
+    GSS_API_BEGIN(ctx)
+    c_->mutations++;
+    Ctx &c = *c_;
+    if (n == 0) return GSS_OK;
+    GSS_REQUIRE(lits && offsets && out_ids, GSS_ERR_INVALID_ARG, "null argument");
+    Prepared p;
+    prepare_clauses(c.cfg.num_vars, lits, offsets, n, p);
+    commit_clauses(c, p, out_ids);
     GSS_API_END
 }
 

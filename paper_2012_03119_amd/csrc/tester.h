@@ -14,8 +14,8 @@
 //
 // Early exit: a wavefront stops reading literals once no lane of its clauses has
 // a live bit left; a lane whose words are all dead issues no more loads.  Hot
-// rows (the first `hot_rows` plane rows; literals are kept in code order inside a
-// clause, so the first literals land there most often) can be staged in LDS.
+// rows (the first `hot_rows` plane rows, those of the lowest variables; a
+// clause's smallest code comes first) can be staged in LDS.
 //
 // Reports need no atomics: every wavefront owns one segment of the report buffer
 // and appends its records at its running count + (records of lower lanes, from
