@@ -183,19 +183,21 @@ def bench_served(args, torch, gss):
     del lits, offs
     log(f"store resident ({ctx.store_info()['device_bytes'] / 2**30:.2f} GiB); serving for {args.serve_seconds:.0f} s")
     res = ctx.serve_simulate(n_threads=P, duration_s=args.serve_seconds, snapshot_rate=200.0, redraw_fraction=0.05,
-                             insert_rate=20_000.0, delete_fraction=0.02, seed=args.seed + 401)
+                             insert_rate=20_000.0, delete_fraction=0.02, seed=args.seed + 401,
+                             test_flags=gss.GSS_TEST_AGGREGATE if args.aggregate else 0)
     log(f"served: {res['runs']} runs, {res['tested']} snapshots tested, {res['dropped']} dropped, "
         f"p50 {res['p50_ms']:.2f} ms p99 {res['p99_ms']:.2f} ms, {res['live_end']} live clauses")
     # the plain test on the final store, every word active
     ctx.set_active(np.full(P, 2**64 - 1, dtype=np.uint64))
+    flags = gss.GSS_TEST_AGGREGATE if args.aggregate else 0
     for _ in range(2):
-        ctx.test()
+        ctx.test(flags)
     ctx.reset_stats()
     torch.cuda.synchronize()
     t = time.perf_counter()
     reps = 10
     for _ in range(reps):
-        ctx.test()
+        ctx.test(flags)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t) / reps
     st = ctx.stats()
@@ -218,7 +220,7 @@ def bench_served(args, torch, gss):
         "gpu_busy": res["gpu_ms"] / (res["wall_s"] * 1e3),
         "plain": {"value": st["last_pairs"] / t_plain, "ms_per_test": t_plain * 1e3,
                   "kernel_ms": st["total_kernel_ms"] / max(st["timed_launches"], 1),
-                  "how": "gss_test of the final store, all 2048 slots active"},
+                  "how": "gss_test of the final store, all 2048 slots active", "flags": flags},
     }
     print(json.dumps(out), flush=True)
 
@@ -299,9 +301,11 @@ def bench_learned(args, torch, gss):
             f, t = table1_words(rng, len(vs))
             ctx.update_words(w, vs, f, t)
 
+    agg = gss.GSS_TEST_AGGREGATE if args.aggregate else 0
+
     def run_test(flags):
         torch.cuda.synchronize()
-        n = ctx.test(flags)
+        n = ctx.test(flags | agg)
         r = ctx.fetch_reports(n)
         st = ctx.stats()
         bits = int(np.unpackbits(np.ascontiguousarray(r["mask"]).view(np.uint8)).sum()) if len(r) else 0
@@ -407,6 +411,8 @@ def main():
     ap.add_argument("--report-capacity", type=int, default=1 << 20)
     ap.add_argument("--no-early-exit", action="store_true")
     ap.add_argument("--trigger", action="store_true")
+    ap.add_argument("--aggregate", action="store_true",
+                    help="aggregate pre-test of each 64-assignment word before reading plane rows")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -459,6 +465,8 @@ def main():
         flags |= gss.GSS_TEST_NO_EARLY_EXIT
     if args.trigger:
         flags |= gss.GSS_TEST_TRIGGER
+    if args.aggregate:
+        flags |= gss.GSS_TEST_AGGREGATE
     ctx = gss.Context(w.n_vars, w.n_slots, hot_vars=args.hot_vars, report_capacity=args.report_capacity)
     t0 = time.perf_counter()
     ctx.add_clauses(w.lits, w.offsets)

@@ -158,6 +158,15 @@ gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots);
 #define GSS_TEST_DENSE 8u             /* write one mask row per clause id (see gss_fetch_masks); no reports */
 #define GSS_TEST_NO_REGROW 16u        /* on overflow return GSS_ERR_REPORT_OVERFLOW instead of growing */
 #define GSS_TEST_NO_HOT 32u           /* do not stage hot-variable rows in LDS */
+/* Aggregate pre-test (Section 4): the 64 assignments of a word form a group, and
+ * the context keeps, per literal, one bit per word saying whether the literal is
+ * F in some slot of it (the group's aggregate).  A clause can only be falsified
+ * in a word where all its literals have that bit, so a lane reads a literal's
+ * plane words only while the aggregate bits of its words allow it.  The result
+ * is the same as without the flag; it is faster when the assignments of a word
+ * are similar (as successive assignments of one solver thread are).  Falsified
+ * mode only: ignored with GSS_TEST_TRIGGER. */
+#define GSS_TEST_AGGREGATE 256u
 
 /* Tests every live clause against every active slot (Section 3.6: a GPU run tests
  * all clauses against all assignments not yet tested and reports every hit).
@@ -377,7 +386,8 @@ typedef struct gss_server gss_server;
 
 typedef struct gss_server_config {
     uint32_t n_producers;     /* 1..W (max_slots / 64) */
-    uint32_t test_flags;      /* flags of every run: GSS_TEST_TRIGGER, GSS_TEST_NO_EARLY_EXIT, GSS_TEST_NO_HOT */
+    uint32_t test_flags;      /* flags of every run: GSS_TEST_TRIGGER, GSS_TEST_NO_EARLY_EXIT, GSS_TEST_NO_HOT,
+                                 GSS_TEST_AGGREGATE */
     double delete_fraction;   /* fraction of the live clauses removed per second (0 = none) */
     uint64_t seed;            /* of the removals */
     const char *log_path;     /* NULL, or a text file receiving every change, run and record in the

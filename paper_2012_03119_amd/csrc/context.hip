@@ -218,6 +218,7 @@ static void destroy_ctx(Ctx *c) {
         c->dfree(b.low);
     }
     c->dfree(c->planes);
+    c->dfree(c->agg);
     c->dfree(c->active);
     c->dfree(c->reports);
     c->dfree(c->seg_counts);
@@ -295,6 +296,9 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         c->planes = (uint64_t *)c->dalloc(n_rows * c->RW * sizeof(uint64_t));
         launch_fill_u64(*c, c->planes, n_rows * c->RW, 0);
         launch_fill_u64(*c, c->planes, c->RW, ~0ull);  // row 0: always F
+        c->agg = c->dalloc(n_rows * agg_elem_bytes(c->RW));
+        launch_fill_u32(*c, (uint32_t *)c->agg, (n_rows * agg_elem_bytes(c->RW) + 3) / 4, 0);
+        agg_rebuild(*c, 0, 2);
         c->active = (uint64_t *)c->dalloc(c->W * sizeof(uint64_t));
         launch_fill_u64(*c, c->active, c->W, 0);
         c->h_active.assign(c->W, 0);

@@ -99,6 +99,7 @@ struct TestArgs {
     uint32_t seg_cap;
     uint64_t *dense;          // GSS_TEST_DENSE: [n_ids][W]
     uint32_t sched_run;       // schedule: a low-priority clause is tested when (sched_run + id) % 4 == 0
+    const void *agg;          // aggregate bits per row (element of 2, 4 or 8 bytes by RW); null: no pre-test
 };
 
 // ---------------------------------------------------------------------------
@@ -138,6 +139,7 @@ struct Ctx {
     std::unordered_map<void *, size_t> allocs;
 
     uint64_t *planes = nullptr;
+    void *agg = nullptr;  // per row: bit w set when word w of the row is nonzero (see agg_elem_bytes)
     uint64_t *active = nullptr;
     std::vector<uint64_t> h_active;
     std::vector<uint64_t> var_seen;  // scratch bitmap for argument checks (kept all-zero)
@@ -221,6 +223,11 @@ struct Ctx {
     Staged stage_upload(size_t bytes);           // a free slot of at least `bytes`
     void stage_done(const Staged &s);            // its consumers are queued
 };
+
+// Bytes of one row's aggregate bits: 2 up to 16 words per row, 4 up to 32, else 8.
+inline uint32_t agg_elem_bytes(uint32_t RW) { return RW <= 16 ? 2u : RW <= 32 ? 4u : 8u; }
+// recomputes the aggregate bits of rows [lo, hi)
+void agg_rebuild(Ctx &c, uint64_t lo, uint64_t hi);
 
 // kernels / launchers (defined in the .hip files)
 void launch_fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t value);

@@ -16,6 +16,53 @@
 
 namespace gss {
 
+// ---- aggregate bits (Section 4): per row, bit w = some slot of word w has the
+//      row's literal F.  Kept in step with every plane update.
+
+__device__ inline uint64_t agg_get(const void *agg, uint32_t RW, uint64_t row) {
+    if (RW <= 16) return reinterpret_cast<const uint16_t *>(agg)[row];
+    if (RW <= 32) return reinterpret_cast<const uint32_t *>(agg)[row];
+    return reinterpret_cast<const uint64_t *>(agg)[row];
+}
+
+__device__ inline void agg_put(void *agg, uint32_t RW, uint64_t row, uint64_t bits) {
+    if (RW <= 16)
+        reinterpret_cast<uint16_t *>(agg)[row] = (uint16_t)bits;
+    else if (RW <= 32)
+        reinterpret_cast<uint32_t *>(agg)[row] = (uint32_t)bits;
+    else
+        reinterpret_cast<uint64_t *>(agg)[row] = bits;
+}
+
+__device__ inline uint64_t row_nonzero_words(const uint64_t *planes, uint32_t RW, uint64_t row) {
+    uint64_t bits = 0;
+    for (uint32_t w = 0; w < RW; ++w) bits |= (uint64_t)(planes[row * RW + w] != 0) << w;
+    return bits;
+}
+
+__global__ void k_agg_rows(const uint64_t *planes, uint32_t RW, void *agg, uint64_t lo, uint64_t hi) {
+    for (uint64_t r = lo + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < hi; r += (uint64_t)gridDim.x * blockDim.x)
+        agg_put(agg, RW, r, row_nonzero_words(planes, RW, r));
+}
+
+// the two rows of each listed variable (skipped when the inputs failed validation)
+__global__ void k_agg_vars(const uint64_t *planes, uint32_t RW, void *agg, const uint32_t *vars, uint32_t n,
+                           const uint32_t *bad) {
+    if (*bad) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t r0 = 2ull * vars[i];
+    agg_put(agg, RW, r0, row_nonzero_words(planes, RW, r0));
+    agg_put(agg, RW, r0 + 1, row_nonzero_words(planes, RW, r0 + 1));
+}
+
+void agg_rebuild(Ctx &c, uint64_t lo, uint64_t hi) {
+    if (hi <= lo) return;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((hi - lo + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_agg_rows, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, c.agg, lo, hi);
+    GSS_HIP(hipGetLastError());
+}
+
 // Packs the slots of word w from a slot-major staging block.  One wavefront per
 // 64 variables; lane b reads slot 64*w + b.  Staging row r holds slot s_lo + r,
 // `pitch` bytes per row (a multiple of 64), byte v-1 = value of variable v.
@@ -105,12 +152,19 @@ __global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RW,
 
 // Packed delta: new plane words of listed variables in one 64-slot word.  Thread
 // per variable; f = slots where the variable is F, t = slots where it is T.
+// The variables of one launch are distinct, so each thread owns its two rows'
+// aggregate bits (bit `word`), updated in place.
 __global__ void k_set_words(uint64_t *planes, uint32_t RW, uint32_t word, const uint32_t *vars, const uint64_t *f,
-                            const uint64_t *t, uint32_t n) {
+                            const uint64_t *t, uint32_t n, void *agg) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint64_t r0 = (uint64_t)(2 * vars[i]) * RW + word;
+        const uint64_t row = 2ull * vars[i];
+        const uint64_t r0 = row * RW + word;
         planes[r0] = f[i];
         planes[r0 + RW] = t[i];
+        const uint64_t bit = 1ull << word;
+        const uint64_t a0 = agg_get(agg, RW, row), a1 = agg_get(agg, RW, row + 1);
+        agg_put(agg, RW, row, f[i] ? (a0 | bit) : (a0 & ~bit));
+        agg_put(agg, RW, row + 1, t[i] ? (a1 | bit) : (a1 & ~bit));
     }
 }
 
@@ -130,7 +184,7 @@ __global__ void k_clear_slots(uint64_t *planes, uint32_t RW, uint64_t n_rows, ui
 void launch_set_words(Ctx &c, uint32_t word, const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n) {
     if (n == 0) return;
     const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, word, vars, f, t, n);
+    hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, word, vars, f, t, n, c.agg);
     GSS_HIP(hipGetLastError());
     c.mutations++;
 }
@@ -206,6 +260,7 @@ extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uin
         GSS_HIP(hipGetLastError());
     }
     if (dev) check_flag(c);  // throws, having applied nothing, if a value was invalid
+    agg_rebuild(c, 2, 2 * (V + 1));
     for (uint32_t w = first_slot / 64; w <= (last - 1) / 64; ++w) c.h_active[w] |= slot_mask(first_slot, n_slots, w);
     upload_active(c);
     c.sync();  // host inputs are read by the copies above: done before returning
@@ -245,6 +300,9 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
     hipLaunchKernelGGL(k_set_vars, dim3((n_vars + 255) / 256, nw), dim3(256), 0, c.stream, c.planes, c.RW,
                        (const uint32_t *)d, n_vars, dvals, first_slot, n_slots, bad);
     GSS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_agg_vars, dim3((n_vars + 255) / 256), dim3(256), 0, c.stream, c.planes, c.RW, c.agg,
+                       (const uint32_t *)d, n_vars, bad);
+    GSS_HIP(hipGetLastError());
     c.stage_done(st);
     if (dev) check_flag(c);  // one synchronisation: device inputs are fully read when the call returns
     GSS_API_END
@@ -262,6 +320,7 @@ extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_
     const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
     hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, n_rows, first_slot, n_slots);
     GSS_HIP(hipGetLastError());
+    agg_rebuild(c, 2, n_rows);
     for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w)
         c.h_active[w] &= ~slot_mask(first_slot, n_slots, w);
     upload_active(c);

@@ -467,7 +467,7 @@ extern "C" gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cf
     *out = nullptr;
     GSS_REQUIRE(cfg->n_producers >= 1 && cfg->n_producers <= c.W, GSS_ERR_INVALID_ARG,
                 "n_producers must be in 1..max_slots/64 (one 64-slot word each)");
-    const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_HOT;
+    const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_HOT | GSS_TEST_AGGREGATE;
     GSS_REQUIRE((cfg->test_flags & ~known) == 0, GSS_ERR_INVALID_ARG, "test flag not allowed for served runs");
     GSS_REQUIRE(cfg->delete_fraction >= 0 && cfg->delete_fraction <= 1, GSS_ERR_INVALID_ARG,
                 "delete_fraction must be in [0, 1]");

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
         __syncthreads();
     }
     const uint32_t lane = threadIdx.x & 63;
-    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, a.sched_run);
+    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, a.sched_run, a.agg);
     const uint32_t waves_per_block = blockDim.x / 64;
     const uint32_t n_waves = gridDim.x * waves_per_block;
     // wave-uniform by construction; readfirstlane lets the compiler keep it in SGPRs
@@ -146,6 +146,7 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     a.seg_counts = c.seg_counts;
     a.seg_cap = c.seg_cap;
     a.dense = c.dense;
+    a.agg = (flags & GSS_TEST_AGGREGATE) ? c.agg : nullptr;
     if (nb) GSS_HIP(hipMemcpyAsync(c.d_desc, h, nb * sizeof(BucketDesc), hipMemcpyHostToDevice, c.stream));
     L.descs = (const BucketDesc *)c.d_desc;
     L.fn = pick_kernel(c.RW, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot);
@@ -190,7 +191,7 @@ static void complete(Ctx &c) {
 // Checks flags and prepares a test; returns false when there is nothing to launch.
 static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
     const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_SORTED | GSS_TEST_DENSE |
-                           GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT | GSS_TEST_SCHEDULED;
+                           GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT | GSS_TEST_SCHEDULED | GSS_TEST_AGGREGATE;
     GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "unknown gss_test flag");
     GSS_REQUIRE(!(flags & GSS_TEST_SORTED), GSS_ERR_INVALID_ARG, "GSS_TEST_SORTED is not supported by this build");
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is already in flight (call gss_test_wait)");

@@ -25,6 +25,8 @@
 
 #include "gss_internal.h"
 
+#include <type_traits>
+
 namespace gss {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -93,6 +95,8 @@ struct Tester {
     static constexpr uint32_t T = 64 / LPC;                 // clauses per wavefront (and per tile)
     static constexpr uint32_t RW = LPC * WPL;               // words per plane row
     static constexpr uint32_t ROW_SHIFT = ilog2<RW>() + 3;  // bytes per plane row
+    // a row's aggregate bits (one per word), as stored by the context
+    using AggT = std::conditional_t<(RW <= 16), uint16_t, std::conditional_t<(RW <= 32), uint32_t, uint64_t>>;
 
     // a tile: wave-uniform code resource and stride, this lane's byte offset of its
     // clause's codes, its metadata (length, id) and its codes 0..3
@@ -115,10 +119,12 @@ struct Tester {
     uint64_t act[WPL];
     const char *pbase;
     const uint64_t *lds;
+    const AggT *agg;  // null: no aggregate pre-test
 
     __device__ Tester(uint32_t lane, const uint64_t *planes, const uint64_t *active, uint32_t W_, uint32_t hot_rows_,
-                      const uint64_t *lds_, uint32_t sched_run_)
-        : j(lane / LPC), w0((lane % LPC) * WPL), W(W_), hot_rows(hot_rows_), sched_run(sched_run_), lds(lds_) {
+                      const uint64_t *lds_, uint32_t sched_run_, const void *agg_)
+        : j(lane / LPC), w0((lane % LPC) * WPL), W(W_), hot_rows(hot_rows_), sched_run(sched_run_), lds(lds_),
+          agg(MODE == 0 ? static_cast<const AggT *>(agg_) : nullptr) {
         lane_ok = w0 < W;
 #pragma unroll
         for (int i = 0; i < WPL; ++i) act[i] = (w0 + i < W) ? active[w0 + i] : 0;
@@ -192,7 +198,24 @@ struct Tester {
                 uint64_t any = 0;
 #pragma unroll
                 for (int i = 0; i < WPL; ++i) any |= af[i] | ou[i];
-                const bool lane_live = lane_ok && k + g0 < len && (!early_exit || any != 0);
+                bool lane_live = lane_ok && k + g0 < len && (!early_exit || any != 0);
+                if constexpr (MODE == 0) {
+                    // aggregate pre-test (Section 4): a word where some literal of the
+                    // group is F in no slot cannot be falsified; skip the gathers when
+                    // that holds for all of this lane's words
+                    if (agg && lane_live) {
+                        uint32_t keep = (1u << WPL) - 1u;
+#pragma unroll
+                        for (uint32_t u = 0; u < kGroup; ++u) {
+                            const uint32_t code = (k + g0 + u < len) ? cs[g0 + u] : 0u;
+                            keep &= (uint32_t)(agg[code] >> w0);
+                        }
+#pragma unroll
+                        for (int i = 0; i < WPL; ++i)
+                            if (!((keep >> i) & 1u)) af[i] = 0;
+                        lane_live = keep != 0;
+                    }
+                }
                 if (lane_live) {
                     Words<WPL> gf[kGroup], gt[kGroup];
 #pragma unroll

@@ -102,6 +102,7 @@ class gss_priority_config(ctypes.Structure):
 MLP_FEATURES = 12
 MLP_PARAMS = 5057
 GSS_TEST_SCHEDULED = 128
+GSS_TEST_AGGREGATE = 256
 
 
 class gss_server_config(ctypes.Structure):

@@ -422,3 +422,67 @@ def test_async_overflow_after_a_change_is_reported_not_repeated():
         k = ctx.test()
         got = reports_to_dense(ctx.fetch_reports(k), n, 1)
     _check(got, want)
+
+
+def _table1_values(rng, n_slots, n_vars):
+    """Slot-major values whose 64-slot words are groups of similar assignments."""
+    return np.concatenate([gen.assignments_table1(rng, 64, n_vars) for _ in range(n_slots // 64)])
+
+
+def _packed(vals_word):
+    """(F words, T words) of one 64-slot word given as [64][V] values."""
+    f = np.zeros(vals_word.shape[1], dtype=np.uint64)
+    t = np.zeros(vals_word.shape[1], dtype=np.uint64)
+    for b in range(64):
+        f |= (vals_word[b] == -1).astype(np.uint64) << np.uint64(b)
+        t |= (vals_word[b] == 1).astype(np.uint64) << np.uint64(b)
+    return f, t
+
+
+@pytest.mark.parametrize("max_slots", [64, 128, 256, 1024, 2048, 4096])
+def test_aggregate_pretest_equals_oracle(max_slots):
+    """The aggregate pre-test (every row width: 2, 4 and 8-byte aggregate words)
+    changes no result, on grouped (Table 1) and on independent assignments, and
+    stays exact through every kind of plane update."""
+    n_vars = 500
+    rng = np.random.default_rng(max_slots)
+    lits, offsets = gen.random_clauses(rng, gen.lengths_mix(rng, 6000), n_vars)
+    lits2, offsets2 = gen.random_clauses(rng, rng.integers(1, 5, 3000), n_vars)  # short: many hits
+    lits = np.concatenate([lits, lits2])
+    offsets = np.concatenate([offsets, offsets[-1] + offsets2[1:]])
+    n = len(offsets) - 1
+    A = gss.GSS_TEST_AGGREGATE
+    print(f"aggregate max_slots={max_slots}", flush=True)
+    with new_context(n_vars, max_slots) as ctx:
+        ctx.add_clauses(lits, offsets)
+        for kind in ("table1", "bernoulli"):
+            vals = (_table1_values(rng, max_slots, n_vars) if kind == "table1" else
+                    gen.assignments_bernoulli(rng, max_slots, n_vars, 0.5))
+            ctx.set_assignments(0, vals)
+            want = oracle.masks(lits, offsets, vals)
+            _check(gpu_dense(ctx, n, A), want)
+            _check(gpu_dense(ctx, n, A | gss.GSS_TEST_NO_EARLY_EXIT), want)
+        # a var-major delta on part of the slots
+        vs = rng.choice(np.arange(1, n_vars + 1), 60, replace=False).astype(np.uint32)
+        first, count = 3, max_slots - 5
+        delta = gen.assignments_table1(rng, count, 60).T.copy()  # [vars][slots]
+        ctx.set_var_values(first, vs, delta)
+        vals[first:first + count][:, vs - 1] = delta.T
+        _check(gpu_dense(ctx, n, A), oracle.masks(lits, offsets, vals))
+        # packed word deltas
+        for w in range(max_slots // 64):
+            vs = rng.choice(np.arange(1, n_vars + 1), 40, replace=False).astype(np.uint32)
+            new = gen.assignments_table1(rng, 64, 40)
+            f, t = _packed(new)
+            ctx.update_words(w, vs, f, t)
+            vals[64 * w:64 * w + 64][:, vs - 1] = new
+        _check(gpu_dense(ctx, n, A), oracle.masks(lits, offsets, vals))
+        # cleared slots are inactive and all-U
+        ctx.clear_slots(1, max_slots // 2)
+        vals[1:1 + max_slots // 2] = 0
+        active = np.ones(max_slots, dtype=bool)
+        active[1:1 + max_slots // 2] = False
+        _check(gpu_dense(ctx, n, A), oracle.masks(lits, offsets, vals, active=active))
+        # ignored in trigger mode
+        _check(gpu_dense(ctx, n, A | gss.GSS_TEST_TRIGGER),
+               oracle.masks(lits, offsets, vals, mode="trigger", active=active))
