@@ -186,8 +186,9 @@ void gss_server::run() {
             uint64_t snaps = 0;
             double arrival = -1.0;
             {
-                std::lock_guard<std::mutex> g(pr.mu);
-                if (pr.snaps == 0) continue;
+                // a producer merging a snapshot holds its lock: take its mailbox next time
+                std::unique_lock<std::mutex> g(pr.mu, std::try_to_lock);
+                if (!g.owns_lock() || pr.snaps == 0) continue;
                 int free_k = -1;
                 for (int k = 0; k < kMails && free_k < 0; ++k) {
                     if (k == pr.open) continue;
