@@ -321,6 +321,13 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         GSS_HIP(hipEventCreate(&c->ev_stop));
         GSS_HIP(hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming));
         GSS_HIP(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
+        // the upload ring starts at 256 KiB a slot, so that per-round deltas do not
+        // allocate pinned memory while a caller is timing them
+        for (int k = 0; k < Ctx::kRing; ++k) {
+            const Ctx::Staged st = c->stage_upload(1u << 18);
+            (void)st;
+        }
+        c->ring_next = 0;
         c->sync();
     } catch (const Error &e) {
         g_create_error = e.what();

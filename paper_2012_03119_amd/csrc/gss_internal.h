@@ -140,6 +140,7 @@ struct Ctx {
 
     uint64_t *planes = nullptr;
     void *agg = nullptr;  // per row: bit w set when word w of the row is nonzero (see agg_elem_bytes)
+    bool agg_valid = true;  // false after bulk plane updates: rebuilt by the next aggregate test
     uint64_t *active = nullptr;
     std::vector<uint64_t> h_active;
     std::vector<uint64_t> var_seen;  // scratch bitmap for argument checks (kept all-zero)

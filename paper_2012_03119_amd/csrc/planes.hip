@@ -17,7 +17,9 @@
 namespace gss {
 
 // ---- aggregate bits (Section 4): per row, bit w = some slot of word w has the
-//      row's literal F.  Kept in step with every plane update.
+//      row's literal F.  Packed word deltas keep them in step; bulk updates
+//      (full sets, var-major deltas, cleared slots) mark them stale, and the next
+//      aggregate test rebuilds them.
 
 __device__ inline uint64_t agg_get(const void *agg, uint32_t RW, uint64_t row) {
     if (RW <= 16) return reinterpret_cast<const uint16_t *>(agg)[row];
@@ -43,17 +45,6 @@ __device__ inline uint64_t row_nonzero_words(const uint64_t *planes, uint32_t RW
 __global__ void k_agg_rows(const uint64_t *planes, uint32_t RW, void *agg, uint64_t lo, uint64_t hi) {
     for (uint64_t r = lo + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < hi; r += (uint64_t)gridDim.x * blockDim.x)
         agg_put(agg, RW, r, row_nonzero_words(planes, RW, r));
-}
-
-// the two rows of each listed variable (skipped when the inputs failed validation)
-__global__ void k_agg_vars(const uint64_t *planes, uint32_t RW, void *agg, const uint32_t *vars, uint32_t n,
-                           const uint32_t *bad) {
-    if (*bad) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t r0 = 2ull * vars[i];
-    agg_put(agg, RW, r0, row_nonzero_words(planes, RW, r0));
-    agg_put(agg, RW, r0 + 1, row_nonzero_words(planes, RW, r0 + 1));
 }
 
 void agg_rebuild(Ctx &c, uint64_t lo, uint64_t hi) {
@@ -260,7 +251,7 @@ extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uin
         GSS_HIP(hipGetLastError());
     }
     if (dev) check_flag(c);  // throws, having applied nothing, if a value was invalid
-    agg_rebuild(c, 2, 2 * (V + 1));
+    c.agg_valid = false;
     for (uint32_t w = first_slot / 64; w <= (last - 1) / 64; ++w) c.h_active[w] |= slot_mask(first_slot, n_slots, w);
     upload_active(c);
     c.sync();  // host inputs are read by the copies above: done before returning
@@ -300,9 +291,7 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
     hipLaunchKernelGGL(k_set_vars, dim3((n_vars + 255) / 256, nw), dim3(256), 0, c.stream, c.planes, c.RW,
                        (const uint32_t *)d, n_vars, dvals, first_slot, n_slots, bad);
     GSS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_agg_vars, dim3((n_vars + 255) / 256), dim3(256), 0, c.stream, c.planes, c.RW, c.agg,
-                       (const uint32_t *)d, n_vars, bad);
-    GSS_HIP(hipGetLastError());
+    c.agg_valid = false;
     c.stage_done(st);
     if (dev) check_flag(c);  // one synchronisation: device inputs are fully read when the call returns
     GSS_API_END
@@ -320,7 +309,7 @@ extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_
     const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
     hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, n_rows, first_slot, n_slots);
     GSS_HIP(hipGetLastError());
-    agg_rebuild(c, 2, n_rows);
+    c.agg_valid = false;
     for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w)
         c.h_active[w] &= ~slot_mask(first_slot, n_slots, w);
     upload_active(c);

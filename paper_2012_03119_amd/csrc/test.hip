@@ -146,7 +146,14 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     a.seg_counts = c.seg_counts;
     a.seg_cap = c.seg_cap;
     a.dense = c.dense;
-    a.agg = (flags & GSS_TEST_AGGREGATE) ? c.agg : nullptr;
+    a.agg = nullptr;
+    if ((flags & GSS_TEST_AGGREGATE) && !(flags & GSS_TEST_TRIGGER)) {
+        if (!c.agg_valid) {
+            agg_rebuild(c, 0, 2ull * ((uint64_t)c.cfg.num_vars + 1));
+            c.agg_valid = true;
+        }
+        a.agg = c.agg;
+    }
     if (nb) GSS_HIP(hipMemcpyAsync(c.d_desc, h, nb * sizeof(BucketDesc), hipMemcpyHostToDevice, c.stream));
     L.descs = (const BucketDesc *)c.d_desc;
     L.fn = pick_kernel(c.RW, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot);
