@@ -345,6 +345,13 @@ gss_status gss_priority_clear_samples(gss_ctx *ctx);
 /* Scores every live clause; scores below threshold are low priority.
  * *out_n_low (may be NULL): how many. */
 gss_status gss_priority_score(gss_ctx *ctx, float threshold, uint64_t *out_n_low);
+/* Rescores only the clauses that may have changed side of the threshold since
+ * they were last scored: new clauses, new LBD or source, a low clause that hit
+ * in a run, a high clause that did not.  The others keep their scores until the
+ * next gss_priority_score (their age still grows).  Uses the threshold of the last
+ * gss_priority_score, which must have run since the last gss_priority_mark.
+ * *out_n_low (may be NULL): low clauses now. */
+gss_status gss_priority_update(gss_ctx *ctx, uint64_t *out_n_low);
 /* Sets the low flags directly, one byte per issued id (host array of next_id
  * entries; nonzero = low), in place of a scoring: schedules of other policies. */
 gss_status gss_priority_mark(gss_ctx *ctx, const uint8_t *low, uint64_t n);

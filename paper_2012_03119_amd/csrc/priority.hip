@@ -10,8 +10,8 @@
 // scheduled test runs a low clause only when (run + id) % 4 == 0.
 //
 // State is kept per clause id (structure of arrays, grown with the id space):
-// length, LBD, birth run, source thread, alive flag, 8 hit counts, this run's
-// hit count, score and low flag.  The schedule bits the test kernel reads are
+// length, LBD, birth run, source thread, alive flag, 8 hit counts (16 bits each,
+// one 16-byte word), this run's hit count, score and low flag.  The schedule bits the test kernel reads are
 // per slot of each length class, rebuilt from the low flags when the store or
 // the scores changed.
 #include "mlp.h"
@@ -29,9 +29,10 @@ struct Priority {
     uint64_t cap = 0;    // ids with state
     uint64_t n_ids = 0;  // ids issued so far (state valid below)
     uint32_t *len = nullptr, *birth = nullptr, *src = nullptr, *hits = nullptr;
-    uint32_t *hist = nullptr;  // [kHist][cap], most recent first
+    uint4 *hist = nullptr;  // [cap]: 8 hit counts of 16 bits, most recent in the low bits of .x
     float *lbd = nullptr, *score = nullptr;
     uint8_t *alive = nullptr, *low = nullptr;
+    uint8_t *dirty = nullptr;  // features changed (beyond age) since the clause was last scored
     float *sx = nullptr, *sy = nullptr;  // samples [sample_cap][kFeat], [sample_cap]
     uint32_t *counters = nullptr;        // [0] samples taken, [1] low clauses of the last scoring
     uint32_t *h_counters = nullptr;      // pinned copy
@@ -41,9 +42,16 @@ struct Priority {
     uint64_t score_epoch = 0;
     uint64_t built_version = ~0ull, built_epoch = ~0ull;
     float threshold = 0.f;
+    uint32_t *list = nullptr;  // ids of the clauses an update rescores
+    uint64_t list_cap = 0;
+    bool scored = false;  // a full scoring (or marking) has set every low flag
 };
 
 namespace {
+
+__device__ inline uint32_t lanes_below_(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
 
 __device__ inline uint64_t mix64(uint64_t z) {
     z += 0x9E3779B97F4A7C15ull;
@@ -53,21 +61,24 @@ __device__ inline uint64_t mix64(uint64_t z) {
 }
 
 struct ProbeArgs {  // per-id arrays as the kernels see them
-    uint32_t *len, *birth, *src, *hits, *hist;
+    uint32_t *len, *birth, *src, *hits;
+    uint4 *hist;
     float *lbd, *score;
-    uint8_t *alive, *low;
+    uint8_t *alive, *low, *dirty;
     uint64_t cap;
 };
 
 ProbeArgs args_of(const Priority &p) {
-    return ProbeArgs{p.len, p.birth, p.src, p.hits, p.hist, p.lbd, p.score, p.alive, p.low, p.cap};
+    return ProbeArgs{p.len, p.birth, p.src, p.hits, p.hist, p.lbd, p.score, p.alive, p.low, p.dirty, p.cap};
 }
 
 __device__ inline void load_features(const ProbeArgs &a, uint64_t id, uint32_t run, float src_scale,
                                      float (&x)[kFeat]) {
+    const uint4 v = a.hist[id];
+    const uint32_t c[4] = {v.x, v.y, v.z, v.w};
     uint32_t h[kHist];
 #pragma unroll
-    for (int k = 0; k < kHist; ++k) h[k] = a.hist[(uint64_t)k * a.cap + id];
+    for (int k = 0; k < kHist; ++k) h[k] = (c[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
     clause_features(x, a.len[id], a.lbd[id], run - a.birth[id], a.src[id], src_scale, h);
 }
 
@@ -80,10 +91,10 @@ __global__ void k_prio_init(ProbeArgs a, uint64_t first, uint32_t n, const uint3
     a.birth[id] = run;
     a.src[id] = 0;
     a.hits[id] = 0;
-#pragma unroll
-    for (int k = 0; k < kHist; ++k) a.hist[(uint64_t)k * a.cap + id] = 0;
+    a.hist[id] = make_uint4(0, 0, 0, 0);
     a.alive[id] = 1;
     a.low[id] = 0;
+    a.dirty[id] = 1;
     a.score[id] = 1.f;
 }
 
@@ -99,6 +110,45 @@ __global__ void k_prio_info(ProbeArgs a, const uint32_t *ids, uint32_t n, const 
     if (i >= n) return;
     a.lbd[ids[i]] = lbd[i];
     a.src[ids[i]] = src[i];
+    a.dirty[ids[i]] = 1;
+}
+
+// ---- counting with one atomic per workgroup.  Wavefronts of one address's
+//      atomics serialize at the cache (one per wavefront over millions of ids
+//      cost milliseconds), so a workgroup of 256 lanes sums first, or claims one
+//      range of output rows for all its lanes.
+
+constexpr uint32_t kPerThread = 16;  // ids per lane in the counting kernels (grid-stride free)
+
+// Inclusive sum of v over the workgroup's lanes below and including this one;
+// *total gets the workgroup's sum.  All 256 lanes must call it.
+__device__ inline uint32_t block_inclusive_sum(uint32_t v, uint32_t &total) {
+    __shared__ uint32_t wave_sum[4];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    if (lane == 63) wave_sum[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < 4; ++w) {
+        before += w < wave ? wave_sum[w] : 0u;
+        total += wave_sum[w];
+    }
+    __syncthreads();
+    return before + x;
+}
+
+// Adds the workgroup's sum of v to *counter with one atomic (signed).
+__device__ inline void block_add(int32_t v, uint32_t *counter) {
+    uint32_t total = 0;
+    block_inclusive_sum((uint32_t)v, total);
+    if (threadIdx.x == 0 && total) atomicAdd(counter, total);  // wraps for negative sums
 }
 
 // Hit counts of the last run: one workgroup per report segment.
@@ -112,50 +162,124 @@ __global__ void k_prio_hits(ProbeArgs a, const gss_report *reports, const uint32
     }
 }
 
-// After a run: samples, history shift, hit counter reset.
-__global__ void k_prio_observe(ProbeArgs a, uint64_t n_ids, uint32_t run, uint32_t scheduled, float src_scale,
-                               uint32_t period, uint64_t seed, float *sx, float *sy, uint64_t sample_cap,
-                               uint32_t *counters) {
-    const uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (id >= n_ids || !a.alive[id]) return;
-    const uint32_t h = a.hits[id];
-    const bool tested = !(scheduled && a.low[id] && ((run + (uint32_t)id) & 3u) != 0);
-    if (tested && period && mix64(seed ^ (id << 32) ^ run) % period == 0) {
-        const uint32_t pos = atomicAdd(&counters[0], 1u);
-        if (pos < sample_cap) {
-            float x[kFeat];
-            load_features(a, id, run, src_scale, x);
-#pragma unroll
-            for (int k = 0; k < kFeat; ++k) sx[(uint64_t)pos * kFeat + k] = x[k];
-            sy[pos] = h ? 1.f : 0.f;
+// After a run: samples, history shift, hit counter reset.  Each lane takes
+// kPerThread ids (strided by the workgroup size); the workgroup claims its sample
+// rows with one atomic.
+__global__ __launch_bounds__(256) void k_prio_observe(ProbeArgs a, uint64_t n_ids, uint32_t run, uint32_t scheduled,
+                                                      float src_scale, uint32_t period, uint64_t seed, float *sx,
+                                                      float *sy, uint64_t sample_cap, uint32_t *counters) {
+    __shared__ uint32_t base_s;
+    const uint64_t first = (uint64_t)blockIdx.x * 256 * kPerThread + threadIdx.x;
+    auto is_tested = [&](uint64_t id, bool &live) {
+        live = id < n_ids && a.alive[id];
+        return live && !(scheduled && a.low[id] && ((run + (uint32_t)id) & 3u) != 0);
+    };
+    auto is_sample = [&](uint64_t id) { return period && mix64(seed ^ (id << 32) ^ run) % period == 0; };
+    uint32_t mine = 0;
+    if (period) {
+        for (uint32_t k = 0; k < kPerThread; ++k) {
+            const uint64_t id = first + (uint64_t)k * 256;
+            bool live;
+            mine += (is_tested(id, live) && is_sample(id)) ? 1u : 0u;
         }
     }
-    if (tested) {
+    uint32_t total = 0;
+    uint32_t pos = block_inclusive_sum(mine, total) - mine;
+    if (threadIdx.x == 0) base_s = total ? atomicAdd(&counters[0], total) : 0u;
+    __syncthreads();
+    pos += base_s;
+    for (uint32_t k = 0; k < kPerThread; ++k) {
+        const uint64_t id = first + (uint64_t)k * 256;
+        bool live;
+        const bool tested = is_tested(id, live);
+        if (!live) continue;
+        const uint32_t h = a.hits[id];
+        if (tested && is_sample(id)) {
+            if (pos < sample_cap) {
+                float x[kFeat];
+                load_features(a, id, run, src_scale, x);
 #pragma unroll
-        for (int k = kHist - 1; k > 0; --k) a.hist[(uint64_t)k * a.cap + id] = a.hist[(uint64_t)(k - 1) * a.cap + id];
-        a.hist[id] = h;
+                for (int q = 0; q < kFeat; ++q) sx[(uint64_t)pos * kFeat + q] = x[q];
+                sy[pos] = h ? 1.f : 0.f;
+            }
+            ++pos;
+        }
+        if (tested) {  // shift in this run's count (a history of zeros stays as it is)
+            const uint4 v = a.hist[id];
+            if (h || (v.x | v.y | v.z | v.w)) {
+                const uint32_t hc = min(h, 0xFFFFu);  // at most 64 x 64 slots: never clipped
+                a.hist[id] = make_uint4((v.x << 16) | hc, (v.y << 16) | (v.x >> 16), (v.z << 16) | (v.y >> 16),
+                                        (v.w << 16) | (v.z >> 16));
+                // rescored by the next update only where its side of the threshold
+                // may change: a low clause that hit, a high one that did not (the
+                // next full scoring catches everything else)
+                if (a.low[id] ? h != 0 : h == 0) a.dirty[id] = 1;
+            }
+        }
+        if (h) a.hits[id] = 0;
     }
-    a.hits[id] = 0;
 }
 
+// Scores every live clause and sets its low flag; counters[1] receives the
+// number of low clauses (one atomic per workgroup).
 __global__ __launch_bounds__(256) void k_prio_score(ProbeArgs a, const float *__restrict__ params, uint64_t n_ids,
                                                     uint32_t run, float src_scale, float threshold,
                                                     uint32_t *counters) {
-    const uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (id >= n_ids) return;
-    if (!a.alive[id]) {
-        a.score[id] = 0.f;
-        a.low[id] = 0;
-        return;
+    uint32_t lows = 0;
+    for (uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; id < n_ids;
+         id += (uint64_t)gridDim.x * blockDim.x) {
+        if (!a.alive[id]) {
+            a.score[id] = 0.f;
+            a.low[id] = 0;
+            continue;
+        }
+        float x[kFeat];
+        load_features(a, id, run, src_scale, x);
+        const float p = sigmoidf_(mlp_logit(params, x));
+        a.score[id] = p;
+        a.low[id] = p < threshold;
+        a.dirty[id] = 0;
+        lows += p < threshold ? 1u : 0u;
     }
-    float x[kFeat];
-    load_features(a, id, run, src_scale, x);
-    const float p = sigmoidf_(mlp_logit(params, x));
-    a.score[id] = p;
-    const bool lo = p < threshold;
-    a.low[id] = lo;
-    const uint64_t b = __ballot(lo);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[1], (uint32_t)__popcll(b));
+    block_add((int32_t)lows, &counters[1]);
+}
+
+// The dirty live clauses, compacted into a list (counters[2] = its length), so
+// that the network runs on dense wavefronts rather than on scattered lanes.
+__global__ __launch_bounds__(256) void k_prio_collect(ProbeArgs a, uint64_t n_ids, uint32_t *list, uint32_t *counters) {
+    __shared__ uint32_t base_s;
+    const uint64_t first = (uint64_t)blockIdx.x * 256 * kPerThread + threadIdx.x;
+    auto is_dirty = [&](uint64_t id) { return id < n_ids && a.alive[id] && a.dirty[id]; };
+    uint32_t mine = 0;
+    for (uint32_t k = 0; k < kPerThread; ++k) mine += is_dirty(first + (uint64_t)k * 256) ? 1u : 0u;
+    uint32_t total = 0;
+    uint32_t pos = block_inclusive_sum(mine, total) - mine;
+    if (threadIdx.x == 0) base_s = total ? atomicAdd(&counters[2], total) : 0u;
+    __syncthreads();
+    pos += base_s;
+    for (uint32_t k = 0; k < kPerThread; ++k) {
+        const uint64_t id = first + (uint64_t)k * 256;
+        if (is_dirty(id)) list[pos++] = (uint32_t)id;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_prio_score_list(ProbeArgs a, const float *__restrict__ params,
+                                                         const uint32_t *list, uint32_t run, float src_scale,
+                                                         float threshold, uint32_t *counters) {
+    const uint32_t n = counters[2];
+    int32_t delta = 0;  // change in the number of low clauses
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t id = list[i];
+        float x[kFeat];
+        load_features(a, id, run, src_scale, x);
+        const float p = sigmoidf_(mlp_logit(params, x));
+        a.score[id] = p;
+        const bool was = a.low[id], now = p < threshold;
+        a.low[id] = now;
+        a.dirty[id] = 0;
+        delta += (int32_t)now - (int32_t)was;
+    }
+    block_add(delta, &counters[1]);
 }
 
 // Schedule bits of one length class: bit s of word s / 32 set when slot s holds
@@ -175,13 +299,14 @@ __global__ void k_sched_bits(const uint2 *meta, uint64_t n_slots, const uint8_t 
     if (lane == 32 && w + 1 < n_words) bits[w + 1] = (uint32_t)(bal >> 32);
 }
 
-__global__ void k_prio_mark(ProbeArgs a, const uint8_t *low, uint64_t n, uint32_t *counters) {
-    const uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    const bool lo = a.alive[id] && low[id];
-    a.low[id] = lo;
-    const uint64_t b = __ballot(lo);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[1], (uint32_t)__popcll(b));
+__global__ __launch_bounds__(256) void k_prio_mark(ProbeArgs a, const uint8_t *low, uint64_t n, uint32_t *counters) {
+    uint32_t lows = 0;
+    for (uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; id < n; id += (uint64_t)gridDim.x * blockDim.x) {
+        const bool lo = a.alive[id] && low[id];
+        a.low[id] = lo;
+        lows += lo ? 1u : 0u;
+    }
+    block_add((int32_t)lows, &counters[1]);
 }
 
 __global__ void k_prio_fetch(ProbeArgs a, const uint32_t *ids, uint32_t n, uint32_t run, float src_scale, float *x,
@@ -226,11 +351,12 @@ void grow(Ctx &c, Priority &p, uint64_t need) {
     move(p.birth, 4, 1);
     move(p.src, 4, 1);
     move(p.hits, 4, 1);
-    move(p.hist, 4, kHist);
+    move(p.hist, 16, 1);
     move(p.lbd, 4, 1);
     move(p.score, 4, 1);
     move(p.alive, 1, 1);
     move(p.low, 1, 1);
+    move(p.dirty, 1, 1);
     p.cap = cap;
 }
 
@@ -300,8 +426,8 @@ void priority_release(Ctx &c) {
     Priority *p = c.prio;
     if (!p) return;
     for (void *q : {(void *)p->len, (void *)p->birth, (void *)p->src, (void *)p->hits, (void *)p->hist, (void *)p->lbd,
-                    (void *)p->score, (void *)p->alive, (void *)p->low, (void *)p->sx, (void *)p->sy,
-                    (void *)p->counters, (void *)p->params})
+                    (void *)p->score, (void *)p->alive, (void *)p->low, (void *)p->dirty, (void *)p->sx, (void *)p->sy,
+                    (void *)p->counters, (void *)p->params, (void *)p->list})
         c.dfree(q);
     if (p->h_counters) (void)hipHostFree(p->h_counters);
     delete p;
@@ -411,7 +537,8 @@ extern "C" gss_status gss_priority_observe(gss_ctx *ctx) {
                            args_of(p), c.reports, c.seg_counts, c.seg_cap, c.last_waves);
     GSS_HIP(hipGetLastError());
     if (p.n_ids)
-        hipLaunchKernelGGL(k_prio_observe, dim3(grid_of(p.n_ids)), dim3(256), 0, c.stream, args_of(p), p.n_ids, p.run,
+        hipLaunchKernelGGL(k_prio_observe, dim3(grid_of(p.n_ids, 256 * kPerThread)), dim3(256), 0, c.stream, args_of(p),
+                           p.n_ids, p.run,
                            (c.last_flags & GSS_TEST_SCHEDULED) ? 1u : 0u, src_scale(p), p.cfg.sample_period,
                            p.cfg.seed, p.sx, p.sy, p.cfg.sample_capacity, p.counters);
     GSS_HIP(hipGetLastError());
@@ -476,10 +603,44 @@ extern "C" gss_status gss_priority_score(gss_ctx *ctx, float threshold, uint64_t
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
     launch_fill_u32(c, p.counters + 1, 1, 0);
     if (p.n_ids)
-        hipLaunchKernelGGL(k_prio_score, dim3(grid_of(p.n_ids)), dim3(256), 0, c.stream, args_of(p), p.params, p.n_ids,
-                           p.run, src_scale(p), threshold, p.counters);
+        hipLaunchKernelGGL(k_prio_score, dim3(std::min<uint64_t>(grid_of(p.n_ids), (uint64_t)c.n_cu * 16)), dim3(256), 0,
+                           c.stream, args_of(p), p.params, p.n_ids, p.run, src_scale(p), threshold, p.counters);
     GSS_HIP(hipGetLastError());
     p.threshold = threshold;
+    p.scored = true;
+    p.score_epoch++;
+    if (out_n_low) {
+        GSS_HIP(hipMemcpyAsync(p.h_counters, p.counters, 8, hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+        *out_n_low = p.h_counters[1];
+    }
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_update(gss_ctx *ctx, uint64_t *out_n_low) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(p.scored, GSS_ERR_STATE, "gss_priority_update needs a full scoring first (gss_priority_score)");
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    if (p.n_ids) {
+        if (p.list_cap < p.cap) {
+            c.sync();
+            c.dfree(p.list);
+            p.list = nullptr;
+            p.list_cap = 0;
+            p.list = (uint32_t *)c.dalloc(p.cap * 4);
+            p.list_cap = p.cap;
+        }
+        launch_fill_u32(c, p.counters + 2, 1, 0);
+        hipLaunchKernelGGL(k_prio_collect, dim3(grid_of(p.n_ids, 256 * kPerThread)), dim3(256), 0, c.stream, args_of(p),
+                           p.n_ids, p.list, p.counters);
+        GSS_HIP(hipGetLastError());
+        const unsigned grid = (unsigned)std::min<uint64_t>(grid_of(p.n_ids), (uint64_t)c.n_cu * 16);
+        hipLaunchKernelGGL(k_prio_score_list, dim3(grid), dim3(256), 0, c.stream, args_of(p), p.params, p.list, p.run,
+                           src_scale(p), p.threshold, p.counters);
+        GSS_HIP(hipGetLastError());
+    }
     p.score_epoch++;
     if (out_n_low) {
         GSS_HIP(hipMemcpyAsync(p.h_counters, p.counters, 8, hipMemcpyDeviceToHost, c.stream));
@@ -502,12 +663,13 @@ extern "C" gss_status gss_priority_mark(gss_ctx *ctx, const uint8_t *low, uint64
         c.sync();
         char *st = mlp_stage(c, w, n);
         GSS_HIP(hipMemcpyAsync(st, low, n, hipMemcpyHostToDevice, c.stream));
-        hipLaunchKernelGGL(k_prio_mark, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), (const uint8_t *)st, n,
-                           p.counters);
+        hipLaunchKernelGGL(k_prio_mark, dim3(std::min<uint64_t>(grid_of(n), (uint64_t)c.n_cu * 16)), dim3(256), 0,
+                           c.stream, args_of(p), (const uint8_t *)st, n, p.counters);
         GSS_HIP(hipGetLastError());
         c.sync();
     }
     p.score_epoch++;
+    p.scored = false;  // low flags of another policy: an update would mix the two
     GSS_API_END
 }
 

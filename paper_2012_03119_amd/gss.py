@@ -185,6 +185,7 @@ def load_library(path: Optional[str] = None):
         "gss_priority_score": ([P, ctypes.c_float, P], ctypes.c_int32),
         "gss_priority_params": ([P, P, P], ctypes.c_int32),
         "gss_priority_mark": ([P, P, u64], ctypes.c_int32),
+        "gss_priority_update": ([P, P], ctypes.c_int32),
         "gss_priority_fetch": ([P, P, u32, P, P, P], ctypes.c_int32),
         "gss_priority_samples": ([P, P, P, u64, P], ctypes.c_int32),
         "gss_priority_info": ([P, P, P, P], ctypes.c_int32),
@@ -659,6 +660,11 @@ class Context:
     def priority_score(self, threshold: float) -> int:
         n = ctypes.c_uint64()
         _check(self.ctx, load_library().gss_priority_score(self.ctx, ctypes.c_float(threshold), ctypes.byref(n)))
+        return n.value
+
+    def priority_update(self) -> int:
+        n = ctypes.c_uint64()
+        _check(self.ctx, load_library().gss_priority_update(self.ctx, ctypes.byref(n)))
         return n.value
 
     def priority_mark(self, low) -> None:

@@ -49,7 +49,7 @@ def stats(args) -> None:
     print("| kernel | calls | total ms | average us | min us | max us | % |")
     print("|---|---:|---:|---:|---:|---:|---:|")
     for r in rows[:args.top]:
-        name = r["Name"].removeprefix("void ").split("(")[0]
+        name = r["Name"].removeprefix("void ").replace("(anonymous namespace)::", "").split("(")[0]
         print(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
               f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
               f"{float(r['Percentage']):.1f} |")

@@ -198,3 +198,39 @@ def test_trained_schedule_misses_at_most_one_percent():
     print(f"[learned] threshold {tau:.4f}, {n_low} of {n} clauses low, missed {missed:.4f} of {hits_plain} hits",
           flush=True)
     assert hits_plain > 0 and missed <= 0.01, f"missed {missed:.4f} of {hits_plain} hits"
+
+
+def test_update_rescores_exactly_the_changed_clauses():
+    rng = np.random.default_rng(13)
+    V, n_words, n = 2000, 2, 8000
+    lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, n), V)
+    vals = _stream_values(rng, n_words, V)
+    params, _, _ = _problem(14, 1, scale=0.2)
+    with new_context(V, 64 * n_words) as ctx:
+        ids = ctx.add_clauses(lits, offs)
+        ctx.priority_enable(n_sources=1, seed=2)
+        ctx.priority_params(set_to=params)
+        ctx.set_assignments(0, vals)
+        ctx.test()
+        ctx.priority_observe()
+        x0, _, _ = ctx.priority_fetch(ids)
+        tau = float(np.median(P.forward(params.astype(np.float64), x0.astype(np.float64))["prob"]))
+        ctx.priority_score(tau)
+        _, s0, _ = ctx.priority_fetch(ids)
+        _redraw(rng, vals, 0.2)
+        ctx.set_assignments(0, vals)
+        ctx.test()
+        ctx.priority_observe()
+        x1, _, _ = ctx.priority_fetch(ids)
+        n_low = ctx.priority_update()
+        _, s1, low1 = ctx.priority_fetch(ids)
+    # rescored: a history that moved this run and a hit that may change the clause's side
+    moved = np.any(x1[:, 4:] != 0, axis=1)
+    hit = x1[:, 4] > 0
+    low0 = s0 < tau
+    changed = moved & np.where(low0, hit, ~hit)
+    assert 0 < changed.sum() < n
+    want = P.forward(params.astype(np.float64), x1.astype(np.float64))["prob"]
+    np.testing.assert_allclose(s1[changed], want[changed], atol=2e-6)
+    np.testing.assert_array_equal(s1[~changed], s0[~changed])  # the others keep their scores
+    assert (low1 == (s1 < tau)).all() and n_low == low1.sum()
