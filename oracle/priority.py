@@ -21,7 +21,9 @@ that extension, in float64:
 * loss: mean binary cross-entropy, written as softplus(z3) - y z3;
 * training: Adam (Kingma and Ba, 2015) on minibatches taken in a given order;
 * schedule: in run r, a clause whose score is below the threshold is tested
-  only when (r + id) mod 4 = 0; every other clause is tested in every run.
+  only when (r + id) mod 4 = 0; every other clause is tested in every run;
+* activity (Section 3.7): MiniSat-style, bumped by decay**-r when a clause hits
+  in run r; a reduction keeps the most active clauses, the newest among equals.
 """
 from __future__ import annotations
 
@@ -126,6 +128,25 @@ def tested(ids, low, run: int) -> np.ndarray:
     whose (run + id) mod 4 is not 0."""
     ids = np.asarray(ids, dtype=np.int64)
     return ~np.asarray(low, dtype=bool) | ((run + ids) % 4 == 0)
+
+
+def activity(hits_by_run, decay: float) -> np.ndarray:
+    """MiniSat-style clause activity after the given runs (Section 3.7: the GPU
+    deletes clauses by activity, bumped whenever a clause triggers): in run r
+    (0-based) every clause with a hit gains decay**-r, the bump that grows by
+    1/decay after each run.  hits_by_run: [runs][n] hit counts (or booleans)."""
+    h = np.asarray(hits_by_run) > 0
+    bumps = np.power(float(decay), -np.arange(h.shape[0], dtype=np.float64))
+    return bumps @ h.astype(np.float64)
+
+
+def reduce_keep(act, ids, keep: int) -> np.ndarray:
+    """The ids a reduction to `keep` clauses keeps: the highest activities, and
+    among equal activities the newest (larger id)."""
+    act = np.asarray(act, dtype=np.float64)
+    ids = np.asarray(ids)
+    order = np.lexsort((ids, act))  # ascending activity, then ascending id: removal order
+    return np.sort(ids[order[len(ids) - keep:]]) if keep < len(ids) else np.sort(ids)
 
 
 def hit_counts(dense: np.ndarray) -> np.ndarray:

@@ -105,3 +105,29 @@ def test_schedule_by_enumeration():
 def test_hit_counts():
     dense = np.array([[0, 1], [2**64 - 1, 3], [0, 0]], dtype=np.uint64)
     np.testing.assert_array_equal(P.hit_counts(dense), [1, 66, 0])
+
+
+def test_activity_closed_forms():
+    decay = 0.95
+    runs = 6
+    always = np.ones((runs, 1))
+    # geometric series: sum over r of decay**-r
+    want = (decay ** -runs - 1) / (decay ** -1 - 1)
+    assert abs(P.activity(always, decay)[0] - want) < 1e-12
+    # a single hit in run r is worth decay**-r; later hits weigh more
+    one = np.zeros((runs, runs))
+    one[np.arange(runs), np.arange(runs)] = 3
+    np.testing.assert_allclose(P.activity(one, decay), decay ** -np.arange(runs))
+    # decay 1: activity counts the runs with a hit
+    h = np.random.default_rng(1).integers(0, 3, (9, 50))
+    np.testing.assert_array_equal(P.activity(h, 1.0), (h > 0).sum(axis=0))
+
+
+def test_reduce_keep_by_enumeration():
+    act = np.array([0.5, 2.0, 0.5, 1.0, 0.0, 2.0])
+    ids = np.array([10, 11, 12, 13, 14, 15])
+    assert list(P.reduce_keep(act, ids, 6)) == [10, 11, 12, 13, 14, 15]
+    assert list(P.reduce_keep(act, ids, 3)) == [11, 13, 15]
+    # 0.5 tie: the newer of 10 and 12 stays
+    assert list(P.reduce_keep(act, ids, 4)) == [11, 12, 13, 15]
+    assert list(P.reduce_keep(act, ids, 0)) == []
