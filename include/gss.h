@@ -323,7 +323,8 @@ typedef struct gss_priority_config {
                                  (seed, id, run) is 0 modulo the period; 0 = no samples */
     uint64_t sample_capacity; /* rows of the sample buffer */
     uint64_t seed;            /* sampling and weight initialisation */
-    uint64_t reserved[4];
+    double activity_decay;    /* Section 3.7 activity: the bump grows by 1/decay per run; 0 = 0.999 */
+    uint64_t reserved[3];
 } gss_priority_config;
 
 /* Enables the priority on a context: per-clause state for every issued id (LBD
@@ -360,6 +361,15 @@ gss_status gss_priority_params(gss_ctx *ctx, float *get, const float *set);
 /* Features ([n][12]), last scores and low flags of n issued ids (host arrays). */
 gss_status gss_priority_fetch(gss_ctx *ctx, const uint32_t *ids, uint32_t n, float *out_features, float *out_scores,
                               uint8_t *out_low);
+/* Activity-based deletion (Section 3.7, the GPU deletes clauses like MiniSat
+ * on the CPU): every observed run adds the current bump to the activity of each
+ * clause with a hit, then the bump grows by 1/activity_decay (activities are
+ * rescaled together when it grows large).  gss_priority_reduce removes live
+ * clauses, least active first (the older among equals), until `keep` remain;
+ * *out_removed (may be NULL) receives how many.  gss_priority_activity copies the
+ * activities of n issued ids (host arrays). */
+gss_status gss_priority_reduce(gss_ctx *ctx, uint64_t keep, uint64_t *out_removed);
+gss_status gss_priority_activity(gss_ctx *ctx, const uint32_t *ids, uint32_t n, float *out_activity);
 /* Copies up to cap samples ([cap][12] features, [cap] labels; host, either may be NULL). */
 gss_status gss_priority_samples(gss_ctx *ctx, float *out_x, float *out_y, uint64_t cap, uint64_t *out_n);
 /* Run counter, samples held, low clauses of the last scoring. */

@@ -31,6 +31,7 @@ struct Priority {
     uint32_t *len = nullptr, *birth = nullptr, *src = nullptr, *hits = nullptr;
     uint4 *hist = nullptr;  // [cap]: 8 hit counts of 16 bits, most recent in the low bits of .x
     float *lbd = nullptr, *score = nullptr;
+    float *act = nullptr;  // activity (Section 3.7)
     uint8_t *alive = nullptr, *low = nullptr;
     uint8_t *dirty = nullptr;  // features changed (beyond age) since the clause was last scored
     float *sx = nullptr, *sy = nullptr;  // samples [sample_cap][kFeat], [sample_cap]
@@ -42,6 +43,8 @@ struct Priority {
     uint64_t score_epoch = 0;
     uint64_t built_version = ~0ull, built_epoch = ~0ull;
     float threshold = 0.f;
+    double decay = 0.999;  // activity bump growth 1/decay per run
+    double bump = 1.0;     // current bump
     uint32_t *list = nullptr;  // ids of the clauses an update rescores
     uint64_t list_cap = 0;
     bool scored = false;  // a full scoring (or marking) has set every low flag
@@ -63,13 +66,13 @@ __device__ inline uint64_t mix64(uint64_t z) {
 struct ProbeArgs {  // per-id arrays as the kernels see them
     uint32_t *len, *birth, *src, *hits;
     uint4 *hist;
-    float *lbd, *score;
+    float *lbd, *score, *act;
     uint8_t *alive, *low, *dirty;
     uint64_t cap;
 };
 
 ProbeArgs args_of(const Priority &p) {
-    return ProbeArgs{p.len, p.birth, p.src, p.hits, p.hist, p.lbd, p.score, p.alive, p.low, p.dirty, p.cap};
+    return ProbeArgs{p.len, p.birth, p.src, p.hits, p.hist, p.lbd, p.score, p.act, p.alive, p.low, p.dirty, p.cap};
 }
 
 __device__ inline void load_features(const ProbeArgs &a, uint64_t id, uint32_t run, float src_scale,
@@ -96,6 +99,7 @@ __global__ void k_prio_init(ProbeArgs a, uint64_t first, uint32_t n, const uint3
     a.low[id] = 0;
     a.dirty[id] = 1;
     a.score[id] = 1.f;
+    a.act[id] = 0.f;
 }
 
 __global__ void k_prio_kill(ProbeArgs a, const uint32_t *ids, uint32_t n) {
@@ -167,7 +171,7 @@ __global__ void k_prio_hits(ProbeArgs a, const gss_report *reports, const uint32
 // rows with one atomic.
 __global__ __launch_bounds__(256) void k_prio_observe(ProbeArgs a, uint64_t n_ids, uint32_t run, uint32_t scheduled,
                                                       float src_scale, uint32_t period, uint64_t seed, float *sx,
-                                                      float *sy, uint64_t sample_cap, uint32_t *counters) {
+                                                      float *sy, uint64_t sample_cap, uint32_t *counters, float bump) {
     __shared__ uint32_t base_s;
     const uint64_t first = (uint64_t)blockIdx.x * 256 * kPerThread + threadIdx.x;
     auto is_tested = [&](uint64_t id, bool &live) {
@@ -216,8 +220,21 @@ __global__ __launch_bounds__(256) void k_prio_observe(ProbeArgs a, uint64_t n_id
                 if (a.low[id] ? h != 0 : h == 0) a.dirty[id] = 1;
             }
         }
-        if (h) a.hits[id] = 0;
+        if (h) {
+            a.act[id] += bump;  // Section 3.7: bumped whenever the clause triggers
+            a.hits[id] = 0;
+        }
     }
+}
+
+__global__ void k_prio_scale(float *act, uint64_t n, float f) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        act[i] *= f;
+}
+
+__global__ void k_prio_gather_act(ProbeArgs a, const uint32_t *ids, uint32_t n, float *out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a.act[ids[i]];
 }
 
 // Scores every live clause and sets its low flag; counters[1] receives the
@@ -354,6 +371,7 @@ void grow(Ctx &c, Priority &p, uint64_t need) {
     move(p.hist, 16, 1);
     move(p.lbd, 4, 1);
     move(p.score, 4, 1);
+    move(p.act, 4, 1);
     move(p.alive, 1, 1);
     move(p.low, 1, 1);
     move(p.dirty, 1, 1);
@@ -426,7 +444,7 @@ void priority_release(Ctx &c) {
     Priority *p = c.prio;
     if (!p) return;
     for (void *q : {(void *)p->len, (void *)p->birth, (void *)p->src, (void *)p->hits, (void *)p->hist, (void *)p->lbd,
-                    (void *)p->score, (void *)p->alive, (void *)p->low, (void *)p->dirty, (void *)p->sx, (void *)p->sy,
+                    (void *)p->score, (void *)p->act, (void *)p->alive, (void *)p->low, (void *)p->dirty, (void *)p->sx, (void *)p->sy,
                     (void *)p->counters, (void *)p->params, (void *)p->list})
         c.dfree(q);
     if (p->h_counters) (void)hipHostFree(p->h_counters);
@@ -447,8 +465,11 @@ extern "C" gss_status gss_priority_enable(gss_ctx *ctx, const gss_priority_confi
     GSS_REQUIRE(cfg->sample_period == 0 || cfg->sample_capacity >= 1, GSS_ERR_INVALID_ARG,
                 "sampling needs a sample capacity");
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    GSS_REQUIRE(cfg->activity_decay == 0 || (cfg->activity_decay > 0 && cfg->activity_decay <= 1), GSS_ERR_INVALID_ARG,
+                "activity_decay must be in (0, 1]");
     auto p = std::make_unique<Priority>();
     p->cfg = *cfg;
+    p->decay = cfg->activity_decay ? cfg->activity_decay : 0.999;
     c.prio = p.get();
     try {
         Priority &q = *p;
@@ -540,10 +561,18 @@ extern "C" gss_status gss_priority_observe(gss_ctx *ctx) {
         hipLaunchKernelGGL(k_prio_observe, dim3(grid_of(p.n_ids, 256 * kPerThread)), dim3(256), 0, c.stream, args_of(p),
                            p.n_ids, p.run,
                            (c.last_flags & GSS_TEST_SCHEDULED) ? 1u : 0u, src_scale(p), p.cfg.sample_period,
-                           p.cfg.seed, p.sx, p.sy, p.cfg.sample_capacity, p.counters);
+                           p.cfg.seed, p.sx, p.sy, p.cfg.sample_capacity, p.counters, (float)p.bump);
     GSS_HIP(hipGetLastError());
     p.observed_serial = c.test_serial;
     p.run++;
+    p.bump /= p.decay;
+    if (p.bump > 1e20) {  // keep activities in float range: scale all of them and the bump
+        if (p.n_ids)
+            hipLaunchKernelGGL(k_prio_scale, dim3((unsigned)std::min<uint64_t>(grid_of(p.n_ids), 65536)), dim3(256), 0,
+                               c.stream, p.act, p.n_ids, 1e-20f);
+        GSS_HIP(hipGetLastError());
+        p.bump *= 1e-20;
+    }
     GSS_API_END
 }
 
@@ -704,6 +733,54 @@ extern "C" gss_status gss_priority_fetch(gss_ctx *ctx, const uint32_t *ids, uint
     GSS_HIP(hipMemcpyAsync(out_features, st + ib, (size_t)n * kFeat * 4, hipMemcpyDeviceToHost, c.stream));
     GSS_HIP(hipMemcpyAsync(out_scores, st + ib + xb, (size_t)n * 4, hipMemcpyDeviceToHost, c.stream));
     GSS_HIP(hipMemcpyAsync(out_low, st + ib + xb + sb, n, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_reduce(gss_ctx *ctx, uint64_t keep, uint64_t *out_removed) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    if (out_removed) *out_removed = 0;
+    if (c.live <= keep) return GSS_OK;
+    // activities of every issued id to the host; the live ones sorted, least active first
+    std::vector<float> act(p.n_ids);
+    if (p.n_ids) GSS_HIP(hipMemcpyAsync(act.data(), p.act, p.n_ids * 4, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    std::vector<uint32_t> live;
+    live.reserve(c.live);
+    for (uint64_t id = 0; id < c.id_loc.size(); ++id)
+        if (c.id_loc[id] != kNoLoc) live.push_back((uint32_t)id);
+    const uint64_t n_rm = live.size() - keep;
+    auto before = [&](uint32_t x, uint32_t y) { return act[x] != act[y] ? act[x] < act[y] : x < y; };
+    std::nth_element(live.begin(), live.begin() + (ptrdiff_t)(n_rm - 1), live.end(), before);
+    std::vector<uint32_t> rm(live.begin(), live.begin() + (ptrdiff_t)n_rm);
+    for (uint64_t k = 0; k < n_rm; k += 1u << 24) {
+        const uint32_t m = (uint32_t)std::min<uint64_t>(n_rm - k, 1u << 24);
+        const gss_status rc = gss_remove_clauses(ctx, rm.data() + k, m);
+        if (rc != GSS_OK) throw Error(rc, c.last_error);
+    }
+    if (out_removed) *out_removed = n_rm;
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_activity(gss_ctx *ctx, const uint32_t *ids, uint32_t n, float *out_activity) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    if (n == 0) return GSS_OK;
+    GSS_REQUIRE(ids && out_activity, GSS_ERR_INVALID_ARG, "null argument");
+    for (uint32_t i = 0; i < n; ++i) GSS_REQUIRE(ids[i] < p.n_ids, GSS_ERR_UNKNOWN_ID, "clause id never issued");
+    MlpWork &w = mlp_work(c);
+    const size_t ib = ((size_t)n * 4 + 255) / 256 * 256;
+    c.sync();
+    char *st = mlp_stage(c, w, 2 * ib);
+    GSS_HIP(hipMemcpyAsync(st, ids, (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
+    hipLaunchKernelGGL(k_prio_gather_act, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), (const uint32_t *)st, n,
+                       (float *)(st + ib));
+    GSS_HIP(hipGetLastError());
+    GSS_HIP(hipMemcpyAsync(out_activity, st + ib, (size_t)n * 4, hipMemcpyDeviceToHost, c.stream));
     c.sync();
     GSS_API_END
 }

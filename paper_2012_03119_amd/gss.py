@@ -96,7 +96,8 @@ class gss_adam_config(ctypes.Structure):
 
 class gss_priority_config(ctypes.Structure):
     _fields_ = [("n_sources", ctypes.c_uint32), ("sample_period", ctypes.c_uint32),
-                ("sample_capacity", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 4)]
+                ("sample_capacity", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("activity_decay", ctypes.c_double),
+                ("reserved", ctypes.c_uint64 * 3)]
 
 
 MLP_FEATURES = 12
@@ -186,6 +187,8 @@ def load_library(path: Optional[str] = None):
         "gss_priority_params": ([P, P, P], ctypes.c_int32),
         "gss_priority_mark": ([P, P, u64], ctypes.c_int32),
         "gss_priority_update": ([P, P], ctypes.c_int32),
+        "gss_priority_reduce": ([P, u64, P], ctypes.c_int32),
+        "gss_priority_activity": ([P, P, u32, P], ctypes.c_int32),
         "gss_priority_fetch": ([P, P, u32, P, P, P], ctypes.c_int32),
         "gss_priority_samples": ([P, P, P, u64, P], ctypes.c_int32),
         "gss_priority_info": ([P, P, P, P], ctypes.c_int32),
@@ -632,8 +635,8 @@ class Context:
 
     # -- learned priority
     def priority_enable(self, *, n_sources: int = 1, sample_period: int = 0, sample_capacity: int = 0,
-                        seed: int = 0) -> None:
-        cfg = gss_priority_config(n_sources, sample_period, sample_capacity, seed)
+                        seed: int = 0, activity_decay: float = 0.0) -> None:
+        cfg = gss_priority_config(n_sources, sample_period, sample_capacity, seed, activity_decay)
         _check(self.ctx, load_library().gss_priority_enable(self.ctx, ctypes.byref(cfg)))
 
     def priority_set_clause_info(self, ids, lbd, source) -> None:
@@ -666,6 +669,17 @@ class Context:
         n = ctypes.c_uint64()
         _check(self.ctx, load_library().gss_priority_update(self.ctx, ctypes.byref(n)))
         return n.value
+
+    def priority_reduce(self, keep: int) -> int:
+        n = ctypes.c_uint64()
+        _check(self.ctx, load_library().gss_priority_reduce(self.ctx, keep, ctypes.byref(n)))
+        return n.value
+
+    def priority_activity(self, ids) -> np.ndarray:
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        out = np.zeros(ids.size, dtype=np.float32)
+        _check(self.ctx, load_library().gss_priority_activity(self.ctx, _np_ptr(ids), ids.size, _np_ptr(out)))
+        return out
 
     def priority_mark(self, low) -> None:
         low = np.ascontiguousarray(low, dtype=np.uint8)

@@ -234,3 +234,44 @@ def test_update_rescores_exactly_the_changed_clauses():
     np.testing.assert_allclose(s1[changed], want[changed], atol=2e-6)
     np.testing.assert_array_equal(s1[~changed], s0[~changed])  # the others keep their scores
     assert (low1 == (s1 < tau)).all() and n_low == low1.sum()
+
+
+def test_activity_and_reduce_follow_the_oracle():
+    """Section 3.7: activities bumped on every hit and a reduction that keeps the
+    most active clauses.  With decay 1/2 every bump is a power of two, so the fp32
+    activities are exact and the kept set must match the oracle's."""
+    rng = np.random.default_rng(15)
+    V, n_words = 1500, 2
+    lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, 4000), V)
+    l2, o2 = gen.random_clauses(rng, rng.integers(1, 4, 3000), V)  # short: frequent hits
+    lits = np.concatenate([lits, l2])
+    offs = np.concatenate([offs, offs[-1] + o2[1:]])
+    n = len(offs) - 1
+    vals = _stream_values(rng, n_words, V)
+    hits_by_run = []
+    with new_context(V, 64 * n_words) as ctx:
+        ids = ctx.add_clauses(lits, offs)
+        ctx.priority_enable(n_sources=1, seed=3, activity_decay=0.5)
+        for r in range(6):
+            ctx.set_assignments(0, vals)
+            ctx.test()
+            ctx.priority_observe()
+            hits_by_run.append(P.hit_counts(oracle.masks(lits, offs, vals)))
+            _redraw(rng, vals, 0.3)
+        act = ctx.priority_activity(ids)
+        want = P.activity(hits_by_run, 0.5)
+        np.testing.assert_array_equal(act, want)
+        keep = n // 3
+        assert ctx.priority_reduce(keep) == n - keep
+        assert ctx.store_info()["live_clauses"] == keep
+        kept = P.reduce_keep(want, ids, keep)
+        # the store now holds exactly the kept clauses: a test on new values shows it
+        ctx.set_assignments(0, vals)
+        m = ctx.test()
+        got = np.sort(ctx.fetch_reports(m), order=["clause_id", "word"])
+        assert ctx.priority_reduce(keep) == 0  # nothing more to remove
+    mask = np.zeros(n, dtype=bool)
+    mask[kept] = True
+    dense = oracle.masks(lits, offs, vals)
+    want_r = oracle.report_set(np.where(mask[:, None], dense, np.uint64(0)), ids)
+    assert len(got) == len(want_r) and (got == want_r).all()
