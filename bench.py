@@ -123,16 +123,22 @@ def bench_batched(args, torch, gss):
             ctx.set_var_values(0, vs, delta)
 
     def run(step_fn):
+        """(ms per round with the deltas, ms per round of the tests alone)"""
         for i in range(args.warmup):
             deltas(i)
             step_fn()
         torch.cuda.synchronize()
         t = time.perf_counter()
+        t_test = 0.0
         for i in range(args.steps):
             deltas(args.warmup + i)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
             step_fn()
+            torch.cuda.synchronize()
+            t_test += time.perf_counter() - t1
         torch.cuda.synchronize()
-        return (time.perf_counter() - t) / args.steps
+        return (time.perf_counter() - t) / args.steps, t_test / args.steps
 
     def batched_step():
         batch.test(gss.GSS_TEST_GRAPH)
@@ -141,9 +147,9 @@ def bench_batched(args, torch, gss):
         for _, ctx, _ in stores:
             ctx.test()
 
-    t_batch = run(batched_step)
+    t_batch, t_batch_test = run(batched_step)
     graph_ms = batch.info()["last_ms"]
-    t_plain = run(plain_step)
+    t_plain, t_plain_test = run(plain_step)
     pairs = sum(ctx.stats()["last_pairs"] for _, ctx, _ in stores)
     out = {
         "metric": "clause x assignment tests/sec (batched: 8 databases, one persistent launch)",
@@ -154,11 +160,14 @@ def bench_batched(args, torch, gss):
                                "assignments, length mix, 5% flips per round",
                    "stores": [list(x) for x in BATCHED_STORES], "schedule": {k: tune[k] for k in
                    ("order", "chunk_tiles", "blocks_per_cu")}, "graph_launch_ms": graph_ms},
-        "plain": {"value": pairs / t_plain, "ms_per_step": t_plain * 1e3,
+        "tests_ms_per_round": t_batch_test * 1e3,
+        "plain": {"value": pairs / t_plain, "ms_per_step": t_plain * 1e3, "tests_ms_per_round": t_plain_test * 1e3,
                   "how": "the same rounds, one gss_test per database"},
         "speedup_vs_plain": t_plain / t_batch,
+        "tests_speedup_vs_plain": t_plain_test / t_batch_test,
     }
-    log(f"batched {t_batch * 1e3:.3f} ms/step vs plain {t_plain * 1e3:.3f} ms/step")
+    log(f"batched {t_batch * 1e3:.3f} ms/step vs plain {t_plain * 1e3:.3f} ms/step; tests alone "
+        f"{t_batch_test * 1e3:.3f} vs {t_plain_test * 1e3:.3f} ms")
     batch.close()
     for _, ctx, _ in stores:
         ctx.close()
