@@ -76,7 +76,8 @@ const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n) {
 void check_flag(Ctx &c) {
     GSS_HIP(hipMemcpyAsync(c.hsmall, c.dsmall, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
     c.sync();
-    GSS_REQUIRE(c.hsmall[0] == 0, GSS_ERR_INVALID_ARG, "truth values must be -1, 0 or +1");
+    GSS_REQUIRE(!(c.hsmall[0] & 1u), GSS_ERR_INVALID_ARG, "truth values must be -1, 0 or +1");
+    GSS_REQUIRE(!(c.hsmall[0] & 2u), GSS_ERR_INVALID_ARG, "variable listed twice");
 }
 
 bool is_device_pointer(const void *p) {
@@ -219,6 +220,7 @@ static void destroy_ctx(Ctx *c) {
     }
     c->dfree(c->planes);
     c->dfree(c->agg);
+    c->dfree(c->var_bits);
     c->dfree(c->active);
     c->dfree(c->reports);
     c->dfree(c->seg_counts);

@@ -144,6 +144,7 @@ struct Ctx {
     uint64_t *active = nullptr;
     std::vector<uint64_t> h_active;
     std::vector<uint64_t> var_seen;  // scratch bitmap for argument checks (kept all-zero)
+    uint32_t *var_bits = nullptr;    // device twin of var_seen for device-input checks (kept all-zero)
 
     Bucket buckets[kMaxBuckets];
     std::vector<uint64_t> id_loc;  // per id: bucket << 40 | slot, or kNoLoc
@@ -162,6 +163,7 @@ struct Ctx {
     uint32_t *dsmall = nullptr;              // 256 B device scratch for flags
     uint32_t *hsmall = nullptr;              // 256 B pinned host
     void *d_desc = nullptr;                  // device copy of the test kernel's bucket descriptors
+    uint64_t desc_version = ~0ull;           // store version the device copy describes
     void *hsmall_desc = nullptr;             // pinned host staging of the same
     uint64_t test_serial = 0;  // tests completed by this context
     uint64_t n_reports = 0;  // records found by the last test

@@ -213,6 +213,28 @@ static void check_vars(Ctx &c, const uint32_t *vars, uint32_t n_vars) {
     GSS_REQUIRE(bad != 2, GSS_ERR_INVALID_ARG, "variable listed twice");
 }
 
+// Every listed variable in 1..num_vars (the cheap half of check_vars).
+static void check_var_range(const Ctx &c, const uint32_t *vars, uint32_t n_vars) {
+    uint32_t bad = 0;
+    const uint32_t V = c.cfg.num_vars;
+    for (uint32_t i = 0; i < n_vars; ++i) bad |= (uint32_t)(vars[i] - 1u >= V);
+    GSS_REQUIRE(!bad, GSS_ERR_BAD_LITERAL, "variable out of range");
+}
+
+// Device half of the variable check: a variable listed twice sets bit 2 of
+// *bad (one bitmap bit per variable, cleared again by k_clear_vars).
+__global__ void k_check_vars(const uint32_t *vars, uint32_t n, uint32_t *bits, uint32_t *bad) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = vars[i], m = 1u << (v & 31);
+    if (atomicOr(&bits[v >> 5], m) & m) atomicOr(bad, 2u);
+}
+
+__global__ void k_clear_vars(const uint32_t *vars, uint32_t n, uint32_t *bits) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) bits[vars[i] >> 5] = 0;
+}
+
 static void check_values_host(const int8_t *v, uint64_t n) {
     uint8_t bad = 0;
     for (uint64_t i = 0; i < n; ++i) bad |= (uint8_t)((uint8_t)(v[i] + 1) > 2);
@@ -270,14 +292,22 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
         const uint64_t sm = slot_mask(first_slot, n_slots, w);
         GSS_REQUIRE((c.h_active[w] & sm) == sm, GSS_ERR_INVALID_ARG, "slot range includes inactive slots");
     }
-    check_vars(c, vars, n_vars);
     const uint64_t nv = (uint64_t)n_vars * n_slots;
     const bool dev = is_device_pointer(values);
     const uint32_t *bad = c.dsmall + 1;  // always zero
-    if (dev)
+    if (dev) {
+        // device values are checked on the device, and so are repeated variables:
+        // one synchronisation at the end reports either
+        check_var_range(c, vars, n_vars);
         bad = queue_value_check(c, values, nv);
-    else
+        if (!c.var_bits) {
+            c.var_bits = (uint32_t *)c.dalloc(((uint64_t)c.cfg.num_vars / 32 + 1) * 4);
+            launch_fill_u32(c, c.var_bits, (uint64_t)c.cfg.num_vars / 32 + 1, 0);
+        }
+    } else {
+        check_vars(c, vars, n_vars);
         check_values_host(values, nv);
+    }
 
     const size_t vars_bytes = ((size_t)n_vars * 4 + 255) / 256 * 256;
     const size_t bytes = vars_bytes + (dev ? 0 : nv);
@@ -287,11 +317,21 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
     if (!dev) std::memcpy(h + vars_bytes, values, nv);
     GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
     const int8_t *dvals = dev ? values : (const int8_t *)(d + vars_bytes);
+    if (dev) {
+        hipLaunchKernelGGL(k_check_vars, dim3((n_vars + 255) / 256), dim3(256), 0, c.stream, (const uint32_t *)d, n_vars,
+                           c.var_bits, c.dsmall);
+        GSS_HIP(hipGetLastError());
+    }
     const uint32_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
     hipLaunchKernelGGL(k_set_vars, dim3((n_vars + 255) / 256, nw), dim3(256), 0, c.stream, c.planes, c.RW,
                        (const uint32_t *)d, n_vars, dvals, first_slot, n_slots, bad);
     GSS_HIP(hipGetLastError());
     c.agg_valid = false;
+    if (dev) {
+        hipLaunchKernelGGL(k_clear_vars, dim3((n_vars + 255) / 256), dim3(256), 0, c.stream, (const uint32_t *)d, n_vars,
+                           c.var_bits);
+        GSS_HIP(hipGetLastError());
+    }
     c.stage_done(st);
     if (dev) check_flag(c);  // one synchronisation: device inputs are fully read when the call returns
     GSS_API_END

@@ -154,7 +154,11 @@ static Launch prepare(Ctx &c, uint32_t flags) {
         }
         a.agg = c.agg;
     }
-    if (nb) GSS_HIP(hipMemcpyAsync(c.d_desc, h, nb * sizeof(BucketDesc), hipMemcpyHostToDevice, c.stream));
+    // the device copy stays valid while the store is unchanged (schedule bits may move: always upload then)
+    if (nb && (sched || c.desc_version != c.version)) {
+        GSS_HIP(hipMemcpyAsync(c.d_desc, h, nb * sizeof(BucketDesc), hipMemcpyHostToDevice, c.stream));
+        c.desc_version = sched ? ~0ull : c.version;
+    }
     L.descs = (const BucketDesc *)c.d_desc;
     L.fn = pick_kernel(c.RW, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot);
     if (hot) L.lds = (size_t)a.hot_rows * c.RW * 8;

@@ -339,7 +339,22 @@ def test_invalid_device_values_apply_nothing():
         with pytest.raises(gss.GssError) as e:
             ctx.set_var_values(0, vs, badd)
         assert e.value.code == gss.GSS_ERR_INVALID_ARG
+        # a variable listed twice is found on the device too, and nothing is applied
+        twice = np.array([5, 9, 13, 9], dtype=np.uint32)
+        flip = torch.from_numpy(np.ascontiguousarray(-w.values[:, twice - 1].T)).cuda()
+        with pytest.raises(gss.GssError) as e:
+            ctx.set_var_values(0, twice, flip)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG and "twice" in str(e.value)
+        with pytest.raises(gss.GssError) as e:  # out of range: found on the host
+            ctx.set_var_values(0, np.array([5, w.n_vars + 1], dtype=np.uint32), flip[:2])
+        assert e.value.code == gss.GSS_ERR_BAD_LITERAL
         _check(gpu_dense(ctx, w.n_clauses), before)
+        # and the bitmap was cleared: the same variables, once each, apply
+        once = np.array([5, 9, 13], dtype=np.uint32)
+        ctx.set_var_values(0, once, flip[:3].contiguous())
+        vals = w.values.copy()
+        vals[:, once - 1] = -w.values[:, once - 1]
+        _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, vals))
 
 
 def _pack_word(vals_64):
