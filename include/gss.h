@@ -160,12 +160,13 @@ gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots);
 #define GSS_TEST_NO_HOT 32u           /* do not stage hot-variable rows in LDS */
 /* Aggregate pre-test (Section 4): the 64 assignments of a word form a group, and
  * the context keeps, per literal, one bit per word saying whether the literal is
- * F in some slot of it (the group's aggregate).  A clause can only be falsified
- * in a word where all its literals have that bit, so a lane reads a literal's
- * plane words only while the aggregate bits of its words allow it.  The result
- * is the same as without the flag; it is faster when the assignments of a word
- * are similar (as successive assignments of one solver thread are).  Falsified
- * mode only: ignored with GSS_TEST_TRIGGER. */
+ * F in some slot of it (canBeFalse of the group's aggregate) and, per variable,
+ * whether it is U in some active slot (canBeUndef).  A clause can only be
+ * falsified in a word where all its literals can be F, and only trigger where the
+ * aggregate recurrence of Section 4.3 says so (Theorem 1), so a lane reads a
+ * literal's plane words only while the aggregate bits of its words allow it.  The
+ * result is the same as without the flag; it is faster when the assignments of a
+ * word are similar (as successive assignments of one solver thread are). */
 #define GSS_TEST_AGGREGATE 256u
 
 /* Tests every live clause against every active slot (Section 3.6: a GPU run tests

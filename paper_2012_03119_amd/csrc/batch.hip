@@ -43,7 +43,7 @@ template <int LPC, int WPL, int MODE>
 __device__ uint32_t batch_tile(const StoreDesc &st, uint32_t tile, gss_report *seg, uint32_t produced,
                                uint32_t early_exit) {
     using Ts = Tester<LPC, WPL, MODE, false>;
-    const Ts ts(threadIdx.x & 63, st.planes, st.active, st.W, 0, nullptr, 0u, nullptr);
+    const Ts ts(threadIdx.x & 63, st.planes, st.active, st.W, 0, nullptr, 0u, nullptr, nullptr);
     uint32_t bi = 0;
     typename Ts::Tile cur;
     ts.open(st.descs, st.n_buckets, bi, tile, cur);

@@ -220,6 +220,7 @@ static void destroy_ctx(Ctx *c) {
     }
     c->dfree(c->planes);
     c->dfree(c->agg);
+    c->dfree(c->aggu);
     c->dfree(c->var_bits);
     c->dfree(c->active);
     c->dfree(c->reports);

@@ -100,6 +100,7 @@ struct TestArgs {
     uint64_t *dense;          // GSS_TEST_DENSE: [n_ids][W]
     uint32_t sched_run;       // schedule: a low-priority clause is tested when (sched_run + id) % 4 == 0
     const void *agg;          // aggregate bits per row (element of 2, 4 or 8 bytes by RW); null: no pre-test
+    const void *aggu;         // trigger mode: per variable, bit w = word w has an active slot where it is U
 };
 
 // ---------------------------------------------------------------------------
@@ -141,6 +142,8 @@ struct Ctx {
     uint64_t *planes = nullptr;
     void *agg = nullptr;  // per row: bit w set when word w of the row is nonzero (see agg_elem_bytes)
     bool agg_valid = true;  // false after bulk plane updates: rebuilt by the next aggregate test
+    void *aggu = nullptr;   // per variable: bit w set when some active slot of word w has it U
+    bool aggu_valid = false;
     uint64_t *active = nullptr;
     std::vector<uint64_t> h_active;
     std::vector<uint64_t> var_seen;  // scratch bitmap for argument checks (kept all-zero)
@@ -231,6 +234,8 @@ struct Ctx {
 inline uint32_t agg_elem_bytes(uint32_t RW) { return RW <= 16 ? 2u : RW <= 32 ? 4u : 8u; }
 // recomputes the aggregate bits of rows [lo, hi)
 void agg_rebuild(Ctx &c, uint64_t lo, uint64_t hi);
+// recomputes the per-variable U bits (trigger-mode aggregates) of every variable
+void aggu_rebuild(Ctx &c);
 
 // kernels / launchers (defined in the .hip files)
 void launch_fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t value);

@@ -47,6 +47,30 @@ __global__ void k_agg_rows(const uint64_t *planes, uint32_t RW, void *agg, uint6
         agg_put(agg, RW, r, row_nonzero_words(planes, RW, r));
 }
 
+// Trigger-mode aggregate of each variable: bit w = some active slot of word w
+// has the variable U (neither row set there).
+__global__ void k_aggu_rows(const uint64_t *planes, uint32_t RW, const uint64_t *active, uint32_t W, void *aggu,
+                            uint64_t n_vars1) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n_vars1; v += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t bits = 0;
+        for (uint32_t w = 0; w < RW; ++w) {
+            const uint64_t act = w < W ? active[w] : 0ull;
+            const uint64_t set = planes[(2 * v) * RW + w] | planes[(2 * v + 1) * RW + w];
+            bits |= (uint64_t)((set & act) != act) << w;
+        }
+        agg_put(aggu, RW, v, bits);
+    }
+}
+
+void aggu_rebuild(Ctx &c) {
+    const uint64_t n = (uint64_t)c.cfg.num_vars + 1;
+    if (!c.aggu) c.aggu = c.dalloc(n * agg_elem_bytes(c.RW));
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_aggu_rows, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, c.active, c.W, c.aggu, n);
+    GSS_HIP(hipGetLastError());
+    c.aggu_valid = true;
+}
+
 void agg_rebuild(Ctx &c, uint64_t lo, uint64_t hi) {
     if (hi <= lo) return;
     const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((hi - lo + 255) / 256, 65536));
@@ -174,6 +198,7 @@ __global__ void k_clear_slots(uint64_t *planes, uint32_t RW, uint64_t n_rows, ui
 
 void launch_set_words(Ctx &c, uint32_t word, const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n) {
     if (n == 0) return;
+    c.aggu_valid = false;
     const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 255) / 256, 4096));
     hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, word, vars, f, t, n, c.agg);
     GSS_HIP(hipGetLastError());
@@ -187,6 +212,7 @@ static uint64_t slot_mask(uint32_t first, uint32_t n, uint32_t w) {
 }
 
 static void upload_active(Ctx &c) {
+    c.aggu_valid = false;  // U counts active slots only
     const Ctx::Staged st = c.stage_upload(c.W * 8);
     std::memcpy(st.h, c.h_active.data(), c.W * 8);
     GSS_HIP(hipMemcpyAsync(c.active, st.h, c.W * 8, hipMemcpyHostToDevice, c.stream));
@@ -274,6 +300,7 @@ extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uin
     }
     if (dev) check_flag(c);  // throws, having applied nothing, if a value was invalid
     c.agg_valid = false;
+    c.aggu_valid = false;
     for (uint32_t w = first_slot / 64; w <= (last - 1) / 64; ++w) c.h_active[w] |= slot_mask(first_slot, n_slots, w);
     upload_active(c);
     c.sync();  // host inputs are read by the copies above: done before returning
@@ -327,6 +354,7 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
                        (const uint32_t *)d, n_vars, dvals, first_slot, n_slots, bad);
     GSS_HIP(hipGetLastError());
     c.agg_valid = false;
+    c.aggu_valid = false;
     if (dev) {
         hipLaunchKernelGGL(k_clear_vars, dim3((n_vars + 255) / 256), dim3(256), 0, c.stream, (const uint32_t *)d, n_vars,
                            c.var_bits);
@@ -350,6 +378,7 @@ extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_
     hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, n_rows, first_slot, n_slots);
     GSS_HIP(hipGetLastError());
     c.agg_valid = false;
+    c.aggu_valid = false;
     for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w)
         c.h_active[w] &= ~slot_mask(first_slot, n_slots, w);
     upload_active(c);

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
         __syncthreads();
     }
     const uint32_t lane = threadIdx.x & 63;
-    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, a.sched_run, a.agg);
+    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, a.sched_run, a.agg, a.aggu);
     const uint32_t waves_per_block = blockDim.x / 64;
     const uint32_t n_waves = gridDim.x * waves_per_block;
     // wave-uniform by construction; readfirstlane lets the compiler keep it in SGPRs
@@ -147,12 +147,17 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     a.seg_cap = c.seg_cap;
     a.dense = c.dense;
     a.agg = nullptr;
-    if ((flags & GSS_TEST_AGGREGATE) && !(flags & GSS_TEST_TRIGGER)) {
+    a.aggu = nullptr;
+    if (flags & GSS_TEST_AGGREGATE) {
         if (!c.agg_valid) {
             agg_rebuild(c, 0, 2ull * ((uint64_t)c.cfg.num_vars + 1));
             c.agg_valid = true;
         }
         a.agg = c.agg;
+        if (flags & GSS_TEST_TRIGGER) {
+            if (!c.aggu_valid) aggu_rebuild(c);
+            a.aggu = c.aggu;
+        }
     }
     // the device copy stays valid while the store is unchanged (schedule bits may move: always upload then)
     if (nb && (sched || c.desc_version != c.version)) {

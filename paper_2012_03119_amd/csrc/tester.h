@@ -119,12 +119,13 @@ struct Tester {
     uint64_t act[WPL];
     const char *pbase;
     const uint64_t *lds;
-    const AggT *agg;  // null: no aggregate pre-test
+    const AggT *agg;   // null: no aggregate pre-test; else per literal code: words with an F slot
+    const AggT *aggu;  // trigger mode: per variable, words with an active U slot
 
     __device__ Tester(uint32_t lane, const uint64_t *planes, const uint64_t *active, uint32_t W_, uint32_t hot_rows_,
-                      const uint64_t *lds_, uint32_t sched_run_, const void *agg_)
+                      const uint64_t *lds_, uint32_t sched_run_, const void *agg_, const void *aggu_)
         : j(lane / LPC), w0((lane % LPC) * WPL), W(W_), hot_rows(hot_rows_), sched_run(sched_run_), lds(lds_),
-          agg(MODE == 0 ? static_cast<const AggT *>(agg_) : nullptr) {
+          agg(static_cast<const AggT *>(agg_)), aggu(static_cast<const AggT *>(aggu_)) {
         lane_ok = w0 < W;
 #pragma unroll
         for (int i = 0; i < WPL; ++i) act[i] = (w0 + i < W) ? active[w0 + i] : 0;
@@ -178,6 +179,8 @@ struct Tester {
             af[i] = len ? act[i] : 0;
             ou[i] = 0;
         }
+        // aggregate recurrence of the trigger test (Section 4.3), one bit per word of this lane
+        uint32_t agg_af = (1u << WPL) - 1u, agg_ou = 0;
         uint4 c = cur.c0;
         for (uint32_t k = 0;; k += 4) {
             {
@@ -213,6 +216,27 @@ struct Tester {
 #pragma unroll
                         for (int i = 0; i < WPL; ++i)
                             if (!((keep >> i) & 1u)) af[i] = 0;
+                        lane_live = keep != 0;
+                    }
+                } else {
+                    // trigger mode: the same recurrence over the group aggregates
+                    // (canBeFalse of the literal, canBeUndef of its variable) decides
+                    // which words can still trigger (Theorem 1: no false negatives)
+                    if (agg && lane_live) {
+#pragma unroll
+                        for (uint32_t u = 0; u < kGroup; ++u) {
+                            const uint32_t code = (k + g0 + u < len) ? cs[g0 + u] : 0u;
+                            const uint32_t cf = (uint32_t)(agg[code] >> w0), cu = (uint32_t)(aggu[code >> 1] >> w0);
+                            agg_ou = (agg_af & cu) | (agg_ou & cf);
+                            agg_af &= cf;
+                        }
+                        const uint32_t keep = (agg_af | agg_ou) & ((1u << WPL) - 1u);
+#pragma unroll
+                        for (int i = 0; i < WPL; ++i)
+                            if (!((keep >> i) & 1u)) {
+                                af[i] = 0;
+                                ou[i] = 0;
+                            }
                         lane_live = keep != 0;
                     }
                 }

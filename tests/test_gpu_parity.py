@@ -457,8 +457,8 @@ def _packed(vals_word):
 @pytest.mark.parametrize("max_slots", [64, 128, 256, 1024, 2048, 4096])
 def test_aggregate_pretest_equals_oracle(max_slots):
     """The aggregate pre-test (every row width: 2, 4 and 8-byte aggregate words)
-    changes no result, on grouped (Table 1) and on independent assignments, and
-    stays exact through every kind of plane update."""
+    changes no result in either mode, on grouped (Table 1) and on independent
+    assignments, and stays exact through every kind of plane update."""
     n_vars = 500
     rng = np.random.default_rng(max_slots)
     lits, offsets = gen.random_clauses(rng, gen.lengths_mix(rng, 6000), n_vars)
@@ -477,6 +477,9 @@ def test_aggregate_pretest_equals_oracle(max_slots):
             want = oracle.masks(lits, offsets, vals)
             _check(gpu_dense(ctx, n, A), want)
             _check(gpu_dense(ctx, n, A | gss.GSS_TEST_NO_EARLY_EXIT), want)
+            want_t = oracle.masks(lits, offsets, vals, mode="trigger")
+            _check(gpu_dense(ctx, n, A | gss.GSS_TEST_TRIGGER), want_t)
+            _check(gpu_dense(ctx, n, A | gss.GSS_TEST_TRIGGER | gss.GSS_TEST_NO_EARLY_EXIT), want_t)
         # a var-major delta on part of the slots
         vs = rng.choice(np.arange(1, n_vars + 1), 60, replace=False).astype(np.uint32)
         first, count = 3, max_slots - 5
@@ -484,6 +487,7 @@ def test_aggregate_pretest_equals_oracle(max_slots):
         ctx.set_var_values(first, vs, delta)
         vals[first:first + count][:, vs - 1] = delta.T
         _check(gpu_dense(ctx, n, A), oracle.masks(lits, offsets, vals))
+        _check(gpu_dense(ctx, n, A | gss.GSS_TEST_TRIGGER), oracle.masks(lits, offsets, vals, mode="trigger"))
         # packed word deltas
         for w in range(max_slots // 64):
             vs = rng.choice(np.arange(1, n_vars + 1), 40, replace=False).astype(np.uint32)
@@ -492,12 +496,13 @@ def test_aggregate_pretest_equals_oracle(max_slots):
             ctx.update_words(w, vs, f, t)
             vals[64 * w:64 * w + 64][:, vs - 1] = new
         _check(gpu_dense(ctx, n, A), oracle.masks(lits, offsets, vals))
+        _check(gpu_dense(ctx, n, A | gss.GSS_TEST_TRIGGER), oracle.masks(lits, offsets, vals, mode="trigger"))
         # cleared slots are inactive and all-U
         ctx.clear_slots(1, max_slots // 2)
         vals[1:1 + max_slots // 2] = 0
         active = np.ones(max_slots, dtype=bool)
         active[1:1 + max_slots // 2] = False
         _check(gpu_dense(ctx, n, A), oracle.masks(lits, offsets, vals, active=active))
-        # ignored in trigger mode
+        # trigger mode: canBeUndef counts active slots only
         _check(gpu_dense(ctx, n, A | gss.GSS_TEST_TRIGGER),
                oracle.masks(lits, offsets, vals, mode="trigger", active=active))
