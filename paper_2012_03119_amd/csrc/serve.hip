@@ -533,6 +533,11 @@ extern "C" gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cf
     catch (const std::bad_alloc &) {          \
         return GSS_ERR_CAPACITY;              \
     }                                         \
+    catch (const std::exception &e) {         \
+        std::lock_guard<std::mutex> g_((sp)->emu); \
+        (sp)->error = e.what();               \
+        return GSS_ERR_DEVICE;                \
+    }                                         \
     return GSS_OK;
 
 extern "C" gss_status gss_server_send(gss_server *s, uint32_t producer, uint32_t n_vars, const uint32_t *vars,

@@ -209,7 +209,7 @@ static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
     const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_SORTED | GSS_TEST_DENSE |
                            GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT | GSS_TEST_SCHEDULED | GSS_TEST_AGGREGATE;
     GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "unknown gss_test flag");
-    GSS_REQUIRE(!(flags & GSS_TEST_SORTED), GSS_ERR_INVALID_ARG, "GSS_TEST_SORTED is not supported by this build");
+    GSS_REQUIRE(!(flags & GSS_TEST_SORTED), GSS_ERR_INVALID_ARG, "GSS_TEST_SORTED is not supported (sort the fetched records instead)");
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is already in flight (call gss_test_wait)");
     if (flags & GSS_TEST_DENSE) {
         const uint64_t rows = std::max<uint64_t>(c.id_loc.size(), 1);

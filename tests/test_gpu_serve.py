@@ -242,3 +242,52 @@ def test_inserts_wait_for_the_hbm_budget():
     want["word"] = 0
     assert len(got) == len(want) and (got == want).all()
     ctx.close()
+
+
+def test_server_argument_errors():
+    V = 500
+    lits, offs = _store(46, 1000, V)
+    ctx = gss.Context(V, 128)
+    ctx.add_clauses(lits, offs)
+    for bad_n in (0, 3):  # 1..W producers, W = 2
+        with pytest.raises(gss.GssError) as e:
+            gss.Server(ctx, bad_n)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+    ctx.set_active(np.full(2, 2**64 - 1, dtype=np.uint64))
+    ctx.test_async()
+    with pytest.raises(gss.GssError) as e:  # a test in flight
+        gss.Server(ctx, 1)
+    assert e.value.code == gss.GSS_ERR_STATE
+    ctx.test_wait()
+    srv = gss.Server(ctx, 2)
+    try:
+        one = np.ones(1, dtype=np.uint64)
+        for args, code in [((2, [1], one, 0 * one), gss.GSS_ERR_INVALID_ARG),      # no such producer
+                           ((0, [V + 1], one, 0 * one), gss.GSS_ERR_BAD_LITERAL),  # variable out of range
+                           ((0, [3], one, one), gss.GSS_ERR_INVALID_ARG)]:         # F and T in one slot
+            with pytest.raises(gss.GssError) as e:
+                srv.send(*args)
+            assert e.value.code == code
+        for (l, o), code in [(([1, -(V + 1)], [0, 2]), gss.GSS_ERR_BAD_LITERAL),
+                             (([1, 2], [0, 0, 2]), gss.GSS_ERR_INVALID_ARG)]:     # an empty clause
+            with pytest.raises(gss.GssError) as e:
+                srv.insert(0, np.array(l, dtype=np.int32), np.array(o, dtype=np.uint64))
+            assert e.value.code == code
+        with pytest.raises(gss.GssError) as e:
+            srv.poll(5)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+        # a valid snapshot still goes through after the refused calls
+        vals, f, t = _snapshot(300, V)
+        srv.send(1, np.arange(1, V + 1, dtype=np.uint32), f, t)
+        got, run = _collect(srv, 1, None)
+    finally:
+        res = srv.stop()
+    assert res["snapshots"] == 1 and res["tested"] == 1 and res["inserted"] == 0
+    want = oracle.report_set(oracle.masks(lits, offs, vals), np.arange(len(offs) - 1))
+    want["word"] = 1
+    assert len(got) == len(want) and (got == want).all()
+    # the context is usable on its own again
+    ctx.set_active(np.array([0, 2**64 - 1], dtype=np.uint64))
+    n = ctx.test()
+    assert n == len(want)
+    ctx.close()
