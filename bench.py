@@ -64,8 +64,21 @@ def stage_rounds(w, n_rounds, seed, torch):
     return rounds
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, seconds):
-    """The oracle, untuned, on the host cores, over a bounded sample of clauses."""
+    """The oracle, untuned, over a bounded sample of clauses: on all the host
+    threads OpenMP uses (the reported value), then on one thread (about a fifth
+    of the time budget, on a smaller sample)."""
     import oracle
     vm = oracle.transpose(w.values)
 
@@ -76,15 +89,28 @@ def cpu_baseline(w, seconds):
         oracle.masks(lits, offs, values_vm=vm)
         return time.perf_counter() - t0
 
-    n = min(w.n_clauses, 2000)
-    t = run(n)
-    n2 = int(min(w.n_clauses, max(n, n * seconds / max(t, 1e-6))))
-    if n2 > n:
-        n, t = n2, run(n2)
+    def sample(budget):
+        n = min(w.n_clauses, 2000)
+        t = run(n)
+        n2 = int(min(w.n_clauses, max(n, n * budget / max(t, 1e-6))))
+        if n2 > n:
+            n, t = n2, run(n2)
+        return n, t
+
+    cores = oracle.max_threads()
+    n, t = sample(seconds)
+    try:
+        oracle.set_threads(1)
+        n1, t1 = sample(seconds / 5)
+    finally:
+        oracle.set_threads(cores)
     rate = n * w.n_slots / t
-    return {"value": rate, "unit": "tests/s", "cores": oracle.max_threads(), "kind": "oracle",
+    return {"value": rate, "unit": "tests/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n} of {w.n_clauses} clauses x {w.n_slots} assignments (round 0), "
-                      f"{t:.1f} s; var-major transpose of the values not timed"}
+                      f"{t:.1f} s; var-major transpose of the values not timed",
+            "single_core": {"value": n1 * w.n_slots / t1, "unit": "tests/s",
+                            "sample": f"first {n1} clauses, {t1:.1f} s on 1 thread"},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 #: the batched workload: (clauses, variables, assignment slots) of 8 independent
@@ -325,6 +351,7 @@ def bench_learned(args, torch, gss):
         ctx.priority_observe()
         advance()
     t1 = time.perf_counter()
+    ctx.priority_set_sampling(0)  # the network is trained once: no samples while it schedules
     loss = ctx.priority_train(args.learn_epochs, batch=4096, lr=3e-3, seed=args.seed + 502)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1

@@ -344,6 +344,9 @@ gss_status gss_priority_observe(gss_ctx *ctx);
 gss_status gss_priority_train(gss_ctx *ctx, uint32_t epochs, const gss_adam_config *cfg, uint64_t seed,
                               float *out_loss);
 gss_status gss_priority_clear_samples(gss_ctx *ctx);
+/* Changes the sample period (0 stops sampling, for instance once the network is
+ * trained; a nonzero period needs the sample capacity given at enable). */
+gss_status gss_priority_set_sampling(gss_ctx *ctx, uint32_t period);
 /* Scores every live clause; scores below threshold are low priority.
  * *out_n_low (may be NULL): how many. */
 gss_status gss_priority_score(gss_ctx *ctx, float threshold, uint64_t *out_n_low);

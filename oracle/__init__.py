@@ -70,6 +70,8 @@ def _load():
         lib.oracle_transpose.argtypes = [i64, i64, p, p]
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         for name in ("oracle_falsified", "oracle_trigger"):
             fn = getattr(lib, name)
             fn.argtypes = [i64, p, p, i64, i64, p, p, p]
@@ -81,6 +83,11 @@ def _load():
 def max_threads() -> int:
     """Threads the C oracle runs on (OpenMP)."""
     return int(_load().oracle_max_threads())
+
+
+def set_threads(n: int) -> int:
+    """Runs the C oracle's loops on n threads from now on; returns the count in use."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def _ptr(a: np.ndarray):

@@ -176,3 +176,17 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the number of threads of the loops above (for timing on fewer cores);
+ * returns the number now in use. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

@@ -167,60 +167,75 @@ __global__ void k_prio_hits(ProbeArgs a, const gss_report *reports, const uint32
 }
 
 // After a run: samples, history shift, hit counter reset.  Each lane takes
-// kPerThread ids (strided by the workgroup size); the workgroup claims its sample
-// rows with one atomic.
+// kObserve ids (strided by the workgroup size) and issues all their loads before
+// it uses any, so that a lane waits for memory once per phase rather than once
+// per id; the workgroup claims its sample rows with one atomic.
+constexpr uint32_t kObserve = 8;
+
 __global__ __launch_bounds__(256) void k_prio_observe(ProbeArgs a, uint64_t n_ids, uint32_t run, uint32_t scheduled,
                                                       float src_scale, uint32_t period, uint64_t seed, float *sx,
                                                       float *sy, uint64_t sample_cap, uint32_t *counters, float bump) {
     __shared__ uint32_t base_s;
-    const uint64_t first = (uint64_t)blockIdx.x * 256 * kPerThread + threadIdx.x;
-    auto is_tested = [&](uint64_t id, bool &live) {
-        live = id < n_ids && a.alive[id];
-        return live && !(scheduled && a.low[id] && ((run + (uint32_t)id) & 3u) != 0);
-    };
-    auto is_sample = [&](uint64_t id) { return period && mix64(seed ^ (id << 32) ^ run) % period == 0; };
-    uint32_t mine = 0;
-    if (period) {
-        for (uint32_t k = 0; k < kPerThread; ++k) {
-            const uint64_t id = first + (uint64_t)k * 256;
-            bool live;
-            mine += (is_tested(id, live) && is_sample(id)) ? 1u : 0u;
-        }
-    }
-    uint32_t total = 0;
-    uint32_t pos = block_inclusive_sum(mine, total) - mine;
-    if (threadIdx.x == 0) base_s = total ? atomicAdd(&counters[0], total) : 0u;
-    __syncthreads();
-    pos += base_s;
-    for (uint32_t k = 0; k < kPerThread; ++k) {
-        const uint64_t id = first + (uint64_t)k * 256;
-        bool live;
-        const bool tested = is_tested(id, live);
-        if (!live) continue;
-        const uint32_t h = a.hits[id];
-        if (tested && is_sample(id)) {
-            if (pos < sample_cap) {
-                float x[kFeat];
-                load_features(a, id, run, src_scale, x);
+    const uint64_t first = (uint64_t)blockIdx.x * 256 * kObserve + threadIdx.x;
+    uint32_t h[kObserve];
+    uint32_t live = 0, low = 0, tested = 0, sample = 0;  // bit k: id first + 256 k
 #pragma unroll
-                for (int q = 0; q < kFeat; ++q) sx[(uint64_t)pos * kFeat + q] = x[q];
-                sy[pos] = h ? 1.f : 0.f;
-            }
-            ++pos;
+    for (uint32_t k = 0; k < kObserve; ++k) {
+        const uint64_t id = first + (uint64_t)k * 256;
+        const bool in = id < n_ids;
+        const uint32_t al = in ? a.alive[id] : 0u, lo = in ? a.low[id] : 0u;
+        h[k] = in ? a.hits[id] : 0u;
+        live |= (al ? 1u : 0u) << k;
+        low |= (lo ? 1u : 0u) << k;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kObserve; ++k) {
+        const uint64_t id = first + (uint64_t)k * 256;
+        const bool skipped = scheduled && ((low >> k) & 1u) && ((run + (uint32_t)id) & 3u) != 0;
+        const bool t = ((live >> k) & 1u) && !skipped;
+        tested |= (t ? 1u : 0u) << k;
+        if (period) sample |= (t && mix64(seed ^ (id << 32) ^ run) % period == 0 ? 1u : 0u) << k;
+    }
+    uint32_t pos = 0;
+    if (period) {  // uniform: sample rows are claimed only while samples are taken
+        const uint32_t mine = __popc(sample);
+        uint32_t total = 0;
+        pos = block_inclusive_sum(mine, total) - mine;
+        if (threadIdx.x == 0) base_s = total ? atomicAdd(&counters[0], total) : 0u;
+        __syncthreads();
+        pos += base_s;
+    }
+    // samples take the features as they were before this run, labelled by its hits
+    for (uint32_t k = 0; k < kObserve && sample; ++k) {
+        if (!((sample >> k) & 1u)) continue;
+        const uint64_t id = first + (uint64_t)k * 256;
+        if (pos < sample_cap) {
+            float x[kFeat];
+            load_features(a, id, run, src_scale, x);
+#pragma unroll
+            for (int q = 0; q < kFeat; ++q) sx[(uint64_t)pos * kFeat + q] = x[q];
+            sy[pos] = h[k] ? 1.f : 0.f;
         }
-        if (tested) {  // shift in this run's count (a history of zeros stays as it is)
-            const uint4 v = a.hist[id];
-            if (h || (v.x | v.y | v.z | v.w)) {
-                const uint32_t hc = min(h, 0xFFFFu);  // at most 64 x 64 slots: never clipped
-                a.hist[id] = make_uint4((v.x << 16) | hc, (v.y << 16) | (v.x >> 16), (v.z << 16) | (v.y >> 16),
-                                        (v.w << 16) | (v.z >> 16));
-                // rescored by the next update only where its side of the threshold
-                // may change: a low clause that hit, a high one that did not (the
-                // next full scoring catches everything else)
-                if (a.low[id] ? h != 0 : h == 0) a.dirty[id] = 1;
-            }
+        ++pos;
+    }
+    uint4 v[kObserve];
+#pragma unroll
+    for (uint32_t k = 0; k < kObserve; ++k)
+        v[k] = ((tested >> k) & 1u) ? a.hist[first + (uint64_t)k * 256] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (uint32_t k = 0; k < kObserve; ++k) {
+        const uint64_t id = first + (uint64_t)k * 256;
+        // a tested clause shifts in this run's count (a history of zeros stays as it is)
+        if (((tested >> k) & 1u) && (h[k] || (v[k].x | v[k].y | v[k].z | v[k].w))) {
+            const uint32_t hc = min(h[k], 0xFFFFu);  // at most 64 x 64 slots: never clipped
+            a.hist[id] = make_uint4((v[k].x << 16) | hc, (v[k].y << 16) | (v[k].x >> 16),
+                                    (v[k].z << 16) | (v[k].y >> 16), (v[k].w << 16) | (v[k].z >> 16));
+            // rescored by the next update only where its side of the threshold may
+            // change: a low clause that hit, a high one that did not (the next full
+            // scoring catches everything else)
+            if (((low >> k) & 1u) ? h[k] != 0 : h[k] == 0) a.dirty[id] = 1;
         }
-        if (h) {
+        if (((live >> k) & 1u) && h[k]) {
             a.act[id] += bump;  // Section 3.7: bumped whenever the clause triggers
             a.hits[id] = 0;
         }
@@ -558,7 +573,7 @@ extern "C" gss_status gss_priority_observe(gss_ctx *ctx) {
                            args_of(p), c.reports, c.seg_counts, c.seg_cap, c.last_waves);
     GSS_HIP(hipGetLastError());
     if (p.n_ids)
-        hipLaunchKernelGGL(k_prio_observe, dim3(grid_of(p.n_ids, 256 * kPerThread)), dim3(256), 0, c.stream, args_of(p),
+        hipLaunchKernelGGL(k_prio_observe, dim3(grid_of(p.n_ids, 256 * kObserve)), dim3(256), 0, c.stream, args_of(p),
                            p.n_ids, p.run,
                            (c.last_flags & GSS_TEST_SCHEDULED) ? 1u : 0u, src_scale(p), p.cfg.sample_period,
                            p.cfg.seed, p.sx, p.sy, p.cfg.sample_capacity, p.counters, (float)p.bump);
@@ -613,6 +628,15 @@ extern "C" gss_status gss_priority_train(gss_ctx *ctx, uint32_t epochs, const gs
     GSS_HIP(hipMemcpyAsync(w.h_loss, w.loss, 4, hipMemcpyDeviceToHost, c.stream));
     c.sync();
     if (out_loss) *out_loss = *w.h_loss;
+    GSS_API_END
+}
+
+extern "C" gss_status gss_priority_set_sampling(gss_ctx *ctx, uint32_t period) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    Priority &p = need_prio(c);
+    GSS_REQUIRE(period == 0 || p.cfg.sample_capacity >= 1, GSS_ERR_INVALID_ARG, "sampling needs a sample capacity");
+    p.cfg.sample_period = period;
     GSS_API_END
 }
 

@@ -187,6 +187,7 @@ def load_library(path: Optional[str] = None):
         "gss_priority_params": ([P, P, P], ctypes.c_int32),
         "gss_priority_mark": ([P, P, u64], ctypes.c_int32),
         "gss_priority_update": ([P, P], ctypes.c_int32),
+        "gss_priority_set_sampling": ([P, u32], ctypes.c_int32),
         "gss_priority_reduce": ([P, u64, P], ctypes.c_int32),
         "gss_priority_activity": ([P, P, u32, P], ctypes.c_int32),
         "gss_priority_fetch": ([P, P, u32, P, P, P], ctypes.c_int32),
@@ -656,6 +657,9 @@ class Context:
         _check(self.ctx, load_library().gss_priority_train(self.ctx, epochs, ctypes.byref(cfg), seed,
                                                            ctypes.byref(loss)))
         return loss.value
+
+    def priority_set_sampling(self, period: int) -> None:
+        _check(self.ctx, load_library().gss_priority_set_sampling(self.ctx, period))
 
     def priority_clear_samples(self) -> None:
         _check(self.ctx, load_library().gss_priority_clear_samples(self.ctx))

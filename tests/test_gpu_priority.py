@@ -101,6 +101,12 @@ def test_features_and_samples_follow_the_runs():
         x, _, _ = ctx.priority_fetch(ids)
         sx, sy = ctx.priority_samples(100_000)
         assert ctx.priority_info()["run"] == runs
+        # with sampling switched off a further run leaves the samples as they are
+        ctx.priority_set_sampling(0)
+        ctx.test()
+        ctx.priority_observe()
+        assert ctx.priority_info()["samples"] == len(sx)
+        assert ctx.priority_info()["run"] == runs + 1
     want = P.features(lens, lbd.astype(np.float64), np.full(n, runs), src, 4, hist)
     np.testing.assert_allclose(x, want, rtol=2e-6, atol=1e-6)
     # every sample is the features of some clause before some run, labelled with

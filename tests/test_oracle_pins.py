@@ -343,3 +343,17 @@ def test_special_case_unit_and_binary():
     a_bits = lambda v, s: sum(1 << a for a in range(64) if vals[a, v - 1] == -s)
     m = oracle.masks(np.array([3, -40], np.int32), np.array([0, 2], np.int64), vals)[0, 0]
     assert int(m) == a_bits(3, 1) & a_bits(40, -1)
+
+
+def test_thread_count_does_not_change_results():
+    # the timing leg runs the oracle on one thread as well: same masks in both modes
+    w = gen.tiny(6, n_clauses=4000)
+    cores = oracle.max_threads()
+    want = {m: oracle.masks(w.lits, w.offsets, w.values, mode=m) for m in ("falsified", "trigger")}
+    try:
+        assert oracle.set_threads(1) == 1
+        for m, x in want.items():
+            np.testing.assert_array_equal(oracle.masks(w.lits, w.offsets, w.values, mode=m), x)
+    finally:
+        oracle.set_threads(cores)
+    assert oracle.max_threads() == cores
