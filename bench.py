@@ -532,7 +532,12 @@ def main():
         flags |= gss.GSS_TEST_TRIGGER
     if args.aggregate:
         flags |= gss.GSS_TEST_AGGREGATE
-    ctx = gss.Context(w.n_vars, w.n_slots, hot_vars=args.hot_vars, report_capacity=args.report_capacity)
+    # the context works on torch's current stream: inputs made there need no extra wait
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = gss.Context(w.n_vars, w.n_slots, hot_vars=args.hot_vars, report_capacity=args.report_capacity,
+                      stream=stream)
     t0 = time.perf_counter()
     ctx.add_clauses(w.lits, w.offsets)
     log(f"clauses stored in {time.perf_counter() - t0:.1f} s")
@@ -540,20 +545,34 @@ def main():
     ctx.set_assignments(0, w.values)
     log(f"assignments packed in {time.perf_counter() - t0:.1f} s")
 
-    def step(i):
+    # A step applies one round's delta and tests the store.  Steps are pipelined:
+    # round i+1's delta is queued on the device behind test i, so the device
+    # applies it while the host collects test i's count and queues test i+1.
+    def queue_delta(i):
         if rounds:
             vs, delta = rounds[i % len(rounds)]
-            ctx.set_var_values(0, vs, delta)
-        return ctx.test(flags)
+            ctx.set_var_values_async(0, vs, delta)
 
-    for i in range(args.warmup):
-        n_rep = step(i)
+    def run_steps(first, n):
+        if n <= 0:
+            return 0
+        queue_delta(first)
+        ctx.test_async(flags)
+        for i in range(first + 1, first + n):
+            queue_delta(i)
+            ctx.test_wait()
+            ctx.test_async(flags)
+        return ctx.test_wait()
+
+    # one synchronous test first sizes the report segments (a pipelined test that
+    # overflows is not repeated, since the next delta is already queued)
+    n_rep = ctx.test(flags)
+    n_rep = run_steps(0, args.warmup) or n_rep
     log(f"warmup done ({args.warmup} steps), {n_rep} reports per test")
     torch.cuda.synchronize()
     ctx.reset_stats()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        n_rep = step(args.warmup + i)
+    n_rep = run_steps(args.warmup, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = ctx.stats()

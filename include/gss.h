@@ -131,6 +131,19 @@ gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slo
 gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, uint32_t n_vars,
                               const uint32_t *vars, const int8_t *values);
 
+/* The same delta with nothing waited for, so that a loop of deltas and tests
+ * keeps the device busy.  values must be device memory, read by kernels queued on
+ * the context's stream; it must stay unchanged until the first test begun after
+ * this call has completed (the return of that gss_test, or of the gss_test_wait
+ * of that gss_test_async).  vars, a host array, is copied before return.  The
+ * slot range and the variable range are checked at once (nothing is queued on
+ * error); the values and repeated variables are checked on the device.  An update
+ * that fails that check applies nothing, nor do the asynchronous updates queued
+ * after it, and the completion of that first test reports INVALID_ARG (the test
+ * ran on the state without those updates; its records can be fetched). */
+gss_status gss_set_var_values_async(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, uint32_t n_vars,
+                                    const uint32_t *vars, const int8_t *values);
+
 /* Packed delta for one 64-slot word (a solver thread that keeps its group of 64
  * assignments as bit words sends only the changed variables): for each listed
  * variable vars[i] (distinct, 1..num_vars), bit b of f_words[i] says slot

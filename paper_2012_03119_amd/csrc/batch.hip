@@ -327,6 +327,7 @@ bool run_once(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
     uint64_t act = 0;
     for (uint32_t s = 0; s < n; ++s) {
         Ctx &c = *b.ctxs[s];
+        c.mark_idle();  // the shared stream was synchronised above
         const unsigned long long *sum = b.h_summary + 4 * s;
         c.last_waves = b.grid * kTestWavesPerBlock;
         c.n_reports = sum[0];

@@ -21,7 +21,7 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t value) {
         p[i] = value;
 }
 
-static unsigned fill_grid(uint64_t n) {
+unsigned fill_grid(uint64_t n) {
     uint64_t g = (n + 255) / 256;
     return (unsigned)(g < 8192 ? (g ? g : 1) : 8192);
 }
@@ -38,26 +38,10 @@ void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value) {
     GSS_HIP(hipGetLastError());
 }
 
-// Sets *bad when any byte is outside {-1, 0, +1}.  Sixteen bytes per load; a byte
-// x is valid iff (x + 1) as an unsigned byte is at most 2.
+// Sets *bad when any byte is outside {-1, 0, +1}.
 __global__ void k_check_values(const int8_t *v, uint64_t n, unsigned int *bad) {
-    unsigned found = 0;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    const uint64_t head = (16 - ((uintptr_t)v & 15)) & 15;  // bytes before the first aligned block
-    for (uint64_t i = tid; i < head && i < n; i += stride) found |= (uint8_t)(v[i] + 1) > 2;
-    const uint64_t n16 = n > head ? (n - head) / 16 : 0;
-    const uint4 *q = reinterpret_cast<const uint4 *>(v + head);
-    for (uint64_t i = tid; i < n16; i += stride) {
-        const uint4 x = q[i];
-        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) found |= (((w[k] >> (8 * s)) + 1) & 0xFFu) > 2;
-    }
-    for (uint64_t i = head + n16 * 16 + tid; i < n; i += stride) found |= (uint8_t)(v[i] + 1) > 2;
-    if (found) atomicOr(bad, 1u);
+    if (values_invalid(v, n, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x))
+        atomicOr(bad, 1u);
 }
 
 // Queues the check of n device-resident truth values; the verdict lands in
@@ -66,11 +50,16 @@ __global__ void k_check_values(const int8_t *v, uint64_t n, unsigned int *bad) {
 // synchronisation (check_flag) gives validate-then-apply semantics.
 const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n) {
     launch_fill_u32(c, c.dsmall, 1, 0);
+    queue_value_check_into(c, values, n, c.dsmall);
+    return c.dsmall;
+}
+
+// The same check ORed into an existing verdict word (bit 0), not cleared first.
+void queue_value_check_into(Ctx &c, const int8_t *values, uint64_t n, uint32_t *verdict) {
     if (n) {
-        hipLaunchKernelGGL(k_check_values, dim3(fill_grid(n)), dim3(256), 0, c.stream, values, n, c.dsmall);
+        hipLaunchKernelGGL(k_check_values, dim3(fill_grid(n)), dim3(256), 0, c.stream, values, n, verdict);
         GSS_HIP(hipGetLastError());
     }
-    return c.dsmall;
 }
 
 void check_flag(Ctx &c) {
@@ -78,6 +67,28 @@ void check_flag(Ctx &c) {
     c.sync();
     GSS_REQUIRE(!(c.hsmall[0] & 1u), GSS_ERR_INVALID_ARG, "truth values must be -1, 0 or +1");
     GSS_REQUIRE(!(c.hsmall[0] & 2u), GSS_ERR_INVALID_ARG, "variable listed twice");
+}
+
+// Asynchronous updates check their device inputs into dsmall[2], a verdict that
+// stays set (and makes later asynchronous updates apply nothing) until a test
+// reports it.
+uint32_t *deferred_flag(Ctx &c) { return c.dsmall + 2; }
+
+uint32_t read_deferred(Ctx &c) {
+    GSS_HIP(hipMemcpyAsync(c.hsmall + 2, c.dsmall + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    return c.hsmall[2];
+}
+
+void report_deferred(Ctx &c, uint32_t verdict) {
+    if (!verdict) return;
+    launch_fill_u32(c, deferred_flag(c), 1, 0);
+    GSS_REQUIRE(!(verdict & 1u), GSS_ERR_INVALID_ARG,
+                "an asynchronous update held truth values other than -1, 0 or +1: it and the asynchronous updates "
+                "queued after it were not applied");
+    GSS_REQUIRE(false, GSS_ERR_INVALID_ARG,
+                "an asynchronous update listed a variable twice: it and the asynchronous updates queued after it "
+                "were not applied");
 }
 
 bool is_device_pointer(const void *p) {
@@ -164,17 +175,22 @@ void *Ctx::host_stage(size_t bytes) {
     return hstage;
 }
 
-void Ctx::sync() { GSS_HIP(hipStreamSynchronize(stream)); }
+void Ctx::sync() {
+    GSS_HIP(hipStreamSynchronize(stream));
+    mark_idle();
+}
+
+void Ctx::mark_idle() {
+    tests_completed = tests_launched;
+    for (RingSlot &s : ring) s.busy = false;
+}
 
 Ctx::Staged Ctx::stage_upload(size_t bytes) {
     const int k = ring_next;
     ring_next = (ring_next + 1) % kRing;
     RingSlot &s = ring[k];
-    if (s.busy) {
-        GSS_HIP(hipEventSynchronize(s.done));
-        s.busy = false;
-    }
-    if (!s.done) GSS_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    if (s.busy && tests_completed < s.free_after) sync();  // its readers may still be queued
+    s.busy = false;
     if (bytes > s.bytes) {
         const size_t want = std::max<size_t>({bytes, 2 * s.bytes, (size_t)1 << 16});
         char *d = (char *)dalloc(want);  // may raise CAPACITY; the slot is unchanged then
@@ -183,18 +199,25 @@ Ctx::Staged Ctx::stage_upload(size_t bytes) {
             dfree(d);
             throw Error(GSS_ERR_DEVICE, "hipHostMalloc failed for the upload ring");
         }
+        void *hd = nullptr;
+        if (hipHostGetDevicePointer(&hd, h, 0) != hipSuccess) {
+            (void)hipHostFree(h);
+            dfree(d);
+            throw Error(GSS_ERR_DEVICE, "hipHostGetDevicePointer failed for the upload ring");
+        }
         dfree(s.d);
         if (s.h) (void)hipHostFree(s.h);
         s.d = d;
         s.h = h;
+        s.hd = (char *)hd;
         s.bytes = want;
     }
-    return Staged{s.h, s.d, k};
+    return Staged{s.h, s.d, k, s.hd};
 }
 
 void Ctx::stage_done(const Staged &st) {
     RingSlot &s = ring[st.slot];
-    GSS_HIP(hipEventRecord(s.done, stream));
+    s.free_after = tests_launched + 1;  // the next test is queued behind its readers
     s.busy = true;
 }
 
@@ -233,7 +256,6 @@ static void destroy_ctx(Ctx *c) {
     for (auto &s : c->ring) {
         c->dfree(s.d);
         if (s.h) (void)hipHostFree(s.h);
-        if (s.done) (void)hipEventDestroy(s.done);
     }
     if (c->h_summary) (void)hipHostFree(c->h_summary);
     c->dfree(c->dsmall);
@@ -243,7 +265,6 @@ static void destroy_ctx(Ctx *c) {
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
-    if (c->ev_done) (void)hipEventDestroy(c->ev_done);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -314,7 +335,9 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         c->seg_counts = (uint32_t *)c->dalloc((uint64_t)c->max_waves * 4);
         c->seg_offsets = (uint64_t *)c->dalloc(((uint64_t)c->max_waves + 1) * 8);
         c->d_summary = (unsigned long long *)c->dalloc(4 * sizeof(unsigned long long));
-        GSS_HIP(hipHostMalloc(&c->h_summary, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+        GSS_HIP(hipHostMalloc(&c->h_summary, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+        std::memset(c->h_summary, 0, 8 * sizeof(unsigned long long));
+        GSS_HIP(hipHostGetDevicePointer((void **)&c->hd_summary, c->h_summary, 0));
         c->dsmall = (uint32_t *)c->dalloc(256);
         launch_fill_u32(*c, c->dsmall, 64, 0);  // dsmall[1] stays zero: the verdict of host-checked inputs
         c->d_desc = c->dalloc(kMaxBuckets * sizeof(BucketDesc));
@@ -323,7 +346,6 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         GSS_HIP(hipEventCreate(&c->ev_start));
         GSS_HIP(hipEventCreate(&c->ev_stop));
         GSS_HIP(hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming));
-        GSS_HIP(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
         // the upload ring starts at 256 KiB a slot, so that per-round deltas do not
         // allocate pinned memory while a caller is timing them
         for (int k = 0; k < Ctx::kRing; ++k) {

@@ -161,8 +161,12 @@ struct Ctx {
     uint32_t last_waves = 0;                 // wavefronts of the last launch
     uint32_t *seg_counts = nullptr;          // [max_waves]
     uint64_t *seg_offsets = nullptr;         // [max_waves + 1] exclusive prefix of the kept records
-    unsigned long long *d_summary = nullptr; // device {total, max, kept}
-    unsigned long long *h_summary = nullptr; // pinned host copy
+    unsigned long long *d_summary = nullptr;  // device {total, max, kept, deferred verdict}
+    unsigned long long *h_summary = nullptr;  // pinned host copy, written by the finalize kernel
+    unsigned long long *hd_summary = nullptr; // h_summary as kernels address it
+    const void *occ_fn = nullptr;             // the test kernel whose occupancy is cached
+    size_t occ_lds = 0;
+    int occ_fit = 0;
     uint32_t *dsmall = nullptr;              // 256 B device scratch for flags
     uint32_t *hsmall = nullptr;              // 256 B pinned host
     void *d_desc = nullptr;                  // device copy of the test kernel's bucket descriptors
@@ -185,7 +189,8 @@ struct Ctx {
 
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     hipEvent_t ev_stage = nullptr;  // recorded after the last queued use of the staging buffers
-    hipEvent_t ev_done = nullptr;   // recorded after a test's summary copy
+    uint64_t tests_launched = 0;    // serial of the last queued test (its finalize kernel writes it to h_summary[4])
+    uint64_t tests_completed = 0;   // serial of the last test seen complete (or of all, after a sync)
     bool pending = false;           // gss_test_async issued, gss_test_wait not yet called
     bool pending_launched = false;
     uint32_t pending_flags = 0;
@@ -207,28 +212,53 @@ struct Ctx {
     void *host_stage(size_t bytes);
     void stage_release();
     void sync();
+    void mark_idle();  // bookkeeping of sync() after the stream was synchronised elsewhere
 
     // Upload ring: small uploads (deltas, inserts, removals, activity) take a slot
-    // of pinned host + device memory; the slot is released by an event recorded
-    // behind the kernels that read it, so a caller can queue uploads behind a test
-    // still running without waiting for it.
+    // of pinned host + device memory; the kernels that read it are queued before
+    // the next test, so the slot is free once that test has completed (or after a
+    // synchronisation).  A caller can queue uploads behind a test still running
+    // without waiting for it, and no event is recorded between the kernels.
     struct Staged {
         char *h;
         char *d;
         int slot;
+        const char *hd;  // h as kernels address it (pinned host memory read over the bus)
     };
     static constexpr int kRing = 8;
     struct RingSlot {
         char *h = nullptr;
+        char *hd = nullptr;
         char *d = nullptr;
         size_t bytes = 0;
-        hipEvent_t done = nullptr;
+        uint64_t free_after = 0;  // free once this test serial has completed
         bool busy = false;
     } ring[kRing];
     int ring_next = 0;
     Staged stage_upload(size_t bytes);           // a free slot of at least `bytes`
     void stage_done(const Staged &s);            // its consumers are queued
 };
+
+// True when this thread's share (grid-stride: first item tid, step stride) of the
+// n truth values at v holds a byte outside {-1, 0, +1}.  Sixteen bytes per load;
+// a byte x is valid iff (x + 1) as an unsigned byte is at most 2.
+__device__ inline bool values_invalid(const int8_t *v, uint64_t n, uint64_t tid, uint64_t stride) {
+    unsigned found = 0;
+    const uint64_t head = (16 - ((uintptr_t)v & 15)) & 15;  // bytes before the first aligned block
+    for (uint64_t i = tid; i < head && i < n; i += stride) found |= (uint8_t)(v[i] + 1) > 2;
+    const uint64_t n16 = n > head ? (n - head) / 16 : 0;
+    const uint4 *q = reinterpret_cast<const uint4 *>(v + head);
+    for (uint64_t i = tid; i < n16; i += stride) {
+        const uint4 x = q[i];
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) found |= (((w[k] >> (8 * s)) + 1) & 0xFFu) > 2;
+    }
+    for (uint64_t i = head + n16 * 16 + tid; i < n; i += stride) found |= (uint8_t)(v[i] + 1) > 2;
+    return found != 0;
+}
 
 // Bytes of one row's aggregate bits: 2 up to 16 words per row, 4 up to 32, else 8.
 inline uint32_t agg_elem_bytes(uint32_t RW) { return RW <= 16 ? 2u : RW <= 32 ? 4u : 8u; }
@@ -241,8 +271,13 @@ void aggu_rebuild(Ctx &c);
 void launch_fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t value);
 void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value);
 bool is_device_pointer(const void *p);
+unsigned fill_grid(uint64_t n);  // workgroups of 256 for a grid-stride pass over n items
 const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n);
+void queue_value_check_into(Ctx &c, const int8_t *values, uint64_t n, uint32_t *verdict);
 void check_flag(Ctx &c);
+uint32_t *deferred_flag(Ctx &c);
+uint32_t read_deferred(Ctx &c);
+void report_deferred(Ctx &c, uint32_t verdict);
 // Clause ingest in two parts.  prepare_clauses validates DIMACS clauses and
 // encodes them (codes 2v+neg, the lead -- smallest code -- first, the length
 // class and lead of each clause); it touches no context and may run on any

@@ -121,18 +121,25 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RW,
     }
 }
 
-// Delta update: thread per (variable, 64-slot word), grid (variables, words).
-// The thread reads the word's 64 values of its variable (four 16-byte loads when
-// the word is whole and aligned) and builds the F and T words; a word only partly
-// inside [first, first + n_slots) keeps its other slots.  vals is var-major
-// [n_vars][n_slots].
+// Delta update: thread per (variable, 64-slot word), the words of one variable
+// on neighbouring lanes, so that a variable's plane rows are written as whole
+// lines and its values read as one contiguous run.  The thread reads the word's
+// 64 values of its variable (four 16-byte loads when the word is whole and
+// aligned) and builds the F and T words; a word only partly inside
+// [first, first + n_slots) keeps its other slots.  vals is var-major
+// [n_vars][n_slots]; nw = words touched.
+// With clear_bits != null, the thread of each variable's first word also clears
+// the variable's word of the duplicate bitmap (left zero for the next check).
 __global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RW, const uint32_t *vars, uint32_t n_vars,
-                                                  const int8_t *vals, uint32_t first, uint32_t n_slots,
-                                                  const uint32_t *bad) {
+                                                  const int8_t *vals, uint32_t first, uint32_t n_slots, uint32_t nw,
+                                                  const uint32_t *bad, uint32_t *clear_bits) {
+    const uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (x >= (uint64_t)n_vars * nw) return;
+    const uint32_t i = (uint32_t)(x / nw);
+    const uint32_t wi = (uint32_t)(x - (uint64_t)i * nw);
+    if (clear_bits && wi == 0) clear_bits[vars[i] >> 5] = 0;
     if (*bad) return;  // the inputs failed validation: apply nothing
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_vars) return;
-    const uint32_t w = first / 64 + blockIdx.y;
+    const uint32_t w = first / 64 + wi;
     const uint32_t lo = max(first, 64 * w), hi = min(first + n_slots, 64 * w + 64);
     const int8_t *src = vals + (uint64_t)i * n_slots + (lo - first);
     uint64_t f = 0, t = 0;
@@ -248,7 +255,7 @@ static void check_var_range(const Ctx &c, const uint32_t *vars, uint32_t n_vars)
 }
 
 // Device half of the variable check: a variable listed twice sets bit 2 of
-// *bad (one bitmap bit per variable, cleared again by k_clear_vars).
+// *bad (one bitmap bit per variable, cleared again by k_set_vars).
 __global__ void k_check_vars(const uint32_t *vars, uint32_t n, uint32_t *bits, uint32_t *bad) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -256,9 +263,44 @@ __global__ void k_check_vars(const uint32_t *vars, uint32_t n, uint32_t *bits, u
     if (atomicOr(&bits[v >> 5], m) & m) atomicOr(bad, 2u);
 }
 
-__global__ void k_clear_vars(const uint32_t *vars, uint32_t n, uint32_t *bits) {
+// Both checks of a queued delta in one launch: the first var_blocks workgroups
+// (dispatched first: their reads cross the bus) take the variable list, which
+// they read from pinned host memory and copy into the device array the later
+// kernels read (no separate copy to wait for), marking repeats (bit 2 of *bad);
+// the others check the truth values (bit 1).
+__global__ __launch_bounds__(256) void k_check_delta(const int8_t *vals, uint64_t n_vals, uint32_t var_blocks,
+                                                     const uint32_t *host_vars, uint32_t *vars, uint32_t n,
+                                                     uint32_t *bits, uint32_t *bad) {
+    if (blockIdx.x >= var_blocks) {
+        const uint32_t b = blockIdx.x - var_blocks, value_blocks = gridDim.x - var_blocks;
+        if (values_invalid(vals, n_vals, b * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)value_blocks * blockDim.x))
+            atomicOr(bad, 1u);
+        return;
+    }
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) bits[vars[i] >> 5] = 0;
+    if (i >= n) return;
+    const uint32_t v = host_vars[i], m = 1u << (v & 31);
+    vars[i] = v;
+    if (atomicOr(&bits[v >> 5], m) & m) atomicOr(bad, 2u);
+}
+
+
+static void launch_set_vars(Ctx &c, const uint32_t *d_vars, uint32_t n_vars, const int8_t *d_vals, uint32_t first_slot,
+                            uint32_t n_slots, const uint32_t *bad, uint32_t *clear_bits) {
+    const uint32_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
+    const uint64_t threads = (uint64_t)n_vars * nw;
+    hipLaunchKernelGGL(k_set_vars, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, c.stream, c.planes, c.RW,
+                       d_vars, n_vars, d_vals, first_slot, n_slots, nw, bad, clear_bits);
+    GSS_HIP(hipGetLastError());
+}
+
+// Checks shared by both forms of gss_set_var_values: the slot range and its activity.
+static void check_delta_slots(const Ctx &c, uint32_t first_slot, uint32_t n_slots) {
+    GSS_REQUIRE((uint64_t)first_slot + n_slots <= c.cfg.max_slots, GSS_ERR_CAPACITY, "slot range beyond max_slots");
+    for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w) {
+        const uint64_t sm = slot_mask(first_slot, n_slots, w);
+        GSS_REQUIRE((c.h_active[w] & sm) == sm, GSS_ERR_INVALID_ARG, "slot range includes inactive slots");
+    }
 }
 
 static void check_values_host(const int8_t *v, uint64_t n) {
@@ -314,11 +356,7 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
     Ctx &c = *c_;
     if (n_slots == 0 || n_vars == 0) return GSS_OK;
     GSS_REQUIRE(vars && values, GSS_ERR_INVALID_ARG, "null argument");
-    GSS_REQUIRE((uint64_t)first_slot + n_slots <= c.cfg.max_slots, GSS_ERR_CAPACITY, "slot range beyond max_slots");
-    for (uint32_t w = first_slot / 64; w <= (first_slot + n_slots - 1) / 64; ++w) {
-        const uint64_t sm = slot_mask(first_slot, n_slots, w);
-        GSS_REQUIRE((c.h_active[w] & sm) == sm, GSS_ERR_INVALID_ARG, "slot range includes inactive slots");
-    }
+    check_delta_slots(c, first_slot, n_slots);
     const uint64_t nv = (uint64_t)n_vars * n_slots;
     const bool dev = is_device_pointer(values);
     const uint32_t *bad = c.dsmall + 1;  // always zero
@@ -349,19 +387,44 @@ extern "C" gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint
                            c.var_bits, c.dsmall);
         GSS_HIP(hipGetLastError());
     }
-    const uint32_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
-    hipLaunchKernelGGL(k_set_vars, dim3((n_vars + 255) / 256, nw), dim3(256), 0, c.stream, c.planes, c.RW,
-                       (const uint32_t *)d, n_vars, dvals, first_slot, n_slots, bad);
-    GSS_HIP(hipGetLastError());
+    launch_set_vars(c, (const uint32_t *)d, n_vars, dvals, first_slot, n_slots, bad, dev ? c.var_bits : nullptr);
     c.agg_valid = false;
     c.aggu_valid = false;
-    if (dev) {
-        hipLaunchKernelGGL(k_clear_vars, dim3((n_vars + 255) / 256), dim3(256), 0, c.stream, (const uint32_t *)d, n_vars,
-                           c.var_bits);
-        GSS_HIP(hipGetLastError());
-    }
     c.stage_done(st);
     if (dev) check_flag(c);  // one synchronisation: device inputs are fully read when the call returns
+    GSS_API_END
+}
+
+extern "C" gss_status gss_set_var_values_async(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots, uint32_t n_vars,
+                                               const uint32_t *vars, const int8_t *values) {
+    GSS_API_BEGIN(ctx)
+    c_->mutations++;  // a test in flight no longer sees the current state
+    Ctx &c = *c_;
+    if (n_slots == 0 || n_vars == 0) return GSS_OK;
+    GSS_REQUIRE(vars && values, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE(is_device_pointer(values), GSS_ERR_INVALID_ARG, "values must be device memory");
+    check_delta_slots(c, first_slot, n_slots);
+    check_var_range(c, vars, n_vars);
+    if (!c.var_bits) {
+        c.var_bits = (uint32_t *)c.dalloc(((uint64_t)c.cfg.num_vars / 32 + 1) * 4);
+        launch_fill_u32(c, c.var_bits, (uint64_t)c.cfg.num_vars / 32 + 1, 0);
+    }
+    // the list goes into a pinned ring slot, read by the checking kernel itself
+    // (a copy queued behind a running test would start only when the test ends)
+    const size_t bytes = (size_t)n_vars * 4;
+    const Ctx::Staged st = c.stage_upload(bytes);
+    std::memcpy(st.h, vars, bytes);
+    uint32_t *dv = (uint32_t *)st.d;
+    uint32_t *bad = deferred_flag(c);  // sticky: set by this check or an earlier one not yet reported
+    const uint64_t nv = (uint64_t)n_vars * n_slots;
+    const uint32_t var_blocks = (n_vars + 255) / 256;
+    hipLaunchKernelGGL(k_check_delta, dim3(var_blocks + fill_grid((nv + 15) / 16)), dim3(256), 0, c.stream, values, nv,
+                       var_blocks, (const uint32_t *)st.hd, dv, n_vars, c.var_bits, bad);
+    GSS_HIP(hipGetLastError());
+    launch_set_vars(c, dv, n_vars, values, first_slot, n_slots, bad, c.var_bits);
+    c.agg_valid = false;
+    c.aggu_valid = false;
+    c.stage_done(st);
     GSS_API_END
 }
 

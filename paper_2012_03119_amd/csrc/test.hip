@@ -5,7 +5,10 @@
 // Tester of tester.h (Sections 3.4-3.5).
 #include "tester.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 
 namespace gss {
@@ -51,9 +54,23 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
     if (lane == 0) a.seg_counts[wave] = produced;
 }
 
+// summary[3] receives the verdict of the asynchronous updates queued before the
+// test.  The summary is also written straight into pinned host memory, followed by
+// the test's serial number: the host sees the test complete when the serial
+// arrives, with no copy or event queued behind the kernel.
 __global__ __launch_bounds__(1024) void k_finalize(const uint32_t *counts, uint32_t n, uint32_t cap,
-                                                    uint64_t *offsets, unsigned long long *summary) {
+                                                    uint64_t *offsets, unsigned long long *summary,
+                                                    const uint32_t *deferred, unsigned long long *host_summary,
+                                                    unsigned long long serial) {
     finalize_segments(counts, n, cap, offsets, summary);
+    if (threadIdx.x == 0) {  // the thread that wrote summary[0..2]
+        summary[3] = *deferred;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) host_summary[k] = summary[k];
+        __threadfence_system();  // the summary reaches the host before the serial
+        host_summary[4] = serial;
+        __threadfence_system();
+    }
 }
 
 // Copies the kept records of every segment into one list (segment order), the
@@ -168,8 +185,12 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     L.fn = pick_kernel(c.RW, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot);
     if (hot) L.lds = (size_t)a.hot_rows * c.RW * 8;
     // persistent: exactly as many workgroups as fit on the device at once
-    int fit = 0;
-    GSS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, L.fn, kTestWavesPerBlock * 64, L.lds));
+    if (c.occ_fn != (const void *)L.fn || c.occ_lds != L.lds) {  // the query costs host time: cache it
+        GSS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&c.occ_fit, L.fn, kTestWavesPerBlock * 64, L.lds));
+        c.occ_fn = (const void *)L.fn;
+        c.occ_lds = L.lds;
+    }
+    const int fit = c.occ_fit;
     const uint64_t per_cu = std::max<int>(1, std::min<int>(fit, (int)kTestBlocksPerCU));
     const uint64_t one_tile_each = (tiles + kTestWavesPerBlock - 1) / kTestWavesPerBlock;
     L.grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(one_tile_each, per_cu * c.n_cu));
@@ -178,24 +199,54 @@ static Launch prepare(Ctx &c, uint32_t flags) {
 
 // Queues the test kernel, the finalize kernel and the copy of the summary.
 static void launch(Ctx &c, const Launch &L, uint32_t flags) {
-    GSS_HIP(hipEventRecord(c.ev_start, c.stream));
-    hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(kTestWavesPerBlock * 64), L.lds, c.stream, L.descs, L.args,
-                       (flags & GSS_TEST_NO_EARLY_EXIT) ? 0u : 1u, (flags & GSS_TEST_DENSE) ? 1u : 0u);
-    GSS_HIP(hipGetLastError());
-    GSS_HIP(hipEventRecord(c.ev_stop, c.stream));
+    // the timing events travel with the dispatch itself (no marker packets between
+    // the kernels, which would leave the device idle around the test)
+    const BucketDesc *descs = L.descs;
+    TestArgs targs = L.args;
+    uint32_t early_exit = (flags & GSS_TEST_NO_EARLY_EXIT) ? 0u : 1u, dense = (flags & GSS_TEST_DENSE) ? 1u : 0u;
+    void *kargs[] = {&descs, &targs, &early_exit, &dense};
+    GSS_HIP(hipExtLaunchKernel(reinterpret_cast<const void *>(L.fn), dim3(L.grid), dim3(kTestWavesPerBlock * 64), kargs,
+                               L.lds, c.stream, c.ev_start, c.ev_stop, 0));
     const uint32_t n_waves = L.grid * kTestWavesPerBlock;
+    const uint64_t serial = c.tests_launched + 1;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, c.stream, c.seg_counts, n_waves, c.seg_cap, c.seg_offsets,
-                       c.d_summary);
+                       c.d_summary, deferred_flag(c), c.hd_summary, (unsigned long long)serial);
     GSS_HIP(hipGetLastError());
-    GSS_HIP(hipMemcpyAsync(c.h_summary, c.d_summary, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream));
-    GSS_HIP(hipEventRecord(c.ev_done, c.stream));
+    c.tests_launched = serial;
     c.last_waves = n_waves;
     c.launch_mutations = c.mutations;
 }
 
-// Waits for a launched test and records its kernel time.
+// True once the last launched test's finalize kernel has written its serial to
+// the host; a device error on the stream is raised.
+static bool summary_arrived(Ctx &c, bool check_stream) {
+    const volatile unsigned long long *hs = c.h_summary;
+    if (hs[4] == c.tests_launched) {
+        std::atomic_thread_fence(std::memory_order_acquire);  // the summary words were written before it
+        return true;
+    }
+    if (check_stream) {
+        const hipError_t e = hipStreamQuery(c.stream);
+        if (e != hipErrorNotReady) {
+            GSS_HIP(e);
+            // the stream is idle: the serial must be there now
+            GSS_REQUIRE(hs[4] == c.tests_launched, GSS_ERR_DEVICE, "the test summary did not arrive");
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Waits for a launched test and records its kernel time.  The wait polls the
+// serial in pinned memory rather than blocking in the runtime: the caller is
+// about to queue the next test, and a blocked thread wakes too late to keep the
+// device busy.  The stream is queried now and then for device errors.
 static void complete(Ctx &c) {
-    GSS_HIP(hipEventSynchronize(c.ev_done));
+    for (uint32_t spins = 1; !summary_arrived(c, (spins & 1023) == 0); ++spins) {
+    }
+    c.tests_completed = c.tests_launched;
+    GSS_HIP(hipEventSynchronize(c.ev_stop));  // recorded before the finalize kernel: already complete
     float ms = 0.f;
     GSS_HIP(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
     c.stats.last_kernel_ms = ms;
@@ -281,6 +332,9 @@ static uint64_t end_test(Ctx &c, uint32_t flags, bool launched) {
     c.n_reports = n;
     c.n_kept = kept;
     c.stats.last_reports = n;
+    // a failed asynchronous update is reported here; the test itself ran on the
+    // state without it, and its records stay available
+    report_deferred(c, launched ? (uint32_t)c.h_summary[3] : read_deferred(c));
     GSS_REQUIRE(kept == n, GSS_ERR_REPORT_OVERFLOW,
                 "report segments of " + std::to_string(c.seg_cap) + " records kept " + std::to_string(kept) + " of " +
                     std::to_string(n) + " records");
@@ -341,13 +395,7 @@ extern "C" gss_status gss_test_query(gss_ctx *ctx, int *done) {
     if (!c.pending_launched) {
         *done = 1;
     } else {
-        const hipError_t e = hipEventQuery(c.ev_done);
-        if (e == hipErrorNotReady) {
-            *done = 0;
-        } else {
-            GSS_HIP(e);
-            *done = 1;
-        }
+        *done = summary_arrived(c, true) ? 1 : 0;
     }
     GSS_API_END
 }

@@ -157,6 +157,7 @@ def load_library(path: Optional[str] = None):
         "gss_store_info": ([P, P, P, P], ctypes.c_int32),
         "gss_set_assignments": ([P, u32, u32, P], ctypes.c_int32),
         "gss_set_var_values": ([P, u32, u32, u32, P, P], ctypes.c_int32),
+        "gss_set_var_values_async": ([P, u32, u32, u32, P, P], ctypes.c_int32),
         "gss_clear_slots": ([P, u32, u32], ctypes.c_int32),
         "gss_test": ([P, u32, P], ctypes.c_int32),
         "gss_fetch_reports": ([P, P, u64, P], ctypes.c_int32),
@@ -290,6 +291,17 @@ def gss_set_var_values(ctx, first_slot: int, vars_, values) -> None:
     n_slots = int(values.shape[1])
     ptr, keep, _ = _data_ptr(values, np.int8)
     _check(ctx, load_library().gss_set_var_values(ctx, first_slot, n_slots, len(vars_), _np_ptr(vars_), ptr))
+    del keep
+
+
+def gss_set_var_values_async(ctx, first_slot: int, vars_, values) -> None:
+    """Queued form of gss_set_var_values: values must be device memory that stays
+    unchanged until the next gss_test / gss_test_wait returns (the caller keeps it
+    alive); a failed device-side check is reported by that call."""
+    vars_ = np.ascontiguousarray(vars_, dtype=np.uint32)
+    n_slots = int(values.shape[1])
+    ptr, keep, _ = _data_ptr(values, np.int8)
+    _check(ctx, load_library().gss_set_var_values_async(ctx, first_slot, n_slots, len(vars_), _np_ptr(vars_), ptr))
     del keep
 
 
@@ -527,6 +539,7 @@ class Context:
         cfg.report_capacity = report_capacity
         cfg.hot_vars = hot_vars
         self.torch_stream = None
+        self._held, self._held_by_test = [], []  # device inputs of queued updates, kept alive
         if use_torch:
             import torch
             if not torch.cuda.is_available():
@@ -575,7 +588,9 @@ class Context:
             return
         import torch
         if any(isinstance(x, torch.Tensor) and x.is_cuda for x in xs):
-            self.torch_stream.wait_stream(torch.cuda.current_stream())
+            cur = torch.cuda.current_stream()
+            if cur != self.torch_stream:  # on the same stream the order already holds
+                self.torch_stream.wait_stream(cur)
 
     # -- ABI calls
     def add_clauses(self, lits, offsets) -> np.ndarray:
@@ -595,6 +610,12 @@ class Context:
         self._sync_inputs(values)
         gss_set_var_values(self.ctx, first_slot, vars_, values)
 
+    def set_var_values_async(self, first_slot: int, vars_, values) -> None:
+        """values (a device tensor) is held until the next test has completed."""
+        self._sync_inputs(values)
+        gss_set_var_values_async(self.ctx, first_slot, vars_, values)
+        self._held.append(values)  # until the next test begun after this call completes
+
     def clear_slots(self, first_slot: int, n_slots: int) -> None:
         gss_clear_slots(self.ctx, first_slot, n_slots)
 
@@ -606,15 +627,21 @@ class Context:
 
     def test_async(self, flags: int = 0) -> None:
         gss_test_async(self.ctx, flags)
+        self._held_by_test, self._held = self._held, []
 
     def test_query(self) -> bool:
         return gss_test_query(self.ctx)
 
     def test_wait(self) -> int:
-        return gss_test_wait(self.ctx)
+        try:
+            return gss_test_wait(self.ctx)
+        finally:
+            self._held_by_test = []
 
     def test(self, flags: int = 0) -> int:
-        return gss_test(self.ctx, flags)
+        n = gss_test(self.ctx, flags)  # on an error the queued inputs stay held (harmless if applied)
+        self._held = []
+        return n
 
     def fetch_reports(self, cap: Optional[int] = None) -> np.ndarray:
         if cap is None:

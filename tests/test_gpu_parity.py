@@ -406,6 +406,98 @@ def test_async_test():
     _check(got, oracle.masks(w.lits, w.offsets, w.values))
 
 
+def test_queued_deltas_pipelined_with_tests():
+    """Asynchronous deltas queued behind a test in flight: each test sees exactly
+    the deltas queued before it (whole words and an unaligned partial range)."""
+    import torch
+    w = gen.paper(12, n_clauses=20_000, n_vars=4_000, n_slots=320)
+    rng = np.random.default_rng(13)
+    vals = w.values.copy()
+    flips = gen.flip_rounds(14, w.n_vars, 5)
+    with new_context(w.n_vars, 320) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, vals)
+        want = [oracle.masks(w.lits, w.offsets, vals)]
+        # a synchronous test first sizes the report segments: a pipelined test
+        # that overflows is not repeated once the next delta is queued
+        _check(gpu_dense(ctx, w.n_clauses), want[0])
+        ctx.test_async()
+        for r, flip in enumerate(flips):
+            gen.apply_flips(vals, flip)
+            ctx.set_var_values_async(0, flip, torch.from_numpy(np.ascontiguousarray(vals[:, flip - 1].T)).cuda())
+            if r == 2:  # a second delta on unaligned slots, queued before the same test
+                vs = np.sort(rng.choice(w.n_vars, 500, replace=False)).astype(np.uint32) + 1
+                new = rng.integers(-1, 2, size=(500, 101)).astype(np.int8)
+                ctx.set_var_values_async(37, vs, torch.from_numpy(new).cuda())
+                vals[37:138, vs - 1] = new.T
+            n = ctx.test_wait()  # the test begun before this round's deltas
+            print(f"pipelined round {r}", flush=True)
+            _check(reports_to_dense(ctx.fetch_reports(n), w.n_clauses, 5), want[-1])
+            want.append(oracle.masks(w.lits, w.offsets, vals))
+            ctx.test_async()
+        n = ctx.test_wait()
+        _check(reports_to_dense(ctx.fetch_reports(n), w.n_clauses, 5), want[-1])
+        # the synchronous test after queued deltas sees them as well
+        flip = flips[0]
+        gen.apply_flips(vals, flip)
+        ctx.set_var_values_async(0, flip, torch.from_numpy(np.ascontiguousarray(vals[:, flip - 1].T)).cuda())
+        _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, vals))
+
+
+def test_queued_delta_errors_are_reported_by_the_next_test():
+    import torch
+    w = gen.tiny(15)
+    with new_context(w.n_vars, 64) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, w.values)
+        before = gpu_dense(ctx, w.n_clauses)
+        vs = np.arange(1, 40, dtype=np.uint32)
+        good = torch.from_numpy(np.ascontiguousarray(-w.values[:, vs - 1].T)).cuda()
+        # immediate errors: host values, a variable out of range
+        with pytest.raises(gss.GssError) as e:
+            ctx.set_var_values_async(0, vs, good.cpu().numpy())
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+        with pytest.raises(gss.GssError) as e:
+            ctx.set_var_values_async(0, np.array([3, w.n_vars + 1], np.uint32), good[:2])
+        assert e.value.code == gss.GSS_ERR_BAD_LITERAL
+        # a bad value: that update and the good one queued after it apply nothing,
+        # and the test that follows reports it (its records are those of the old state)
+        bad = good.clone()
+        bad[7, 3] = 4
+        ctx.set_var_values_async(0, vs, bad)
+        ctx.set_var_values_async(0, vs, good)
+        with pytest.raises(gss.GssError) as e:
+            ctx.test()
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG and "-1, 0 or +1" in str(e.value)
+        _check(reports_to_dense(ctx.fetch_reports(), w.n_clauses, 1), before)
+        _check(gpu_dense(ctx, w.n_clauses), before)  # reported once
+        # a variable listed twice, found on the device, reported by test_wait
+        twice = np.array([5, 9, 5], dtype=np.uint32)
+        ctx.set_var_values_async(0, twice, good[:3].contiguous())
+        ctx.test_async()
+        with pytest.raises(gss.GssError) as e:
+            ctx.test_wait()
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG and "twice" in str(e.value)
+        _check(gpu_dense(ctx, w.n_clauses), before)
+        # after the report, queued updates apply again
+        ctx.set_var_values_async(0, vs, good)
+        vals = w.values.copy()
+        vals[:, vs - 1] = -w.values[:, vs - 1]
+        _check(gpu_dense(ctx, w.n_clauses), oracle.masks(w.lits, w.offsets, vals))
+
+
+def test_queued_delta_error_without_a_launch_is_still_reported():
+    import torch
+    with new_context(50, 64) as ctx:  # no clauses: the test launches nothing
+        ctx.set_assignments(0, np.zeros((64, 50), np.int8))
+        bad = torch.full((3, 64), 9, dtype=torch.int8, device="cuda")
+        ctx.set_var_values_async(0, np.array([1, 2, 3], np.uint32), bad)
+        with pytest.raises(gss.GssError) as e:
+            ctx.test()
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
+        assert ctx.test() == 0
+
+
 def test_async_overflow_after_a_change_is_reported_not_repeated():
     """An overflowing asynchronous test is not repeated once the state changed
     behind it (a rerun would test the new state): the exact count is reported,
