@@ -591,8 +591,12 @@ def main():
             tr = json.load(fh)
         if tr.get("kernel_sha256_16") == kernel_hash() and tr.get("config") == desc:
             traffic = tr.get("hbm_bytes_per_launch")
+    # the counters' bytes over the same kernel time: how close the real traffic runs to the peak
+    traffic_gbs = traffic / (kernel_ms * 1e-3) / 1e9 if traffic else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_GBps": round(traffic_gbs, 1) if traffic_gbs else None,
+                "traffic_frac": round(traffic_gbs / HBM_PEAK_GBS, 4) if traffic_gbs else None,
                 "kernel": "gss::k_test", "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes,
                 "alg_bytes": "4 B per stored literal + 8 B per clause (length, id) + plane table once "
                              "(2 rows x W words x 8 B per variable) + 16 B per report"}

@@ -38,6 +38,23 @@ void launch_fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t value) {
     GSS_HIP(hipGetLastError());
 }
 
+// Copy of pinned host memory into device memory by a kernel (16 bytes a lane):
+// unlike a queued DMA copy, it starts as soon as the kernel before it ends.
+__global__ void k_copy_in(const uint4 *src, uint4 *dst, uint64_t n16) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+void copy_in(Ctx &c, void *dst, const void *src_hd, size_t bytes) {
+    if (!bytes) return;
+    GSS_REQUIRE(bytes % 16 == 0 && ((uintptr_t)dst & 15) == 0 && ((uintptr_t)src_hd & 15) == 0, GSS_ERR_DEVICE,
+                "copy_in needs 16-byte sizes and alignment");
+    const uint64_t n16 = bytes / 16;
+    hipLaunchKernelGGL(k_copy_in, dim3(std::min<uint64_t>((n16 + 255) / 256, 4096)), dim3(256), 0, c.stream,
+                       (const uint4 *)src_hd, (uint4 *)dst, n16);
+    GSS_HIP(hipGetLastError());
+}
+
 // Sets *bad when any byte is outside {-1, 0, +1}.
 __global__ void k_check_values(const int8_t *v, uint64_t n, unsigned int *bad) {
     if (values_invalid(v, n, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x))

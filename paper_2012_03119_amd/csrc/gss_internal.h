@@ -275,6 +275,12 @@ unsigned fill_grid(uint64_t n);  // workgroups of 256 for a grid-stride pass ove
 const uint32_t *queue_value_check(Ctx &c, const int8_t *values, uint64_t n);
 void queue_value_check_into(Ctx &c, const int8_t *values, uint64_t n, uint32_t *verdict);
 void check_flag(Ctx &c);
+// Queues a kernel copy of `bytes` (a multiple of 16, 16-byte aligned) from pinned
+// host memory (as kernels address it, Staged::hd) into device memory.
+void copy_in(Ctx &c, void *dst, const void *src_hd, size_t bytes);
+// Queues the copy of the last test's first n kept records, as one list, into
+// device memory dst (on the context's stream).
+void queue_stitch(Ctx &c, gss_report *dst, uint64_t n);
 uint32_t *deferred_flag(Ctx &c);
 uint32_t read_deferred(Ctx &c);
 void report_deferred(Ctx &c, uint32_t verdict);

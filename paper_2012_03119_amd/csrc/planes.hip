@@ -218,11 +218,20 @@ static uint64_t slot_mask(uint32_t first, uint32_t n, uint32_t w) {
     return (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1) << (a - 64 * w));
 }
 
+__global__ void k_copy_words(const uint64_t *src, uint64_t *dst, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// The active words go up by a kernel reading the pinned ring slot: a queued DMA
+// copy would start only after the test before it and then hold up the next one.
 static void upload_active(Ctx &c) {
     c.aggu_valid = false;  // U counts active slots only
     const Ctx::Staged st = c.stage_upload(c.W * 8);
     std::memcpy(st.h, c.h_active.data(), c.W * 8);
-    GSS_HIP(hipMemcpyAsync(c.active, st.h, c.W * 8, hipMemcpyHostToDevice, c.stream));
+    hipLaunchKernelGGL(k_copy_words, dim3((c.W + 255) / 256), dim3(256), 0, c.stream, (const uint64_t *)st.hd, c.active,
+                       c.W);
+    GSS_HIP(hipGetLastError());
     c.stage_done(st);
 }
 

@@ -10,13 +10,15 @@
 //     a variable sent twice keeps its last value)
 //   manager: takes the mailbox (swapping in a free one) and copies it to the
 //     device on a copy stream while the current run still executes; once that
-//     run's records are fetched, it queues the plane update (behind the copy) and
-//     launches the next run
-//   next run: tests every word with a new snapshot; its records are routed by
-//     word to the producers' queues, which is when the snapshot is notified.
+//     run has completed, it queues the copy of the run's records to the host (on
+//     a fetch stream), then the plane update (behind the upload) and the next run
+//   next run: tests every word with a new snapshot; while the run after it
+//     executes, its records are routed by word to the producers' queues, which
+//     is when the snapshot is notified.
 //
 // Runs are launched back to back (continuous batching): while run k executes,
-// the manager admits snapshots, inserts and removals for run k+1.
+// the manager routes the records of run k-1 and admits snapshots, inserts and
+// removals for run k+1.
 #include "gss_internal.h"
 
 #include <algorithm>
@@ -42,9 +44,9 @@ struct Mail {
     uint32_t n = 0;
     char *d = nullptr;
     uint32_t dcap = 0;
-    hipEvent_t done = nullptr;  // recorded after the kernel that read d
-    bool busy = false;          // uploaded or applied, until `done` completes
-    bool queued = false;        // uploaded, plane update not queued yet (`done` not recorded)
+    uint64_t free_after = 0;    // the test queued behind the kernel that read d
+    bool busy = false;          // uploaded or applied, until that test completes
+    bool queued = false;        // uploaded, plane update not queued yet
 
     static size_t vbytes(uint32_t cap) { return ((size_t)cap * 4 + 255) / 256 * 256; }
     static size_t bytes(uint32_t cap) { return vbytes(cap) + (size_t)cap * 16; }
@@ -115,6 +117,11 @@ struct gss_server {
     std::vector<Producer> prod;
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_copied = nullptr;
+    // records of a finished run travel to the host on their own stream while the
+    // next run executes: stitched into fdev[k], copied into pinned rec[k]
+    hipStream_t fetch_stream = nullptr;
+    hipEvent_t ev_stitched = nullptr;
+    hipEvent_t ev_fetched[2] = {nullptr, nullptr};
     FILE *log = nullptr;
 
     // inserts waiting for admission, already validated and encoded by the
@@ -156,8 +163,17 @@ void gss_server::run() {
     uint64_t rng = cfg.seed * 0x2545F4914F6CDD1Dull + 11;
     std::vector<double> staged(P, -1.0), inflight(P, -1.0);  // arrival of the untested / tested snapshot
     std::vector<std::vector<gss_report>> route(P);
-    gss_report *rec = nullptr;  // pinned: the records of a run come back at full link speed
-    uint64_t rec_cap = 0;
+    // two buffer pairs, used in turn: pinned records (they come back at full link
+    // speed) and the device list they are copied from
+    gss_report *rec[2] = {nullptr, nullptr}, *fdev[2] = {nullptr, nullptr};
+    uint64_t rec_cap[2] = {0, 0}, fdev_cap[2] = {0, 0};
+    int next_k = 0;
+    struct Fetch {  // the records of a finished run on their way to the host (at most one)
+        bool active = false;
+        uint64_t run = 0, n = 0;
+        int k = 0;
+        std::vector<double> arrivals;  // per producer: the tested snapshot's send time, or -1
+    } fq;
     std::vector<uint64_t> act(C.W, 0);
     struct Taken {
         uint32_t p;
@@ -195,9 +211,7 @@ void gss_server::run() {
                     Mail &x = pr.mail[k];
                     if (x.queued) continue;
                     if (x.busy) {
-                        const hipError_t e = hipEventQuery(x.done);
-                        if (e == hipErrorNotReady) continue;
-                        GSS_HIP(e);
+                        if (C.tests_completed < x.free_after) continue;
                         x.busy = false;
                     }
                     free_k = k;
@@ -244,7 +258,7 @@ void gss_server::run() {
                 const size_t vb = Mail::vbytes(m.dcap);
                 launch_set_words(C, x.p, (const uint32_t *)m.d, (const uint64_t *)(m.d + vb),
                                  (const uint64_t *)(m.d + vb) + m.dcap, m.n);
-                GSS_HIP(hipEventRecord(m.done, C.stream));
+                m.free_after = C.tests_launched + 1;  // the run launched right after this
                 m.queued = false;
                 if (log) {
                     std::fprintf(log, "W %u %u\n", x.p, m.n);
@@ -305,7 +319,7 @@ void gss_server::run() {
                 if (admitted) {
                     res.inserted += n;
                     live.insert(live.end(), ids.begin(), ids.end());
-                    if (log)
+                    if (log) {
                         for (uint32_t i = 0; i < n; ++i) {
                             std::fprintf(log, "A %u %llu", ids[i], (unsigned long long)(ins.offs[i + 1] - ins.offs[i]));
                             for (uint64_t k = ins.offs[i]; k < ins.offs[i + 1]; ++k) {
@@ -314,6 +328,7 @@ void gss_server::run() {
                             }
                             std::fputc('\n', log);
                         }
+                    }
                     ins.clear();
                 } else {
                     // budget full: back in front of what arrived since, until a removal
@@ -325,6 +340,52 @@ void gss_server::run() {
                 }
             }
         }
+    };
+
+    // Routes the records of the fetched run to the producers' queues (which is when
+    // their snapshots are notified).  With wait false, returns false while the copy
+    // is still on its way.  Runs on the manager thread while the next run executes
+    // (a thread of its own measured slower: the host cores are shared with the
+    // solver threads).
+    auto route_fetch = [&](bool wait) -> bool {
+        if (!fq.active) return false;
+        if (wait) {
+            timed(res.fetch_ms, [&] { GSS_HIP(hipEventSynchronize(ev_fetched[fq.k])); });
+        } else {
+            const hipError_t e = hipEventQuery(ev_fetched[fq.k]);
+            if (e == hipErrorNotReady) return false;
+            GSS_HIP(e);
+        }
+        const double route_t0 = now();
+        const gss_report *r = rec[fq.k];
+        const uint64_t got = fq.n;
+        for (auto &x : route) x.clear();
+        for (uint64_t i = 0; i < got; ++i) route[r[i].word].push_back(r[i]);
+        if (log) {
+            for (uint64_t i = 0; i < got; ++i)
+                std::fprintf(log, "P %llu %u %u %llx\n", (unsigned long long)fq.run, r[i].clause_id, r[i].word,
+                             (unsigned long long)r[i].mask);
+            std::fprintf(log, "E %llu %llu\n", (unsigned long long)fq.run, (unsigned long long)got);
+        }
+        const double t = now();
+        for (uint32_t p = 0; p < P; ++p) {
+            if (fq.arrivals[p] < 0) continue;
+            {
+                Producer &pr = prod[p];
+                std::lock_guard<std::mutex> g(pr.omu);
+                if (pr.outbox.empty())
+                    pr.outbox.swap(route[p]);
+                else
+                    pr.outbox.insert(pr.outbox.end(), route[p].begin(), route[p].end());
+                pr.last_run = fq.run;
+            }
+            lat.push_back((t - fq.arrivals[p]) * 1e3);
+            res.tested++;
+        }
+        res.reports += got;
+        res.route_ms += (now() - route_t0) * 1e3;
+        fq.active = false;
+        return true;
     };
 
     auto finish = [&]() {
@@ -351,45 +412,42 @@ void gss_server::run() {
                 }
             return;
         }
-        if (n > rec_cap) {
-            if (rec) (void)hipHostFree(rec);
-            rec = nullptr;
-            rec_cap = 0;
+        // routes the records of the run fetched before this one, then starts this
+        // run's fetch; the next run is launched without waiting for it
+        if (fq.active) route_fetch(true);
+        const int k = next_k;
+        next_k ^= 1;
+        if (n > rec_cap[k]) {
+            if (rec[k]) (void)hipHostFree(rec[k]);
+            rec[k] = nullptr;
+            rec_cap[k] = 0;
             const uint64_t want = n + n / 4 + 1024;
-            GSS_HIP(hipHostMalloc((void **)&rec, want * sizeof(gss_report), hipHostMallocDefault));
-            rec_cap = want;
+            GSS_HIP(hipHostMalloc((void **)&rec[k], want * sizeof(gss_report), hipHostMallocDefault));
+            rec_cap[k] = want;
         }
-        uint64_t got = 0;
-        gss_status rf = GSS_OK;
-        timed(res.fetch_ms, [&] { rf = gss_fetch_reports(ctx, rec, n, &got); });
-        if (rf != GSS_OK) throw Error(rf, C.last_error);
-        const double route_t0 = now();
-        for (auto &r : route) r.clear();
-        for (uint64_t i = 0; i < got; ++i) route[rec[i].word].push_back(rec[i]);
-        if (log) {
-            for (uint64_t i = 0; i < got; ++i)
-                std::fprintf(log, "P %llu %u %u %llx\n", (unsigned long long)this_run, rec[i].clause_id, rec[i].word,
-                             (unsigned long long)rec[i].mask);
-            std::fprintf(log, "E %llu %llu\n", (unsigned long long)this_run, (unsigned long long)got);
+        if (n > fdev_cap[k]) {
+            C.dfree(fdev[k]);
+            fdev[k] = nullptr;
+            fdev_cap[k] = 0;
+            const uint64_t want = n + n / 4 + 1024;
+            fdev[k] = (gss_report *)C.dalloc(want * sizeof(gss_report));
+            fdev_cap[k] = want;
         }
-        const double t = now();
-        for (uint32_t p = 0; p < P; ++p) {
-            if (inflight[p] < 0) continue;
-            {
-                Producer &pr = prod[p];
-                std::lock_guard<std::mutex> g(pr.omu);
-                if (pr.outbox.empty())
-                    pr.outbox.swap(route[p]);
-                else
-                    pr.outbox.insert(pr.outbox.end(), route[p].begin(), route[p].end());
-                pr.last_run = this_run;
+        timed(res.fetch_ms, [&] {
+            if (n) {
+                queue_stitch(C, fdev[k], n);
+                GSS_HIP(hipEventRecord(ev_stitched, C.stream));
+                GSS_HIP(hipStreamWaitEvent(fetch_stream, ev_stitched, 0));
+                GSS_HIP(hipMemcpyAsync(rec[k], fdev[k], n * sizeof(gss_report), hipMemcpyDeviceToHost, fetch_stream));
             }
-            lat.push_back((t - inflight[p]) * 1e3);
-            res.tested++;
-            inflight[p] = -1.0;
-        }
-        res.reports += got;
-        res.route_ms += (now() - route_t0) * 1e3;
+            GSS_HIP(hipEventRecord(ev_fetched[k], fetch_stream));
+        });
+        fq.active = true;
+        fq.run = this_run;
+        fq.n = n;
+        fq.k = k;
+        fq.arrivals = inflight;
+        std::fill(inflight.begin(), inflight.end(), -1.0);
     };
 
     try {
@@ -403,12 +461,16 @@ void gss_server::run() {
                 const gss_status rq = gss_test_query(ctx, &done);
                 if (rq != GSS_OK) throw Error(rq, C.last_error);
                 if (!done && !stopping) {
-                    std::this_thread::sleep_for(std::chrono::microseconds(20));
+                    // the previous run's records, while this one executes
+                    if (!route_fetch(false)) std::this_thread::sleep_for(std::chrono::microseconds(20));
                     continue;
                 }
                 finish();
             }
-            if (stopping) break;
+            if (stopping) {
+                route_fetch(true);
+                break;
+            }
             // ---- next run: every word with an untested snapshot
             uint32_t n_act = 0;
             std::fill(act.begin(), act.end(), 0);
@@ -420,6 +482,7 @@ void gss_server::run() {
                     ++n_act;
                 }
             if (!n_act) {
+                route_fetch(false);
                 if (now() - last_change > 0.005) {
                     timed(res.store_ms, change_store);
                     last_change = now();
@@ -457,7 +520,11 @@ void gss_server::run() {
         (void)gss_test_wait(ctx, &n);
     }
     (void)hipStreamSynchronize(C.stream);
-    if (rec) (void)hipHostFree(rec);
+    (void)hipStreamSynchronize(fetch_stream);
+    for (int k = 0; k < 2; ++k) {
+        if (rec[k]) (void)hipHostFree(rec[k]);
+        C.dfree(fdev[k]);
+    }
     res.gpu_ms = C.stats.total_kernel_ms - kernel_ms0;
 }
 
@@ -488,13 +555,13 @@ extern "C" gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cf
     try {
         GSS_HIP(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
         GSS_HIP(hipEventCreateWithFlags(&s->ev_copied, hipEventDisableTiming));
+        GSS_HIP(hipStreamCreateWithFlags(&s->fetch_stream, hipStreamNonBlocking));
+        GSS_HIP(hipEventCreateWithFlags(&s->ev_stitched, hipEventDisableTiming));
+        for (hipEvent_t &e : s->ev_fetched) GSS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         const uint32_t first = std::min<uint32_t>(s->V, 1u << 16);
         for (Producer &p : s->prod) {
             p.pos.assign((size_t)s->V + 1, 0);
-            for (Mail &m : p.mail) {
-                GSS_HIP(hipEventCreateWithFlags(&m.done, hipEventDisableTiming));
-                ensure_host(m, first, s->V);
-            }
+            for (Mail &m : p.mail) ensure_host(m, first, s->V);
         }
         // every word starts untested and inactive
         std::vector<uint64_t> none(c.W, 0);
@@ -503,12 +570,14 @@ extern "C" gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cf
         c.sync();
     } catch (...) {
         for (Producer &p : s->prod)
-            for (Mail &m : p.mail) {
+            for (Mail &m : p.mail)
                 if (m.h) (void)hipHostFree(m.h);
-                if (m.done) (void)hipEventDestroy(m.done);
-            }
         if (s->ev_copied) (void)hipEventDestroy(s->ev_copied);
         if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+        for (hipEvent_t e : s->ev_fetched)
+            if (e) (void)hipEventDestroy(e);
+        if (s->ev_stitched) (void)hipEventDestroy(s->ev_stitched);
+        if (s->fetch_stream) (void)hipStreamDestroy(s->fetch_stream);
         if (s->log) std::fclose(s->log);
         throw;
     }
@@ -635,11 +704,14 @@ extern "C" gss_status gss_server_stop(gss_server *s, gss_serve_result *out) {
         for (Mail &m : p.mail) {
             if (m.h) (void)hipHostFree(m.h);
             c.dfree(m.d);
-            if (m.done) (void)hipEventDestroy(m.done);
         }
     r.device_bytes_end = c.device_bytes;
     (void)hipEventDestroy(s->ev_copied);
     (void)hipStreamDestroy(s->copy_stream);
+    (void)hipStreamSynchronize(s->fetch_stream);
+    for (hipEvent_t e : s->ev_fetched) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(s->ev_stitched);
+    (void)hipStreamDestroy(s->fetch_stream);
     if (s->log) std::fclose(s->log);
     if (out) *out = r;
     const gss_status st = s->status;

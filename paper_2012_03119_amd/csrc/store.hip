@@ -234,6 +234,19 @@ void Prepared::append(const Prepared &o) {
 }
 
 // ---- ingest, part 2: ids, order, growth and upload
+// Appends one chunk staged on the device at d: codes | coff[m+1] | ids[m].
+static void launch_append(Ctx &c, Bucket &B, uint64_t slot0, const char *d, size_t codes_bytes, size_t coff_bytes,
+                          uint32_t m, uint64_t nl) {
+    const uint32_t *dcodes = (const uint32_t *)d;
+    const uint64_t *dcoff = (const uint64_t *)(d + codes_bytes);
+    const uint32_t *dids = (const uint32_t *)(d + codes_bytes + coff_bytes);
+    hipLaunchKernelGGL(k_append_lits, dim3(grid_for(nl)), dim3(256), 0, c.stream, B.lits, B.stride_log2, slot0, dcodes,
+                       dcoff, m, nl);
+    GSS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_append_meta, dim3(grid_for(m)), dim3(256), 0, c.stream, B.meta, slot0, dcoff, dids, m);
+    GSS_HIP(hipGetLastError());
+}
+
 void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
     const uint32_t n = p.size();
     if (n == 0) return;
@@ -285,12 +298,26 @@ void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
             a = q;
         }
     }
-    // one chunk goes through the upload ring (no waiting for queued tests);
-    // several use the bulk staging, one chunk at a time
-    const bool ring = cuts.size() == 2;
-    Ctx::Staged rs{nullptr, nullptr, -1};
+    // a batch of up to 64 MiB goes through one slot of the upload ring, every chunk
+    // after the previous one (no waiting for queued tests); a larger one uses the
+    // bulk staging, one chunk at a time
+    size_t ring_bytes = 0;
+    for (size_t ch = 0; ch + 1 < cuts.size(); ++ch) {
+        const uint64_t m = cuts[ch + 1] - cuts[ch];
+        ring_bytes += round_up(chunk_lits[ch] * 4, 256) + round_up((m + 1) * 8, 256) + round_up(m * 4, 256);
+    }
+    const bool ring = ring_bytes <= (64u << 20);
+    Ctx::Staged rs{nullptr, nullptr, -1, nullptr};
+    size_t ring_off = 0;
+    struct ChunkLaunch {
+        int b;
+        uint64_t slot0, nl;
+        uint32_t m;
+        size_t off, codes_bytes, coff_bytes;
+    };
+    std::vector<ChunkLaunch> launches;
     if (ring) {
-        rs = c.stage_upload(stage_bytes);  // may raise CAPACITY; nothing has changed yet
+        rs = c.stage_upload(ring_bytes);  // may raise CAPACITY; nothing has changed yet
     } else {
         c.device_stage(stage_bytes);
         c.host_stage(stage_bytes);
@@ -340,8 +367,8 @@ void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
         const size_t coff_bytes = round_up((uint64_t)(m + 1) * 8, 256);
         const size_t ids_bytes = round_up((uint64_t)m * 4, 256);
         const size_t bytes = codes_bytes + coff_bytes + ids_bytes;
-        char *h = ring ? rs.h : (char *)c.host_stage(bytes);
-        char *d = ring ? rs.d : (char *)c.device_stage(bytes);
+        char *h = ring ? rs.h + ring_off : (char *)c.host_stage(bytes);
+        char *d = ring ? rs.d + ring_off : (char *)c.device_stage(bytes);
         uint32_t *hcodes = (uint32_t *)h;
         uint64_t *hcoff = (uint64_t *)(h + codes_bytes);
         uint32_t *hids = (uint32_t *)(h + codes_bytes + coff_bytes);
@@ -364,22 +391,23 @@ void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
             const uint32_t i = order[q0 + r];
             std::memcpy(hcodes + hcoff[r], p.codes.data() + offsets[i], (offsets[i + 1] - offsets[i]) * 4);
         }
-        GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
-        const uint32_t *dcodes = (const uint32_t *)d;
-        const uint64_t *dcoff = (const uint64_t *)(d + codes_bytes);
-        const uint32_t *dids = (const uint32_t *)(d + codes_bytes + coff_bytes);
-        hipLaunchKernelGGL(k_append_lits, dim3(grid_for(nl)), dim3(256), 0, c.stream, B.lits, B.stride_log2, slot0,
-                           dcodes, dcoff, m, nl);
-        GSS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_append_meta, dim3(grid_for(m)), dim3(256), 0, c.stream, B.meta, slot0, dcoff, dids, m);
-        GSS_HIP(hipGetLastError());
-        if (ring)
-            c.stage_done(rs);
-        else
+        if (ring) {  // launched once the whole slot is on the device
+            launches.push_back({b, slot0, nl, m, ring_off, codes_bytes, coff_bytes});
+            ring_off += bytes;
+        } else {
+            GSS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c.stream));
+            launch_append(c, B, slot0, d, codes_bytes, coff_bytes, m, nl);
             c.stage_release();  // the next chunk's host_stage waits for this one
+        }
         slot_cursor[b] += m;
         B.n_slots = slot_cursor[b];
         B.n_lits += nl;
+    }
+    if (ring) {
+        copy_in(c, rs.d, rs.hd, ring_off);
+        for (const ChunkLaunch &L : launches)
+            launch_append(c, c.buckets[L.b], L.slot0, rs.d + L.off, L.codes_bytes, L.coff_bytes, L.m, L.nl);
+        c.stage_done(rs);
     }
     c.live += n;
     c.version++;
@@ -443,13 +471,12 @@ extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint
             std::memcpy(st.h + off * 8, per[b].data(), per[b].size() * 8);
             off += per[b].size();
         }
-        GSS_HIP(hipMemcpyAsync(st.d, st.h, total * 8, hipMemcpyHostToDevice, c.stream));
         off = 0;
-        for (int b = 0; b < kMaxBuckets; ++b) {
+        for (int b = 0; b < kMaxBuckets; ++b) {  // the kernels read the lists from pinned memory
             if (per[b].empty()) continue;
             Bucket &B = c.buckets[b];
             hipLaunchKernelGGL(k_tombstone, dim3(grid_for(per[b].size())), dim3(256), 0, c.stream, B.meta,
-                               (const uint64_t *)st.d + off, (uint32_t)per[b].size());
+                               (const uint64_t *)st.hd + off, (uint32_t)per[b].size());
             GSS_HIP(hipGetLastError());
             off += per[b].size();
         }

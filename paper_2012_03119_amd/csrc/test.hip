@@ -341,6 +341,14 @@ static uint64_t end_test(Ctx &c, uint32_t flags, bool launched) {
     return n;
 }
 
+void queue_stitch(Ctx &c, gss_report *dst, uint64_t n) {
+    if (!n) return;
+    const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>(c.last_waves, 65535));
+    hipLaunchKernelGGL(k_stitch, dim3(grid), dim3(256), 0, c.stream, c.reports, c.seg_counts, c.seg_offsets, c.seg_cap,
+                       c.last_waves, n, dst);
+    GSS_HIP(hipGetLastError());
+}
+
 }  // namespace gss
 
 using namespace gss;
@@ -412,10 +420,7 @@ extern "C" gss_status gss_fetch_reports(gss_ctx *ctx, gss_report *out, uint64_t 
         GSS_REQUIRE(out != nullptr, GSS_ERR_INVALID_ARG, "null argument");
         const bool dev = is_device_pointer(out);
         gss_report *dst = dev ? out : (gss_report *)c.device_stage(n * sizeof(gss_report));
-        const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>(c.last_waves, 65535));
-        hipLaunchKernelGGL(k_stitch, dim3(grid), dim3(256), 0, c.stream, c.reports, c.seg_counts, c.seg_offsets,
-                           c.seg_cap, c.last_waves, n, dst);
-        GSS_HIP(hipGetLastError());
+        queue_stitch(c, dst, n);
         if (!dev) GSS_HIP(hipMemcpyAsync(out, dst, n * sizeof(gss_report), hipMemcpyDeviceToHost, c.stream));
         c.sync();
     }
