@@ -299,6 +299,18 @@ def table1_words(rng, n):
     return f, t
 
 
+def recency_params():
+    """Hit recency as a network: any hit in the last 8 tested runs scores ~1, none
+    scores 0.27 (weights set by hand)."""
+    from paper_2012_03119_amd import gss
+    recency = np.zeros(gss.MLP_PARAMS, dtype=np.float32)
+    recency[4 * 64:12 * 64:64] = 1.0      # W1[4..11][0] = 1
+    recency[832] = 1.0                    # W2[0][0] = 1
+    recency[4992] = 100.0                 # w3[0]
+    recency[5056] = -1.0                  # b3
+    return recency
+
+
 def bench_learned(args, torch, gss):
     """The learned schedule against the plain test on one stream: 32 words of
     Table 1 snapshots, 5% of the variables of each word redrawn per run, over an
@@ -352,7 +364,7 @@ def bench_learned(args, torch, gss):
         advance()
     t1 = time.perf_counter()
     ctx.priority_set_sampling(0)  # the network is trained once: no samples while it schedules
-    loss = ctx.priority_train(args.learn_epochs, batch=4096, lr=3e-3, seed=args.seed + 502)
+    loss = ctx.priority_train(args.learn_epochs, batch=4096, lr=args.learn_lr, seed=args.seed + 502)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     info = ctx.priority_info()
@@ -360,18 +372,13 @@ def bench_learned(args, torch, gss):
     learned = ctx.priority_params()
     p = gss.gss_mlp_forward(ctx.ctx, learned, sx)
     pos = np.sort(p[sy > 0.5])
-    tau = float(pos[int(0.004 * len(pos))]) if len(pos) else 0.5
+    tau = float(pos[int(args.learn_quantile * len(pos))]) if len(pos) else 0.5
     log(f"learned: {info['samples']} samples ({sy.mean():.3f} positive), trained in {t_train:.2f} s "
         f"(loss {loss:.4f}), threshold {tau:.4f}")
-    # hit recency as a network: any hit in the last 8 tested runs scores ~1, none scores 0.27
-    recency = np.zeros(gss.MLP_PARAMS, dtype=np.float32)
-    recency[4 * 64:12 * 64:64] = 1.0      # W1[4..11][0] = 1
-    recency[832] = 1.0                    # W2[0][0] = 1
-    recency[4992] = 100.0                 # w3[0]
-    recency[5056] = -1.0                  # b3
+    recency = recency_params()
     sums = {k: [0, 0.0, 0] for k in ("plain", "learned", "recency", "random")}  # hit bits, kernel ms, runs
     plain_bits = {}
-    low_frac = []
+    low_frac, recency_low = [], []
     overhead = 0.0  # the learned schedule's own work per run: scoring (every K runs) and observing
     K = args.learn_rescore
     n_low_learned = None
@@ -401,7 +408,7 @@ def bench_learned(args, torch, gss):
         sums["plain"][2] += 1
         if r % K == K - 1:  # baselines on the same run (the next run scores everything again)
             ctx.priority_params(set_to=recency)
-            ctx.priority_score(0.5)
+            recency_low.append(ctx.priority_score(0.5) / n0)
             b, ms, _ = run_test(gss.GSS_TEST_SCHEDULED)
             sums["recency"][0] += b
             sums["recency"][1] += ms
@@ -421,6 +428,8 @@ def bench_learned(args, torch, gss):
     out_sched = {}
     for k in ("learned", "recency", "random"):
         runs = sums[k][2]
+        if not runs:  # fewer evaluated runs than one rescoring cycle: no baseline run
+            continue
         hits_plain = sums["plain"][0] if k == "learned" else sums["plain_at_baselines"][0]
         ms = sums[k][1] / max(runs, 1)
         out_sched[k] = {"kernel_ms": ms, "runs": runs, "speedup_vs_plain": plain_ms / ms if ms else None,
@@ -439,7 +448,9 @@ def bench_learned(args, torch, gss):
         "config": {"workload": f"learned: {n0} clauses (length mix) over {V} variables, 32 words of Table 1 "
                                f"snapshots, 5% redrawn per run; MLP 12-64-64-1 fp32 trained on "
                                f"{args.learn_train_runs} runs of hit logs", "threshold": tau,
-                   "low_fraction": float(np.mean(low_frac)), "train_s": t_train, "samples": info["samples"],
+                   "low_fraction": float(np.mean(low_frac)),
+                   "recency_low_fraction": float(np.mean(recency_low)) if recency_low else None,
+                   "train_s": t_train, "samples": info["samples"],
                    "rescore_every": K, "update_every": args.learn_update, "aggregate": bool(args.aggregate)},
         "plain_kernel_ms": plain_ms, "schedules": out_sched,
         "missed_hit_rate": out_sched["learned"]["missed_hit_rate"],
@@ -447,7 +458,9 @@ def bench_learned(args, torch, gss):
     }
     log(f"learned: plain {plain_ms:.3f} ms, " + ", ".join(
         f"{k} {v['kernel_ms']:.3f} ms missed {v['missed_hit_rate']:.4f}" for k, v in out_sched.items()) +
-        f"; learned overhead {overhead_ms:.3f} ms/run, end to end {out_sched['learned']['end_to_end_speedup']:.2f}x")
+        f"; learned overhead {overhead_ms:.3f} ms/run, end to end {out_sched['learned']['end_to_end_speedup']:.2f}x"
+        f"; low fraction learned {np.mean(low_frac):.3f}"
+        + (f", recency {np.mean(recency_low):.3f}" if recency_low else ""))
     print(json.dumps(out), flush=True)
 
 
@@ -460,12 +473,15 @@ def main():
     ap.add_argument("--learn-clauses", type=int, default=8_000_000)
     ap.add_argument("--learn-vars", type=int, default=2_000_000)
     ap.add_argument("--learn-train-runs", type=int, default=24)
-    ap.add_argument("--learn-eval-runs", type=int, default=16)
+    ap.add_argument("--learn-eval-runs", type=int, default=32)
     ap.add_argument("--learn-epochs", type=int, default=2)
     ap.add_argument("--learn-sample-period", type=int, default=64)
-    ap.add_argument("--learn-rescore", type=int, default=16,
+    ap.add_argument("--learn-rescore", type=int, default=32,
                     help="score every clause every K runs (only the changed ones in between)")
-    ap.add_argument("--learn-update", type=int, default=2, help="rescore the changed clauses every U runs")
+    ap.add_argument("--learn-update", type=int, default=4, help="rescore the changed clauses every U runs")
+    ap.add_argument("--learn-lr", type=float, default=3e-3)
+    ap.add_argument("--learn-quantile", type=float, default=0.004,
+                    help="threshold: the score under which this fraction of the training positives fall")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-clauses", type=int, default=8_000_000)
     ap.add_argument("--clauses", type=int, default=4_000_000)
