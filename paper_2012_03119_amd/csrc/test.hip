@@ -1,9 +1,7 @@
-// The single-store clause test: a persistent kernel over one store's tiles, the
-// finalize kernel that turns per-wavefront record counts into totals and segment
-// offsets, the stitch that joins the segments on fetch, and the host entry points
-// gss_test, gss_fetch_reports and gss_fetch_masks.  The per-tile work is the
-// Tester of tester.h (Sections 3.4-3.5).
-#include "tester.h"
+// Host side of the single-store clause test: launch shape, the entry points
+// gss_test, gss_test_async / query / wait, gss_fetch_reports and gss_fetch_masks.
+// The kernels are in test_kernels.h.
+#include "test_kernels.h"
 
 #include <hip/hip_ext.h>
 
@@ -12,89 +10,6 @@
 #include <cstring>
 
 namespace gss {
-
-// Each wavefront walks the tiles t = wave, wave + N, ... (N wavefronts in the
-// grid) and prefetches the next tile's metadata and first codes while it tests
-// the current one.
-template <int LPC, int WPL, int MODE, bool HOT>
-__global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDesc *__restrict__ descs,
-                                                                   const TestArgs a, uint32_t early_exit,
-                                                                   uint32_t dense) {
-    using Ts = Tester<LPC, WPL, MODE, HOT>;
-    extern __shared__ uint64_t lds_rows[];
-    if constexpr (HOT) {
-        const uint32_t n = a.hot_rows * Ts::RW;
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lds_rows[i] = a.planes[i];
-        __syncthreads();
-    }
-    const uint32_t lane = threadIdx.x & 63;
-    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, a.sched_run, a.agg, a.aggu);
-    const uint32_t waves_per_block = blockDim.x / 64;
-    const uint32_t n_waves = gridDim.x * waves_per_block;
-    // wave-uniform by construction; readfirstlane lets the compiler keep it in SGPRs
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * waves_per_block +
-                                                         threadIdx.x / 64);
-    gss_report *const seg = a.reports + (uint64_t)wave * a.seg_cap;
-    uint64_t *const dense_out = dense ? a.dense : nullptr;
-    uint32_t produced = 0;  // records of this wavefront (uniform)
-    uint32_t bi = 0;
-
-    const uint32_t last = a.n_tiles - 1;
-    uint32_t t = wave;
-    typename Ts::Tile cur;
-    ts.open(descs, a.n_buckets, bi, t < a.n_tiles ? t : last, cur);
-    while (t < a.n_tiles) {
-        const uint32_t tn = t + n_waves;
-        typename Ts::Tile nxt;
-        ts.open(descs, a.n_buckets, bi, tn < a.n_tiles ? tn : last, nxt);  // prefetch, unconditionally
-        produced = ts.run(cur, seg, a.seg_cap, produced, early_exit, dense_out);
-        t = tn;
-        cur = nxt;
-    }
-    if (lane == 0) a.seg_counts[wave] = produced;
-}
-
-// summary[3] receives the verdict of the asynchronous updates queued before the
-// test.  The summary is also written straight into pinned host memory, followed by
-// the test's serial number: the host sees the test complete when the serial
-// arrives, with no copy or event queued behind the kernel.
-__global__ __launch_bounds__(1024) void k_finalize(const uint32_t *counts, uint32_t n, uint32_t cap,
-                                                    uint64_t *offsets, unsigned long long *summary,
-                                                    const uint32_t *deferred, unsigned long long *host_summary,
-                                                    unsigned long long serial) {
-    finalize_segments(counts, n, cap, offsets, summary);
-    if (threadIdx.x == 0) {  // the thread that wrote summary[0..2]
-        summary[3] = *deferred;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) host_summary[k] = summary[k];
-        __threadfence_system();  // the summary reaches the host before the serial
-        host_summary[4] = serial;
-        __threadfence_system();
-    }
-}
-
-// Copies the kept records of every segment into one list (segment order), the
-// first `limit` records only.  One workgroup per segment.
-__global__ void k_stitch(const gss_report *reports, const uint32_t *counts, const uint64_t *offsets, uint32_t seg_cap,
-                         uint32_t n_segments, uint64_t limit, gss_report *out) {
-    for (uint32_t s = blockIdx.x; s < n_segments; s += gridDim.x) {
-        const uint32_t n = min(counts[s], seg_cap);
-        const uint64_t base = offsets[s];
-        const u32x4 *src = reinterpret_cast<const u32x4 *>(reports) + (uint64_t)s * seg_cap;
-        u32x4 *dst = reinterpret_cast<u32x4 *>(out);
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-            if (base + i < limit) dst[base + i] = src[i];
-    }
-}
-
-// Dense-mode fetch: out[i] = dense row of ids[i], or zeros when ids[i] == kDeadId.
-__global__ void k_gather_rows(uint64_t *out, const uint64_t *dense, const uint32_t *ids, uint32_t n, uint32_t W) {
-    const uint64_t total = (uint64_t)n * W;
-    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t id = ids[x / W];
-        out[x] = id == kDeadId ? 0ull : dense[(uint64_t)id * W + x % W];
-    }
-}
 
 using KernelFn = void (*)(const BucketDesc *, const TestArgs, uint32_t, uint32_t);
 

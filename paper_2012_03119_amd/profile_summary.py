@@ -19,18 +19,27 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2012_03119_amd", "csrc", f) for f in ("test.hip", "tester.h")]
+CSRC = os.path.join(ROOT, "paper_2012_03119_amd", "csrc")
+# the test kernel's device code; its launch shape constants are matched in gss_internal.h
+KERNEL_SOURCES = [os.path.join(CSRC, f) for f in ("test_kernels.h", "tester.h")]
+LAUNCH_SHAPE = (os.path.join(CSRC, "gss_internal.h"), re.compile(rb"^constexpr \w+ kTest\w+ = .*$", re.M))
 
 
 def kernel_hash() -> str:
-    """Hash of the sources of the test kernel (the counters are stale once it changes)."""
+    """Hash of the test kernel's device code and launch shape (the counters are
+    stale once it changes; host-side code around the launch does not count)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(p, "rb") as fh:
             h.update(fh.read())
+    path, pattern = LAUNCH_SHAPE
+    with open(path, "rb") as fh:
+        for m in pattern.finditer(fh.read()):
+            h.update(m.group(0))
     return h.hexdigest()[:16]
 
 
