@@ -46,9 +46,12 @@ def make_workload(args):
     from paper_2012_03119_amd import gen
     if args.workload == "tiny":
         return gen.tiny(args.seed), "plain test, tiny: 20k clauses x 2k vars, 64 assignments"
-    w = gen.paper(args.seed, n_clauses=args.clauses, n_vars=args.vars, n_slots=args.slots)
+    weights = gen.zipf_weights(args.vars, args.zipf) if args.zipf else None
+    w = gen.paper(args.seed, n_clauses=args.clauses, n_vars=args.vars, n_slots=args.slots, var_weights=weights)
     desc = (f"plain test, paper scale: {args.clauses} clauses x {args.vars} vars, {args.slots} assignments, "
             f"length mix 50%[2,10] 40%[11,50] 10%[51,300], 5% variable flips per round")
+    if args.zipf:
+        desc += f", Zipf({args.zipf}) variable frequencies (variable 1 most frequent)"
     return w, desc
 
 
@@ -488,7 +491,9 @@ def main():
     ap.add_argument("--vars", type=int, default=1_000_000)
     ap.add_argument("--slots", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--hot-vars", type=int, default=0)
+    ap.add_argument("--hot-vars", type=int, default=0, help="variables whose plane rows are staged in LDS")
+    ap.add_argument("--zipf", type=float, default=0.0,
+                    help="Zipf exponent of the variable frequencies (0: uniform, as in the paper-scale workload)")
     ap.add_argument("--report-capacity", type=int, default=1 << 20)
     ap.add_argument("--no-early-exit", action="store_true")
     ap.add_argument("--trigger", action="store_true")

@@ -134,14 +134,14 @@ struct Tester {
 
     // This lane's words of plane row `code`.  Code 0 is the all-ones row, the
     // identity of the AND: literals past a clause's end read it.
+    // A hot row is read from LDS through the same generic load: the address is
+    // chosen per lane, so a wavefront whose lanes mix hot and cold rows issues one
+    // load instead of splitting into an LDS path and a global path.
     __device__ Words<WPL> gather(uint32_t code) const {
         if constexpr (HOT) {
-            if (code < hot_rows) {
-                Words<WPL> r;
-#pragma unroll
-                for (int i = 0; i < WPL; ++i) r.v[i] = lds[code * RW + w0 + i];
-                return r;
-            }
+            const char *p = code < hot_rows ? reinterpret_cast<const char *>(lds + code * RW + w0)
+                                            : pbase + (code << ROW_SHIFT);
+            return load_words<WPL>(p);
         }
         return load_words<WPL>(pbase + (code << ROW_SHIFT));
     }
