@@ -23,7 +23,7 @@ namespace gss {
 
 // Appends one segment of new clauses to a bucket: thread per literal.  Clause i
 // of the segment goes to slot slot0 + i; its codes are codes[coff[i] .. coff[i+1]).
-__global__ void k_append_lits(uint32_t *lits, uint32_t stride_log2, uint64_t slot0,
+__global__ void k_append_lits(uint32_t *lits, uint32_t stride_log2, uint32_t tile_log2, uint64_t slot0,
                               const uint32_t *codes, const uint64_t *coff, uint32_t n_clauses, uint64_t n_lits) {
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n_lits; x += (uint64_t)gridDim.x * blockDim.x) {
         // clause owning literal x: last i with coff[i] <= x
@@ -33,7 +33,7 @@ __global__ void k_append_lits(uint32_t *lits, uint32_t stride_log2, uint64_t slo
             if (coff[mid] <= x) lo = mid; else hi = mid;
         }
         const uint64_t k = x - coff[lo];
-        lits[((slot0 + lo) << stride_log2) + k] = codes[x];
+        lits[code_index(slot0 + lo, (uint32_t)k, stride_log2, tile_log2)] = codes[x];
     }
 }
 
@@ -51,14 +51,14 @@ __global__ void k_tombstone(uint2 *meta, const uint64_t *slots, uint32_t n) {
 
 // Compaction: new slot s takes the clause of old slot old_slot[s]; thread per
 // (new slot, literal row).
-__global__ void k_compact_lits(uint32_t *dst, const uint32_t *src, uint32_t stride_log2, const uint64_t *old_slot,
-                               uint64_t n_new) {
+__global__ void k_compact_lits(uint32_t *dst, const uint32_t *src, uint32_t stride_log2, uint32_t tile_log2,
+                               const uint64_t *old_slot, uint64_t n_new) {
     const uint64_t S = 1ull << stride_log2;
     const uint64_t total = n_new * S;
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t s = x >> stride_log2, k = x & (S - 1);
-        dst[x] = src[(old_slot[s] << stride_log2) + k];
-        (void)s;
+        const uint64_t s = x >> stride_log2;
+        const uint32_t k = (uint32_t)(x & (S - 1));
+        dst[code_index(s, k, stride_log2, tile_log2)] = src[code_index(old_slot[s], k, stride_log2, tile_log2)];
     }
 }
 
@@ -98,6 +98,12 @@ static void host_parallel(uint64_t n, uint64_t weight, F fn) {
     for (auto &x : th) x.join();
 }
 
+static uint32_t tile_log2(const Ctx &c) {
+    uint32_t l = 0;
+    while ((1u << l) < c.T) ++l;
+    return l;
+}
+
 // Fills a meta array with empty slots (length 0, dead id).
 static void fill_meta(Ctx &c, uint2 *meta, uint64_t n) {
     launch_fill_u64(c, reinterpret_cast<uint64_t *>(meta), n, (uint64_t)kDeadId << 32);
@@ -111,8 +117,9 @@ static void grow_bucket(Ctx &c, Bucket &b, uint64_t cap) {
     uint2 *meta = (uint2 *)c.dalloc(cap * 8);
     launch_fill_u32(c, lits, cap * S, 0);
     fill_meta(c, meta, cap);
-    if (b.n_slots) {
-        GSS_HIP(hipMemcpyAsync(lits, b.lits, b.n_slots * S * 4, hipMemcpyDeviceToDevice, c.stream));
+    if (b.n_slots) {  // whole tiles: a tile's codes are interleaved (code_index)
+        const uint64_t used = (b.n_slots + c.T - 1) / c.T * c.T;
+        GSS_HIP(hipMemcpyAsync(lits, b.lits, used * S * 4, hipMemcpyDeviceToDevice, c.stream));
         GSS_HIP(hipMemcpyAsync(meta, b.meta, b.n_slots * 8, hipMemcpyDeviceToDevice, c.stream));
     }
     c.sync();
@@ -145,7 +152,7 @@ static bool compact_bucket(Ctx &c, int bi) {
     if (n_new) {
         GSS_HIP(hipMemcpyAsync(dmap, old_slot.data(), n_new * 8, hipMemcpyHostToDevice, c.stream));
         hipLaunchKernelGGL(k_compact_lits, dim3(grid_for(n_new * S)), dim3(256), 0, c.stream, lits, b.lits,
-                           b.stride_log2, dmap, n_new);
+                           b.stride_log2, tile_log2(c), dmap, n_new);
         GSS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_compact_meta, dim3(grid_for(n_new)), dim3(256), 0, c.stream, meta, b.meta, dmap, n_new);
         GSS_HIP(hipGetLastError());
@@ -240,7 +247,7 @@ static void launch_append(Ctx &c, Bucket &B, uint64_t slot0, const char *d, size
     const uint32_t *dcodes = (const uint32_t *)d;
     const uint64_t *dcoff = (const uint64_t *)(d + codes_bytes);
     const uint32_t *dids = (const uint32_t *)(d + codes_bytes + coff_bytes);
-    hipLaunchKernelGGL(k_append_lits, dim3(grid_for(nl)), dim3(256), 0, c.stream, B.lits, B.stride_log2, slot0, dcodes,
+    hipLaunchKernelGGL(k_append_lits, dim3(grid_for(nl)), dim3(256), 0, c.stream, B.lits, B.stride_log2, tile_log2(c), slot0, dcodes,
                        dcoff, m, nl);
     GSS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_append_meta, dim3(grid_for(m)), dim3(256), 0, c.stream, B.meta, slot0, dcoff, dids, m);

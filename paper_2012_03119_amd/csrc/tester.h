@@ -154,7 +154,8 @@ struct Tester {
         const uint32_t slot = (t - d.tile_begin) * T + j;
         tl.s_log2 = d.stride_log2;
         tl.lits = make_rsrc(d.lits, d.lits_bytes);
-        tl.code_off = slot << (d.stride_log2 + 2);
+        // the tile's codes start at tile * T * S; this clause's first group at j * 16 B
+        tl.code_off = (((t - d.tile_begin) * T) << (d.stride_log2 + 2)) + j * 16u;
         const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(d.meta, d.meta_bytes), slot * 8u, 0, 0);
         tl.meta = make_uint2(m[0], m[1]);
         const auto q = __builtin_amdgcn_raw_buffer_load_b128(tl.lits, tl.code_off, 0, 0);
@@ -191,7 +192,9 @@ struct Tester {
             }
             uint4 cn = make_uint4(0, 0, 0, 0);
             if (k + 4 < S) {  // uniform branch: the next four codes, in flight during this group
-                const auto q = __builtin_amdgcn_raw_buffer_load_b128(cur.lits, cur.code_off + (k + 4) * 4u, 0, 0);
+                // group (k + 4) / 4 of this clause: the tile's groups are T * 16 bytes apart
+                const auto q = __builtin_amdgcn_raw_buffer_load_b128(cur.lits, cur.code_off + ((k + 4) >> 2) * (T * 16u),
+                                                                     0, 0);
                 cn = make_uint4(q[0], q[1], q[2], q[3]);
             }
             const uint32_t cs[4] = {c.x, c.y, c.z, c.w};
