@@ -598,3 +598,54 @@ def test_aggregate_pretest_equals_oracle(max_slots):
         # trigger mode: canBeUndef counts active slots only
         _check(gpu_dense(ctx, n, A | gss.GSS_TEST_TRIGGER),
                oracle.masks(lits, offsets, vals, mode="trigger", active=active))
+
+
+def test_more_queued_deltas_than_upload_slots():
+    """Twelve queued deltas (more than the upload ring's slots) with no test in
+    between: a slot whose readers may still be queued is taken only after a
+    synchronisation, and every delta lands."""
+    import torch
+    w = gen.tiny(16)
+    rng = np.random.default_rng(17)
+    vals = w.values.copy()
+    with new_context(w.n_vars, 64) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, vals)
+        for r in range(12):
+            vs = np.sort(rng.choice(w.n_vars, 150, replace=False)).astype(np.uint32) + 1
+            new = rng.integers(-1, 2, size=(150, 64)).astype(np.int8)
+            ctx.set_var_values_async(0, vs, torch.from_numpy(new).cuda())
+            vals[:, vs - 1] = new.T
+            if r == 5:  # a store change queued among them uses the ring too
+                ctx.remove_clauses(np.arange(0, 200, 7, dtype=np.uint32))
+        removed = set(range(0, 200, 7))
+        got = gpu_dense(ctx, w.n_clauses)
+    want = oracle.masks(w.lits, w.offsets, vals)
+    want[sorted(removed)] = 0
+    _check(got, want)
+
+
+def test_inserts_of_several_length_classes_behind_a_test_in_flight():
+    """One batch of inserts spanning several length classes, queued while a test
+    runs (one upload-ring slot, chunks one after another): the running test sees
+    the old store, the next one the new."""
+    w = gen.tiny(18)
+    rng = np.random.default_rng(19)
+    n_old = 12_000
+    old_offs = w.offsets[: n_old + 1]
+    old_lits = w.lits[: old_offs[-1]]
+    new_lits, new_offs = gen.random_clauses(rng, gen.lengths_mix(rng, 3_000), w.n_vars)
+    assert len(np.unique(np.diff(new_offs) > 16)) == 2  # short and long classes
+    with new_context(w.n_vars, 64) as ctx:
+        ctx.add_clauses(old_lits, old_offs)
+        ctx.set_assignments(0, w.values)
+        gpu_dense(ctx, n_old)  # sizes the report segments
+        ctx.test_async()
+        ids = ctx.add_clauses(new_lits, new_offs)
+        assert (ids == np.arange(n_old, n_old + 3_000)).all()
+        n = ctx.test_wait()
+        _check(reports_to_dense(ctx.fetch_reports(n), n_old, 1), oracle.masks(old_lits, old_offs, w.values))
+        got = gpu_dense(ctx, n_old + 3_000)
+    lits = np.concatenate([old_lits, new_lits])
+    offs = np.concatenate([old_offs, old_offs[-1] + new_offs[1:]])
+    _check(got, oracle.masks(lits, offs, w.values))
