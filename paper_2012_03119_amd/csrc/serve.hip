@@ -211,7 +211,13 @@ void gss_server::run() {
                     Mail &x = pr.mail[k];
                     if (x.queued) continue;
                     if (x.busy) {
-                        if (C.tests_completed < x.free_after) continue;
+                        // free once the run queued behind its plane update has completed,
+                        // or once the stream is idle (a run that launched nothing)
+                        if (C.tests_completed < x.free_after) {
+                            const hipError_t e = hipStreamQuery(C.stream);
+                            if (e == hipErrorNotReady) continue;
+                            GSS_HIP(e);
+                        }
                         x.busy = false;
                     }
                     free_k = k;

@@ -15,22 +15,27 @@ using KernelFn = void (*)(const BucketDesc *, const TestArgs, uint32_t, uint32_t
 
 // row words RW (power of two) -> lanes per clause and words per lane (a lane
 // takes one 32-byte sector: 4 words, or the whole row when it is shorter)
-template <int MODE, bool HOT>
+template <int MODE, bool HOT, bool AGG>
 static KernelFn pick_rw(uint32_t rw) {
     switch (rw) {
-    case 1: return k_test<1, 1, MODE, HOT>;
-    case 2: return k_test<1, 2, MODE, HOT>;
-    case 4: return k_test<1, 4, MODE, HOT>;
-    case 8: return k_test<2, 4, MODE, HOT>;
-    case 16: return k_test<4, 4, MODE, HOT>;
-    case 32: return k_test<8, 4, MODE, HOT>;
-    default: return k_test<16, 4, MODE, HOT>;
+    case 1: return k_test<1, 1, MODE, HOT, AGG>;
+    case 2: return k_test<1, 2, MODE, HOT, AGG>;
+    case 4: return k_test<1, 4, MODE, HOT, AGG>;
+    case 8: return k_test<2, 4, MODE, HOT, AGG>;
+    case 16: return k_test<4, 4, MODE, HOT, AGG>;
+    case 32: return k_test<8, 4, MODE, HOT, AGG>;
+    default: return k_test<16, 4, MODE, HOT, AGG>;
     }
 }
 
-static KernelFn pick_kernel(uint32_t rw, int mode, bool hot) {
-    if (mode == 0) return hot ? pick_rw<0, true>(rw) : pick_rw<0, false>(rw);
-    return hot ? pick_rw<1, true>(rw) : pick_rw<1, false>(rw);
+template <bool AGG>
+static KernelFn pick_mode(uint32_t rw, int mode, bool hot) {
+    if (mode == 0) return hot ? pick_rw<0, true, AGG>(rw) : pick_rw<0, false, AGG>(rw);
+    return hot ? pick_rw<1, true, AGG>(rw) : pick_rw<1, false, AGG>(rw);
+}
+
+static KernelFn pick_kernel(uint32_t rw, int mode, bool hot, bool agg) {
+    return agg ? pick_mode<true>(rw, mode, hot) : pick_mode<false>(rw, mode, hot);
 }
 
 struct Launch {
@@ -97,7 +102,7 @@ static Launch prepare(Ctx &c, uint32_t flags) {
         c.desc_version = sched ? ~0ull : c.version;
     }
     L.descs = (const BucketDesc *)c.d_desc;
-    L.fn = pick_kernel(c.RW, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot);
+    L.fn = pick_kernel(c.RW, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot, a.agg != nullptr);
     if (hot) L.lds = (size_t)a.hot_rows * c.RW * 8;
     // persistent: exactly as many workgroups as fit on the device at once
     if (c.occ_fn != (const void *)L.fn || c.occ_lds != L.lds) {  // the query costs host time: cache it

@@ -12,11 +12,11 @@ namespace gss {
 // Each wavefront walks the tiles t = wave, wave + N, ... (N wavefronts in the
 // grid) and prefetches the next tile's metadata and first codes while it tests
 // the current one.
-template <int LPC, int WPL, int MODE, bool HOT>
+template <int LPC, int WPL, int MODE, bool HOT, bool AGG>
 __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDesc *__restrict__ descs,
                                                                    const TestArgs a, uint32_t early_exit,
                                                                    uint32_t dense) {
-    using Ts = Tester<LPC, WPL, MODE, HOT>;
+    using Ts = Tester<LPC, WPL, MODE, HOT, AGG>;
     extern __shared__ uint64_t lds_rows[];
     if constexpr (HOT) {
         const uint32_t n = a.hot_rows * Ts::RW;

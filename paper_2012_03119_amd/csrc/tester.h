@@ -31,11 +31,14 @@ namespace gss {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Literals gathered between a lane's liveness checks.  One: a lane whose words
-// died stops at once.  The gathers of a lane then wait on each other, but the
-// lines saved count for more than the latency hidden (measured: 4 -> 1 took the
-// paper-scale test from 0.545 to 0.481 ms).
-constexpr uint32_t kGroup = 1;
+// Literals gathered between a lane's liveness checks.  Plain tests take one: a
+// lane whose words died stops at once; its gathers then wait on each other, but
+// the lines saved count for more than the latency hidden (measured: 4 -> 1 took
+// the paper-scale test from 0.545 to 0.481 ms).  With the aggregate pre-test a
+// group of four is checked at once: its aggregate loads and gathers go out
+// together instead of as one long dependent chain.
+template <bool AGG>
+constexpr uint32_t kGroupOf = AGG ? 4u : 1u;
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that a
 // contiguous range of logical workgroups (neighbouring tiles, sharing cache lines
@@ -94,8 +97,9 @@ __device__ inline Words<WPL> load_words(const char *p) {
 
 // One store's clause test for one lane: LPC lanes per clause, WPL words per lane,
 // a plane row of RW = LPC * WPL words.  MODE 0 = falsified, 1 = trigger.
-template <int LPC, int WPL, int MODE, bool HOT>
+template <int LPC, int WPL, int MODE, bool HOT, bool AGG = false>
 struct Tester {
+    static constexpr uint32_t kGroup = kGroupOf<AGG>;
     static constexpr uint32_t T = 64 / LPC;                 // clauses per wavefront (and per tile)
     static constexpr uint32_t RW = LPC * WPL;               // words per plane row
     static constexpr uint32_t ROW_SHIFT = ilog2<RW>() + 3;  // bytes per plane row
@@ -123,8 +127,8 @@ struct Tester {
     uint64_t act[WPL];
     const char *pbase;
     const uint64_t *lds;
-    const AggT *agg;   // null: no aggregate pre-test; else per literal code: words with an F slot
-    const AggT *aggu;  // trigger mode: per variable, words with an active U slot
+    const AggT *agg;   // AGG: per literal code, words with an F slot
+    const AggT *aggu;  // AGG in trigger mode: per variable, words with an active U slot
 
     __device__ Tester(uint32_t lane, const uint64_t *planes, const uint64_t *active, uint32_t W_, uint32_t hot_rows_,
                       const uint64_t *lds_, uint32_t sched_run_, const void *agg_, const void *aggu_)
@@ -213,7 +217,7 @@ struct Tester {
                     // aggregate pre-test (Section 4): a word where some literal of the
                     // group is F in no slot cannot be falsified; skip the gathers when
                     // that holds for all of this lane's words
-                    if (agg && lane_live) {
+                    if (AGG && lane_live) {
                         uint32_t keep = (1u << WPL) - 1u;
 #pragma unroll
                         for (uint32_t u = 0; u < kGroup; ++u) {
@@ -229,7 +233,7 @@ struct Tester {
                     // trigger mode: the same recurrence over the group aggregates
                     // (canBeFalse of the literal, canBeUndef of its variable) decides
                     // which words can still trigger (Theorem 1: no false negatives)
-                    if (agg && lane_live) {
+                    if (AGG && lane_live) {
 #pragma unroll
                         for (uint32_t u = 0; u < kGroup; ++u) {
                             const uint32_t code = (k + g0 + u < len) ? cs[g0 + u] : 0u;
