@@ -167,7 +167,7 @@ gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots);
 #define GSS_TEST_FALSIFIED 0u         /* default: every literal F */
 #define GSS_TEST_TRIGGER 1u           /* Definition 1: no literal T and at most one not F */
 #define GSS_TEST_NO_EARLY_EXIT 2u     /* read every literal (no wavefront early exit) */
-#define GSS_TEST_SORTED 4u            /* order reports by (clause_id, word) */
+#define GSS_TEST_SORTED 4u            /* gss_fetch_reports returns records ordered by (clause_id, word) */
 #define GSS_TEST_DENSE 8u             /* write one mask row per clause id (see gss_fetch_masks); no reports */
 #define GSS_TEST_NO_REGROW 16u        /* on overflow return GSS_ERR_REPORT_OVERFLOW instead of growing */
 #define GSS_TEST_NO_HOT 32u           /* do not stage hot-variable rows in LDS */
@@ -191,8 +191,10 @@ gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots);
  * GSS_TEST_NO_REGROW: then GSS_ERR_REPORT_OVERFLOW is returned, *out_n_reports
  * holds the exact count, and only the records that fit are kept (which ones is
  * unspecified).  Records come in a deterministic order for a given store, slot
- * set and device (GSS_TEST_SORTED, ordering by id and word, is reserved and
- * rejected with GSS_ERR_INVALID_ARG by this version). */
+ * set and device; with GSS_TEST_SORTED, gss_fetch_reports orders them by clause
+ * id, then word (a device radix sort of every kept record at fetch time, which
+ * needs 64 bytes of device memory per record; cap takes the first records of
+ * that order).  GSS_TEST_SORTED with GSS_TEST_DENSE: INVALID_ARG. */
 gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_reports);
 
 /* The same test split in two: gss_test_async queues it and returns; the host may

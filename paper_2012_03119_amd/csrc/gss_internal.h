@@ -282,6 +282,9 @@ void copy_in(Ctx &c, void *dst, const void *src_hd, size_t bytes);
 // Queues the copy of the last test's first n kept records, as one list, into
 // device memory dst (on the context's stream).
 void queue_stitch(Ctx &c, gss_report *dst, uint64_t n);
+// Writes the n records at src (device) into dst (device) ordered by (clause id,
+// word); synchronises the stream.
+void sort_records(Ctx &c, const gss_report *src, uint64_t n, gss_report *dst);
 uint32_t *deferred_flag(Ctx &c);
 uint32_t read_deferred(Ctx &c);
 void report_deferred(Ctx &c, uint32_t verdict);

@@ -178,7 +178,8 @@ static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
     const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_SORTED | GSS_TEST_DENSE |
                            GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT | GSS_TEST_SCHEDULED | GSS_TEST_AGGREGATE;
     GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "unknown gss_test flag");
-    GSS_REQUIRE(!(flags & GSS_TEST_SORTED), GSS_ERR_INVALID_ARG, "GSS_TEST_SORTED is not supported (sort the fetched records instead)");
+    GSS_REQUIRE(!((flags & GSS_TEST_SORTED) && (flags & GSS_TEST_DENSE)), GSS_ERR_INVALID_ARG,
+                "GSS_TEST_SORTED orders records; GSS_TEST_DENSE produces none");
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is already in flight (call gss_test_wait)");
     if (flags & GSS_TEST_DENSE) {
         const uint64_t rows = std::max<uint64_t>(c.id_loc.size(), 1);
@@ -338,7 +339,28 @@ extern "C" gss_status gss_fetch_reports(gss_ctx *ctx, gss_report *out, uint64_t 
         GSS_REQUIRE(out != nullptr, GSS_ERR_INVALID_ARG, "null argument");
         const bool dev = is_device_pointer(out);
         gss_report *dst = dev ? out : (gss_report *)c.device_stage(n * sizeof(gss_report));
-        queue_stitch(c, dst, n);
+        if (c.last_flags & GSS_TEST_SORTED) {
+            // every kept record takes part in the order; the first n of it are returned
+            const uint64_t all = c.n_kept;
+            gss_report *st = (gss_report *)c.dalloc(all * sizeof(gss_report));
+            gss_report *so = (dev && n == all) ? dst : (gss_report *)c.dalloc(all * sizeof(gss_report));
+            try {
+                queue_stitch(c, st, all);
+                sort_records(c, st, all, so);
+                if (so != dst)
+                    GSS_HIP(hipMemcpyAsync(dst, so, n * sizeof(gss_report), hipMemcpyDeviceToDevice, c.stream));
+                c.sync();
+            } catch (...) {
+                (void)hipStreamSynchronize(c.stream);
+                c.dfree(st);
+                if (so != dst) c.dfree(so);
+                throw;
+            }
+            c.dfree(st);
+            if (so != dst) c.dfree(so);
+        } else {
+            queue_stitch(c, dst, n);
+        }
         if (!dev) GSS_HIP(hipMemcpyAsync(out, dst, n * sizeof(gss_report), hipMemcpyDeviceToHost, c.stream));
         c.sync();
     }

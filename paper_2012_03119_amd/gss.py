@@ -353,6 +353,14 @@ def gss_fetch_reports(ctx, cap: int) -> np.ndarray:
     return out[:n.value]
 
 
+def gss_fetch_reports_into(ctx, ptr: int, cap: int) -> int:
+    """Copies up to cap records into memory at address ptr (device or host, room
+    for cap 16-byte records); returns how many were copied."""
+    n = ctypes.c_uint64()
+    _check(ctx, load_library().gss_fetch_reports(ctx, ctypes.c_void_p(ptr), cap, ctypes.byref(n)))
+    return n.value
+
+
 def gss_fetch_masks(ctx, ids, n_words: int) -> np.ndarray:
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     out = np.zeros((len(ids), n_words), dtype=np.uint64)

@@ -649,3 +649,38 @@ def test_inserts_of_several_length_classes_behind_a_test_in_flight():
     lits = np.concatenate([old_lits, new_lits])
     offs = np.concatenate([old_offs, old_offs[-1] + new_offs[1:]])
     _check(got, oracle.masks(lits, offs, w.values))
+
+
+@pytest.mark.parametrize("mode,max_slots", [("falsified", 320), ("trigger", 320), ("falsified", 2048)])
+def test_sorted_reports_equal_the_oracle_in_order(mode, max_slots):
+    """GSS_TEST_SORTED: the fetched records are exactly the oracle's report set in
+    (clause id, word) order; a smaller cap returns the first records of that order;
+    a device buffer receives the same."""
+    import torch
+    rng = np.random.default_rng(20 + max_slots)
+    V = 3_000
+    lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, 25_000), V)
+    vals = gen.assignments_bernoulli(rng, max_slots, V, rng.uniform(0.3, 0.9, size=max_slots))
+    flags = gss.GSS_TEST_SORTED | (gss.GSS_TEST_TRIGGER if mode == "trigger" else 0)
+    want = oracle.report_set(oracle.masks(lits, offs, vals, mode=mode))
+    with new_context(V, max_slots) as ctx:
+        ctx.add_clauses(lits, offs)
+        ctx.set_assignments(0, vals)
+        n = ctx.test(flags)
+        assert n == len(want) > 1000
+        got = ctx.fetch_reports(n)
+        assert (got == want).all(), f"{mode}: sorted records differ from the oracle"
+        head = ctx.fetch_reports(n // 3)
+        assert (head == want[: n // 3]).all()
+        dev = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+        got_n = gss.gss_fetch_reports_into(ctx.ctx, dev.data_ptr(), n)
+        assert got_n == n
+        raw = dev.cpu().numpy().view(want.dtype).reshape(-1)
+        assert (raw == want).all()
+        # an unsorted test of the same state returns the same set in another order
+        n2 = ctx.test(flags & ~gss.GSS_TEST_SORTED)
+        plain = ctx.fetch_reports(n2)
+        assert (np.sort(plain, order=["clause_id", "word"]) == want).all()
+        with pytest.raises(gss.GssError) as e:
+            ctx.test(gss.GSS_TEST_SORTED | gss.GSS_TEST_DENSE)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG
