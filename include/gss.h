@@ -52,6 +52,7 @@ typedef int32_t gss_status;
 #define GSS_ERR_REPORT_OVERFLOW (-5) /* more hits than report capacity; count is still exact */
 #define GSS_ERR_DEVICE (-6)          /* a HIP runtime call failed */
 #define GSS_ERR_STATE (-7)           /* call not valid now (e.g. fetch before any test) */
+#define GSS_NOT_READY 1              /* gss_poll: the test is still running (not an error) */
 
 typedef struct gss_ctx gss_ctx;
 
@@ -152,6 +153,11 @@ gss_status gss_set_var_values_async(gss_ctx *ctx, uint32_t first_slot, uint32_t 
  * unchanged; activity is not changed. */
 gss_status gss_update_words(gss_ctx *ctx, uint32_t word, uint32_t n_vars, const uint32_t *vars,
                             const uint64_t *f_words, const uint64_t *t_words);
+/* The same call under the name of a delta of variable rows: fp_words are the F
+ * words (a positive literal is false), fn_words the T words (a negative literal
+ * is false). */
+gss_status gss_update_vars(gss_ctx *ctx, uint32_t word, uint32_t n_vars, const uint32_t *vars,
+                           const uint64_t *fp_words, const uint64_t *fn_words);
 
 /* Replaces the set of active slots (W words, host): the slots a test reports on.
  * Plane values of inactive slots are kept, so a slot group can be switched off
@@ -210,6 +216,11 @@ gss_status gss_test(gss_ctx *ctx, uint32_t flags, uint64_t *out_n_reports);
 gss_status gss_test_async(gss_ctx *ctx, uint32_t flags);
 gss_status gss_test_query(gss_ctx *ctx, int *done);
 gss_status gss_test_wait(gss_ctx *ctx, uint64_t *out_n_reports);
+/* Non-blocking form of the two above: GSS_NOT_READY (a positive status, not an
+ * error) while the test in flight runs; once it has completed, exactly
+ * gss_test_wait (its status and *out_n_reports).  No test in flight:
+ * GSS_ERR_STATE. */
+gss_status gss_poll(gss_ctx *ctx, uint64_t *out_n_reports);
 
 /* Copies the records of the last gss_test into out (host or device, room for cap
  * records) as one list.  *out_n receives the number copied: min(cap, records

@@ -489,3 +489,8 @@ extern "C" gss_status gss_set_active(gss_ctx *ctx, const uint64_t *active) {
     upload_active(c);
     GSS_API_END
 }
+
+extern "C" gss_status gss_update_vars(gss_ctx *ctx, uint32_t word, uint32_t n_vars, const uint32_t *vars,
+                                      const uint64_t *fp_words, const uint64_t *fn_words) {
+    return gss_update_words(ctx, word, n_vars, vars, fp_words, fn_words);
+}

@@ -314,6 +314,14 @@ extern "C" gss_status gss_test_wait(gss_ctx *ctx, uint64_t *out_n_reports) {
     GSS_API_END
 }
 
+extern "C" gss_status gss_poll(gss_ctx *ctx, uint64_t *out_n_reports) {
+    int done = 0;
+    const gss_status q = gss_test_query(ctx, &done);
+    if (q != GSS_OK) return q;
+    if (!done) return GSS_NOT_READY;
+    return gss_test_wait(ctx, out_n_reports);
+}
+
 extern "C" gss_status gss_test_query(gss_ctx *ctx, int *done) {
     GSS_API_BEGIN(ctx)
     Ctx &c = *c_;

@@ -32,6 +32,7 @@ GSS_TEST_FALSIFIED = 0
 GSS_TEST_TRIGGER = 1
 GSS_TEST_NO_EARLY_EXIT = 2
 GSS_TEST_SORTED = 4
+GSS_NOT_READY = 1  # gss_poll: the test is still running
 GSS_TEST_DENSE = 8
 GSS_TEST_NO_REGROW = 16
 GSS_TEST_NO_HOT = 32
@@ -166,9 +167,11 @@ def load_library(path: Optional[str] = None):
         "gss_reset_stats": ([P], ctypes.c_int32),
         "gss_get_stream": ([P, ctypes.POINTER(P)], ctypes.c_int32),
         "gss_update_words": ([P, u32, u32, P, P, P], ctypes.c_int32),
+        "gss_update_vars": ([P, u32, u32, P, P, P], ctypes.c_int32),
         "gss_set_active": ([P, P], ctypes.c_int32),
         "gss_test_async": ([P, u32], ctypes.c_int32),
         "gss_test_query": ([P, P], ctypes.c_int32),
+        "gss_poll": ([P, P], ctypes.c_int32),
         "gss_test_wait": ([P, P], ctypes.c_int32),
         "gss_batch_create": ([P, u32, ctypes.POINTER(P)], ctypes.c_int32),
         "gss_batch_destroy": ([P], None),
@@ -322,6 +325,17 @@ def gss_set_active(ctx, active) -> None:
 
 def gss_test_async(ctx, flags: int = 0) -> None:
     _check(ctx, load_library().gss_test_async(ctx, flags))
+
+
+def gss_poll(ctx) -> Optional[int]:
+    """None while the test in flight runs; once it has completed, its record count
+    (the test is then complete, as after gss_test_wait)."""
+    n = ctypes.c_uint64()
+    rc = load_library().gss_poll(ctx, ctypes.byref(n))
+    if rc == GSS_NOT_READY:
+        return None
+    _check(ctx, rc)
+    return n.value
 
 
 def gss_test_query(ctx) -> bool:
@@ -636,6 +650,16 @@ class Context:
     def test_async(self, flags: int = 0) -> None:
         gss_test_async(self.ctx, flags)
         self._held_by_test, self._held = self._held, []
+
+    def poll(self) -> Optional[int]:
+        try:
+            n = gss_poll(self.ctx)
+        except GssError:
+            self._held_by_test = []  # the test completed with an error
+            raise
+        if n is not None:
+            self._held_by_test = []
+        return n
 
     def test_query(self) -> bool:
         return gss_test_query(self.ctx)

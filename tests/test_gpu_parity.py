@@ -684,3 +684,34 @@ def test_sorted_reports_equal_the_oracle_in_order(mode, max_slots):
         with pytest.raises(gss.GssError) as e:
             ctx.test(gss.GSS_TEST_SORTED | gss.GSS_TEST_DENSE)
         assert e.value.code == gss.GSS_ERR_INVALID_ARG
+
+
+def test_poll_and_update_vars():
+    """gss_poll completes a test once it is done (GSS_NOT_READY before, never an
+    error while it runs); gss_update_vars is gss_update_words under its other name."""
+    w = gen.tiny(21)
+    rng = np.random.default_rng(22)
+    vals = w.values.copy()
+    with new_context(w.n_vars, 64) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, vals)
+        with pytest.raises(gss.GssError) as e:
+            ctx.poll()  # no test in flight
+        assert e.value.code == gss.GSS_ERR_STATE
+        vs = np.sort(rng.choice(w.n_vars, 200, replace=False)).astype(np.uint32) + 1
+        new = rng.integers(-1, 2, size=(64, 200)).astype(np.int8)
+        bits = (np.uint64(1) << np.arange(64, dtype=np.uint64))[:, None]
+        fp = ((new == -1).astype(np.uint64) * bits).sum(axis=0, dtype=np.uint64)
+        fn = ((new == 1).astype(np.uint64) * bits).sum(axis=0, dtype=np.uint64)
+        lib = gss.load_library()
+        rc = lib.gss_update_vars(ctx.ctx, 0, len(vs), vs.ctypes.data, fp.ctypes.data, fn.ctypes.data)
+        assert rc == gss.GSS_OK
+        vals[:, vs - 1] = new
+        ctx.test_async()
+        polls = 0
+        while (n := ctx.poll()) is None:
+            polls += 1
+        got = reports_to_dense(ctx.fetch_reports(n), w.n_clauses, 1)
+        _check(got, oracle.masks(w.lits, w.offsets, vals))
+        with pytest.raises(gss.GssError):
+            ctx.poll()  # completed: nothing in flight any more
