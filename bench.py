@@ -330,17 +330,46 @@ def bench_learned(args, torch, gss):
     lens = np.diff(offs)
     ctx = gss.Context(V, P * 64, hbm_budget_bytes=64 << 30, report_capacity=1 << 22)
     ids = ctx.add_clauses(lits, offs)
+    n_s = min(n0, 200_000)  # clause sample for the aggregate-negative ratio
+    s_lits, s_offs = lits[: offs[n_s]].copy(), offs[: n_s + 1].copy()
     del lits, offs
     ctx.priority_enable(n_sources=P, sample_period=args.learn_sample_period, sample_capacity=1 << 22,
                         seed=args.seed + 501)
     ctx.priority_set_clause_info(ids, (2 + rng.random(n0) * (np.maximum(lens, 2) - 2)).astype(np.float32),
                                  rng.integers(0, P, n0).astype(np.uint32))
     all_vars = np.arange(1, V + 1, dtype=np.uint32)
+    # Section 4: a (clause, word) pair whose aggregate test is negative (some
+    # literal is F in no slot of the word) cannot be falsified in that word
+    # (falsified); trigger mode runs the recurrence of Section 4.3 over canBeFalse
+    # and canBeUndef of the clause's literals, position by position
+    s_var = np.abs(s_lits).astype(np.int64) - 1
+    s_pos = s_lits > 0
+    s_len = np.diff(s_offs)
+    s_clause = np.repeat(np.arange(n_s), s_len)
+    s_k = np.arange(len(s_lits)) - np.repeat(s_offs[:-1], s_len)  # position in the clause
+    by_k = np.argsort(s_k, kind="stable")  # literal entries grouped by position
+    k_start = np.searchsorted(s_k[by_k], np.arange(int(s_len.max()) + 1))
+    agg_negative = agg_negative_trigger = 0
     for w in range(P):
         f, t = table1_words(rng, V)
         ctx.update_words(w, all_vars, f, t)
+        cbf = np.where(s_pos, f[s_var] != 0, t[s_var] != 0)
+        cbu = (f[s_var] | t[s_var]) != ~np.uint64(0)
+        agg_negative += int(np.count_nonzero(np.bincount(s_clause[~cbf], minlength=n_s)))
+        af = np.ones(n_s, dtype=bool)
+        ou = np.zeros(n_s, dtype=bool)
+        for k in range(int(s_len.max())):
+            at = by_k[k_start[k]:k_start[k + 1]]
+            c, lf, lu = s_clause[at], cbf[at], cbu[at]
+            ou[c] = (af[c] & lu) | (ou[c] & lf)
+            af[c] &= lf
+        agg_negative_trigger += int(np.count_nonzero(~(af | ou)))
+    agg_negative_ratio = agg_negative / (n_s * P)
+    agg_negative_trigger_ratio = agg_negative_trigger / (n_s * P)
+    del s_var, s_pos, s_clause, s_k
     ctx.set_active(np.full(P, 2**64 - 1, dtype=np.uint64))
-    log(f"learned: store and snapshots ready in {time.perf_counter() - t0:.1f} s")
+    log(f"learned: store and snapshots ready in {time.perf_counter() - t0:.1f} s; aggregate-negative ratio "
+        f"{agg_negative_ratio:.4f} (trigger {agg_negative_trigger_ratio:.4f}) over {n_s} clauses x {P} words")
     blocks = (V + 63) // 64
 
     def advance():  # every word redraws 5% of its variables, in runs of 64
@@ -454,7 +483,10 @@ def bench_learned(args, torch, gss):
                    "low_fraction": float(np.mean(low_frac)),
                    "recency_low_fraction": float(np.mean(recency_low)) if recency_low else None,
                    "train_s": t_train, "samples": info["samples"],
-                   "rescore_every": K, "update_every": args.learn_update, "aggregate": bool(args.aggregate)},
+                   "rescore_every": K, "update_every": args.learn_update, "aggregate": bool(args.aggregate),
+                   "aggregate_negative_ratio": agg_negative_ratio,
+                   "aggregate_negative_ratio_trigger": agg_negative_trigger_ratio,
+                   "aggregate_negative_how": f"falsified aggregate test of {n_s} clauses x {P} words, first snapshot"},
         "plain_kernel_ms": plain_ms, "schedules": out_sched,
         "missed_hit_rate": out_sched["learned"]["missed_hit_rate"],
         "speedup_vs_plain": out_sched["learned"]["speedup_vs_plain"],
