@@ -135,8 +135,9 @@ gss_status gss_set_var_values(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slot
 /* The same delta with nothing waited for, so that a loop of deltas and tests
  * keeps the device busy.  values must be device memory, read by kernels queued on
  * the context's stream; it must stay unchanged until the first test begun after
- * this call has completed (the return of that gss_test, or of the gss_test_wait
- * of that gss_test_async).  vars, a host array, is copied before return.  The
+ * this call has completed (the return of that gss_test, of the gss_test_wait of
+ * that gss_test_async, or of a gss_batch_test that includes the context).  vars,
+ * a host array, is copied before return.  The
  * slot range and the variable range are checked at once (nothing is queued on
  * error); the values and repeated variables are checked on the device.  An update
  * that fails that check applies nothing, nor do the asynchronous updates queued

@@ -28,6 +28,7 @@ struct StoreDesc {
     uint32_t RW;
     uint32_t seg_cap;
     uint32_t pad;
+    const uint32_t *deferred;  // the context's verdict of queued updates (reported after the test)
 };
 
 // A run of `count` consecutive tiles of one store, starting at its tile `tile0`;
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(1024) void k_finalize_batch(const StoreDesc *stores
                                                           unsigned long long *summary) {
     const StoreDesc &st = stores[blockIdx.x];
     finalize_segments(st.seg_counts, n_waves, st.seg_cap, st.seg_offsets, summary + 4 * blockIdx.x);
+    if (threadIdx.x == 0) summary[4 * blockIdx.x + 3] = *st.deferred;  // the thread that wrote the others
 }
 
 }  // namespace gss
@@ -193,6 +195,7 @@ void plan(gss_batch &b) {
         sd.RW = c.RW;
         sd.seg_cap = c.seg_cap;
         sd.pad = 0;
+        sd.deferred = deferred_flag(c);
     }
 
     std::vector<SchedSeg> segs;
@@ -360,6 +363,20 @@ bool run_once(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
             }
         }
     }
+    // failed checks of queued updates: every context's verdict is cleared, the first reported
+    gss_status bad = GSS_OK;
+    std::string why;
+    for (uint32_t s = 0; s < n; ++s) {
+        try {
+            report_deferred(*b.ctxs[s], (uint32_t)b.h_summary[4 * s + 3]);
+        } catch (const Error &e) {
+            if (bad == GSS_OK) {
+                bad = e.code;
+                why = std::string("store ") + std::to_string(s) + ": " + e.what();
+            }
+        }
+    }
+    GSS_REQUIRE(bad == GSS_OK, bad, why);
     return overflow;
 }
 

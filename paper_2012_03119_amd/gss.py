@@ -827,7 +827,10 @@ class Batch:
         gss_batch_set_schedule(self.b, order, chunk_tiles, blocks_per_cu)
 
     def test(self, flags: int = 0) -> np.ndarray:
-        return gss_batch_test(self.b, len(self.contexts), flags)
+        counts = gss_batch_test(self.b, len(self.contexts), flags)
+        for c in self.contexts:  # their queued updates have been read
+            c._held = []
+        return counts
 
     def info(self) -> dict:
         return gss_batch_info(self.b)

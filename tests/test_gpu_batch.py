@@ -124,3 +124,38 @@ def test_autotuner_picks_and_caches(tmp_path):
         assert again["source"] == "cache" and again["order"] == first["order"]
     for it in items:
         it[1].close()
+
+
+def test_batch_with_queued_deltas_and_their_errors():
+    """Queued (asynchronous) deltas of every store land before a batched test, in
+    graph replays too; a failed device-side check is reported by the batched test,
+    which applies nothing of that store's queued updates and leaves the others."""
+    import torch
+    _, items = _make(6)
+    rng = np.random.default_rng(9)
+    with gss.Batch([it[1] for it in items]) as b:
+        for rep in range(3):
+            for it in items:
+                w, ctx, vals = it
+                vs = np.sort(rng.choice(w.n_vars, max(1, w.n_vars // 20), replace=False)).astype(np.uint32) + 1
+                vals[:, vs - 1] = -vals[:, vs - 1]
+                ctx.set_var_values_async(0, vs, torch.from_numpy(np.ascontiguousarray(vals[:, vs - 1].T)).cuda())
+            counts = b.test(gss.GSS_TEST_GRAPH)
+            print(f"queued deltas, replay {rep}", flush=True)
+            _check_all(items, counts)
+        # store 3: a bad value; store 5: a good delta queued in the same round
+        w3, ctx3, vals3 = items[3]
+        bad = torch.zeros((4, w3.values.shape[0]), dtype=torch.int8, device="cuda")
+        bad[1, 2] = 7
+        ctx3.set_var_values_async(0, np.array([1, 2, 3, 4], np.uint32), bad)
+        w5, ctx5, vals5 = items[5]
+        vs = np.arange(1, 30, dtype=np.uint32)
+        vals5[:, vs - 1] = -vals5[:, vs - 1]
+        ctx5.set_var_values_async(0, vs, torch.from_numpy(np.ascontiguousarray(vals5[:, vs - 1].T)).cuda())
+        with pytest.raises(gss.GssError) as e:
+            b.test(gss.GSS_TEST_GRAPH)
+        assert e.value.code == gss.GSS_ERR_INVALID_ARG and "store 3" in str(e.value)
+        counts = b.test(gss.GSS_TEST_GRAPH)  # reported once; store 3 unchanged, store 5 updated
+        _check_all(items, counts)
+    for it in items:
+        it[1].close()
