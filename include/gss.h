@@ -16,14 +16,16 @@
  * GPU again (gss_remove_clauses, Section 3.7 on deleting GPU clauses).
  *
  * Conventions for every call:
- *  - Return value: GSS_OK (0) or a negative gss_status.  No exception, abort or
+ *  - Return value: GSS_OK (0) or a negative gss_status (gss_poll alone may also
+ *    return the positive GSS_NOT_READY).  No exception, abort or
  *    longjmp crosses this interface.  After an error, gss_last_error() holds a
  *    message.  Errors detected while validating arguments leave the context
  *    unchanged (validate, then apply).  GSS_ERR_DEVICE means a HIP call failed;
  *    the context may then be unusable and should be destroyed.
  *  - Input arrays are owned by the caller and are not retained after the call
- *    returns.  Unless a call says otherwise they are host memory.  Calls marked
- *    "host or device" also accept device pointers (detected with
+ *    returns (gss_set_var_values_async states its own longer lifetime for its
+ *    device values).  Unless a call says otherwise they are host memory.  Calls
+ *    marked "host or device" also accept device pointers (detected with
  *    hipPointerGetAttributes); device inputs must stay valid until the call returns.
  *  - A context is not thread-safe: one thread drives it, like the single GPU
  *    manager thread of the paper's solver (Section 5).  Work is issued on the
