@@ -121,19 +121,32 @@ bool is_device_pointer(const void *p) {
 // memory
 // ---------------------------------------------------------------------------
 
+bool Ctx::fits(uint64_t bytes) {
+    if (cfg.hbm_budget_bytes == 0 || device_bytes + bytes <= cfg.hbm_budget_bytes) return true;
+    if (deferred_frees.empty()) return false;
+    sync();  // releases the deferred frees
+    return device_bytes + bytes <= cfg.hbm_budget_bytes;
+}
+
 void *Ctx::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
-    GSS_REQUIRE(cfg.hbm_budget_bytes == 0 || device_bytes + bytes <= cfg.hbm_budget_bytes, GSS_ERR_CAPACITY,
+    GSS_REQUIRE(fits(bytes), GSS_ERR_CAPACITY,
                 "HBM budget exhausted (" + std::to_string(device_bytes + bytes) + " > " +
                     std::to_string(cfg.hbm_budget_bytes) + " bytes)");
     void *p = nullptr;
-    if (cfg.dev_alloc) {
-        p = cfg.dev_alloc(bytes, stream, cfg.alloc_user);
-        GSS_REQUIRE(p != nullptr, GSS_ERR_DEVICE, "device allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
-    } else {
-        GSS_HIP(hipMalloc(&p, bytes));
+    for (int attempt = 0;; ++attempt) {
+        if (cfg.dev_alloc) {
+            p = cfg.dev_alloc(bytes, stream, cfg.alloc_user);
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        if (p || attempt == 1 || deferred_frees.empty()) break;
+        sync();  // out of device memory with frees pending: release them and retry once
     }
+    GSS_REQUIRE(p != nullptr, cfg.dev_alloc ? GSS_ERR_DEVICE : GSS_ERR_CAPACITY,
+                "device allocation of " + std::to_string(bytes) + " bytes failed");
     allocs[p] = bytes;
     device_bytes += bytes;
     return p;
@@ -200,6 +213,23 @@ void Ctx::sync() {
 void Ctx::mark_idle() {
     tests_completed = tests_launched;
     for (RingSlot &s : ring) s.busy = false;
+    for (auto &d : deferred_frees) d.second = 0;  // everything queued has run
+    release_deferred();
+}
+
+void Ctx::defer_free(void *p) {
+    if (p) deferred_frees.emplace_back(p, tests_launched + 1);
+}
+
+void Ctx::release_deferred() {
+    size_t k = 0;
+    for (auto &d : deferred_frees) {
+        if (d.second <= tests_completed)
+            dfree(d.first);
+        else
+            deferred_frees[k++] = d;
+    }
+    deferred_frees.resize(k);
 }
 
 Ctx::Staged Ctx::stage_upload(size_t bytes) {
@@ -251,6 +281,8 @@ static thread_local std::string g_create_error;
 static void destroy_ctx(Ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    for (auto &d : c->deferred_frees) c->dfree(d.first);
+    c->deferred_frees.clear();
     priority_release(*c);
     mlp_release(*c);
     for (auto &b : c->buckets) {

@@ -214,6 +214,14 @@ struct Ctx {
     void stage_release();
     void sync();
     void mark_idle();  // bookkeeping of sync() after the stream was synchronised elsewhere
+    // Device memory that queued work may still read: freed once the test queued
+    // after that work has completed (or at the next synchronisation).
+    void defer_free(void *p);
+    void release_deferred();  // frees what the completed tests no longer need
+    // true when `bytes` more fit the HBM budget, after releasing deferred frees
+    // (which synchronises) if that is what it takes
+    bool fits(uint64_t bytes);
+    std::vector<std::pair<void *, uint64_t>> deferred_frees;
 
     // Upload ring: small uploads (deltas, inserts, removals, activity) take a slot
     // of pinned host + device memory; the kernels that read it are queued before

@@ -122,9 +122,10 @@ static void grow_bucket(Ctx &c, Bucket &b, uint64_t cap) {
         GSS_HIP(hipMemcpyAsync(lits, b.lits, used * S * 4, hipMemcpyDeviceToDevice, c.stream));
         GSS_HIP(hipMemcpyAsync(meta, b.meta, b.n_slots * 8, hipMemcpyDeviceToDevice, c.stream));
     }
-    c.sync();
-    c.dfree(b.lits);
-    c.dfree(b.meta);
+    // the old arrays may still be read by a test in flight and by the copies just
+    // queued: freed once the next test completes, without waiting here
+    c.defer_free(b.lits);
+    c.defer_free(b.meta);
     b.lits = lits;
     b.meta = meta;
     b.cap_slots = cap;
@@ -142,7 +143,7 @@ static bool compact_bucket(Ctx &c, int bi) {
     const uint64_t S = 1ull << b.stride_log2;
     const uint64_t cap = round_up(std::max<uint64_t>(n_new + n_new / 4, 256), c.T);
     const uint64_t need = cap * S * 4 + cap * 8 + n_new * 8 + 4096;
-    if (c.cfg.hbm_budget_bytes && c.device_bytes + need > c.cfg.hbm_budget_bytes) return false;
+    if (!c.fits(need)) return false;
 
     uint32_t *lits = (uint32_t *)c.dalloc(cap * S * 4);
     uint2 *meta = (uint2 *)c.dalloc(cap * 8);
@@ -150,17 +151,20 @@ static bool compact_bucket(Ctx &c, int bi) {
     launch_fill_u32(c, lits, cap * S, 0);
     fill_meta(c, meta, cap);
     if (n_new) {
-        GSS_HIP(hipMemcpyAsync(dmap, old_slot.data(), n_new * 8, hipMemcpyHostToDevice, c.stream));
+        // the slot map goes up through a pinned ring slot: nothing waits for the copy
+        const Ctx::Staged st = c.stage_upload(n_new * 8);
+        std::memcpy(st.h, old_slot.data(), n_new * 8);
+        GSS_HIP(hipMemcpyAsync(dmap, st.h, n_new * 8, hipMemcpyHostToDevice, c.stream));
+        c.stage_done(st);
         hipLaunchKernelGGL(k_compact_lits, dim3(grid_for(n_new * S)), dim3(256), 0, c.stream, lits, b.lits,
                            b.stride_log2, tile_log2(c), dmap, n_new);
         GSS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_compact_meta, dim3(grid_for(n_new)), dim3(256), 0, c.stream, meta, b.meta, dmap, n_new);
         GSS_HIP(hipGetLastError());
     }
-    c.sync();
-    c.dfree(dmap);
-    c.dfree(b.lits);
-    c.dfree(b.meta);
+    c.defer_free(dmap);  // read by the compaction kernels just queued
+    c.defer_free(b.lits);
+    c.defer_free(b.meta);
     b.lits = lits;
     b.meta = meta;
     b.cap_slots = cap;
@@ -347,8 +351,7 @@ void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
                     GSS_ERR_CAPACITY, "length class " + std::to_string(1u << B.stride_log2) + " would exceed 4 GiB of codes");
         grow_bytes += bucket_bytes(new_cap[b], B.stride_log2);
     }
-    GSS_REQUIRE(c.cfg.hbm_budget_bytes == 0 || c.device_bytes + grow_bytes <= c.cfg.hbm_budget_bytes, GSS_ERR_CAPACITY,
-                "HBM budget exhausted by the clause store");
+    GSS_REQUIRE(c.fits(grow_bytes), GSS_ERR_CAPACITY, "HBM budget exhausted by the clause store");
     for (int b = 0; b < kMaxBuckets; ++b)
         if (new_cap[b]) grow_bucket(c, c.buckets[b], new_cap[b]);
 

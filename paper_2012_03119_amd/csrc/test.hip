@@ -164,6 +164,7 @@ static void complete(Ctx &c) {
     for (uint32_t spins = 1; !summary_arrived(c, (spins & 1023) == 0); ++spins) {
     }
     c.tests_completed = c.tests_launched;
+    c.release_deferred();
     GSS_HIP(hipEventSynchronize(c.ev_stop));  // recorded before the finalize kernel: already complete
     float ms = 0.f;
     GSS_HIP(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
