@@ -715,3 +715,32 @@ def test_poll_and_update_vars():
         _check(got, oracle.masks(w.lits, w.offsets, vals))
         with pytest.raises(gss.GssError):
             ctx.poll()  # completed: nothing in flight any more
+
+
+def test_store_growth_under_a_budget_releases_old_arrays():
+    """A store loaded in many small batches with no test in between: each length
+    class grows several times and its old arrays wait for the next test.  Under a
+    budget of twice the final size (the waiting arrays alone would pass it), a
+    budget check releases them first, every batch fits, and the result is exact."""
+    rng = np.random.default_rng(30)
+    V = 4_000
+    lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, 120_000), V)
+    chunks = np.array_split(np.arange(120_000), 40)
+    vals = gen.assignments_bernoulli(rng, 64, V, rng.uniform(0.3, 0.9, size=64))
+
+    def load(ctx):
+        for ch in chunks:
+            sub_offs = offs[ch[0]: ch[-1] + 2] - offs[ch[0]]
+            ctx.add_clauses(lits[offs[ch[0]]: offs[ch[-1] + 1]], sub_offs)
+
+    with new_context(V, 64) as ctx:  # no budget: the final size once everything is freed
+        load(ctx)
+        ctx.set_assignments(0, vals)
+        gpu_dense(ctx, 120_000)
+        final = ctx.store_info()["device_bytes"]
+    with new_context(V, 64, hbm_budget_bytes=2 * final) as ctx:
+        load(ctx)
+        ctx.set_assignments(0, vals)
+        got = gpu_dense(ctx, 120_000)
+        assert ctx.store_info()["device_bytes"] <= 2 * final
+    _check(got, oracle.masks(lits, offs, vals))
