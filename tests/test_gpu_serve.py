@@ -111,7 +111,7 @@ def replay(path, lits0, offs0, V, W, mode="falsified"):
 
 
 @pytest.mark.parametrize("store,report_capacity,mode", [("mix", 1 << 16, "falsified"), ("short", 1, "falsified"),
-                                                        ("mix", 1 << 16, "trigger")])
+                                                        ("mix", 1 << 16, "trigger"), ("mix", 1 << 16, "aggregate")])
 def test_served_runs_equal_oracle_replay(tmp_path, store, report_capacity, mode):
     W, P = 4, 4
     if store == "mix":  # the length mix of the large workloads
@@ -127,8 +127,10 @@ def test_served_runs_equal_oracle_replay(tmp_path, store, report_capacity, mode)
     print(f"[serve] replay case store={store} capacity={report_capacity} mode={mode}", flush=True)
     res = ctx.serve_simulate(n_threads=P, duration_s=1.0, snapshot_rate=25.0, redraw_fraction=0.05,
                              insert_rate=400.0, delete_fraction=0.1, seed=7,
-                             test_flags=gss.GSS_TEST_TRIGGER if mode == "trigger" else 0, log_path=str(log))
-    counts, clauses, F, T = replay(str(log), lits, offs, V, W, mode)
+                             test_flags={"trigger": gss.GSS_TEST_TRIGGER, "aggregate": gss.GSS_TEST_AGGREGATE}.get(mode, 0),
+                             log_path=str(log))
+    # the aggregate pre-test changes no record: the replay checks the falsified result
+    counts, clauses, F, T = replay(str(log), lits, offs, V, W, "trigger" if mode == "trigger" else "falsified")
     assert res["runs"] == counts["E"] + counts["X"] and counts["E"] >= 5
     assert res["overflowed_runs"] == counts["X"]
     if report_capacity == 1:
@@ -144,10 +146,10 @@ def test_served_runs_equal_oracle_replay(tmp_path, store, report_capacity, mode)
     # the context is usable again: a plain test equals the oracle on the final state
     ones = np.full(W, 2**64 - 1, dtype=np.uint64)
     ctx.set_active(ones)
-    flags = gss.GSS_TEST_TRIGGER if mode == "trigger" else 0
+    flags = {"trigger": gss.GSS_TEST_TRIGGER, "aggregate": gss.GSS_TEST_AGGREGATE}.get(mode, 0)
     n = ctx.test(flags)
     got = np.sort(ctx.fetch_reports(n), order=["clause_id", "word"])
-    want = _expected(clauses, F, T, [2**64 - 1] * W, W, V, mode)
+    want = _expected(clauses, F, T, [2**64 - 1] * W, W, V, "trigger" if mode == "trigger" else "falsified")
     assert len(got) == len(want) and (got == want).all()
     ctx.close()
 
