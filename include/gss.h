@@ -232,7 +232,9 @@ gss_status gss_fetch_reports(gss_ctx *ctx, gss_report *out, uint64_t cap, uint64
 
 /* After a gss_test with GSS_TEST_DENSE: copies the mask rows of n clause ids into
  * out (host or device, uint64 [n][W], W = max_slots/64).  Removed ids give zero
- * rows; ids never issued are GSS_ERR_UNKNOWN_ID. */
+ * rows; ids never issued are GSS_ERR_UNKNOWN_ID; ids issued after that test
+ * (which has no row for them) are GSS_ERR_STATE.  Both are checked on the host
+ * before anything is queued. */
 gss_status gss_fetch_masks(gss_ctx *ctx, const uint32_t *ids, uint32_t n, uint64_t *out);
 
 /* Counters and timings of the context. */
@@ -295,7 +297,8 @@ const char *gss_batch_last_error(const gss_batch *batch);
 gss_status gss_batch_set_schedule(gss_batch *batch, const gss_schedule *schedule);
 
 /* Tests every store of the batch.  flags: GSS_TEST_TRIGGER, GSS_TEST_NO_EARLY_EXIT,
- * GSS_TEST_NO_REGROW, GSS_TEST_GRAPH.  out_n_reports (n entries, may be NULL)
+ * GSS_TEST_NO_REGROW, GSS_TEST_GRAPH.  A member with a gss_test_async in flight:
+ * GSS_ERR_STATE (nothing queued).  out_n_reports (n entries, may be NULL)
  * receives each store's record count.  A store whose report segments overflow is
  * grown and the whole batch repeated (unless GSS_TEST_NO_REGROW: then
  * GSS_ERR_REPORT_OVERFLOW, with exact counts). */

@@ -458,6 +458,9 @@ extern "C" gss_status gss_batch_test(gss_batch *b, uint32_t flags, uint64_t *out
     GSS_BATCH_BEGIN(b)
     const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_REGROW | GSS_TEST_GRAPH;
     GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "flag not supported by gss_batch_test");
+    // a member's asynchronous test would have its report segments overwritten
+    for (const Ctx *c : b_->ctxs)
+        GSS_REQUIRE(!c->pending, GSS_ERR_STATE, "a member context has a test in flight (call gss_test_wait)");
     bool grown = false;
     bool overflow = run_once(*b_, flags, grown);
     if (overflow && grown) overflow = run_once(*b_, flags, grown);

@@ -181,6 +181,7 @@ struct Ctx {
 
     uint64_t *dense = nullptr;
     uint64_t dense_rows = 0;
+    uint64_t dense_ids = 0;  // ids issued when the last dense test ran: the rows it wrote
 
     // staging for uploads (device) and pinned host staging
     void *dstage = nullptr;

@@ -192,6 +192,7 @@ static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
             c.dense_rows = want;
         }
         launch_fill_u64(c, c.dense, c.dense_rows * c.W, 0);
+        c.dense_ids = c.id_loc.size();
     }
     uint64_t act = 0;
     for (uint64_t x : c.h_active) act += __builtin_popcountll(x);
@@ -386,6 +387,10 @@ extern "C" gss_status gss_fetch_masks(gss_ctx *ctx, const uint32_t *ids, uint32_
     std::vector<uint32_t> q(n);
     for (uint32_t i = 0; i < n; ++i) {
         GSS_REQUIRE(ids[i] < c.id_loc.size(), GSS_ERR_UNKNOWN_ID, "clause id " + std::to_string(ids[i]) + " never issued");
+        // the dense rows cover the ids issued when the test ran; a clause added
+        // since has no row (and may lie beyond the buffer)
+        GSS_REQUIRE(ids[i] < c.dense_ids, GSS_ERR_STATE,
+                    "clause id " + std::to_string(ids[i]) + " was added after the last dense test");
         q[i] = c.id_loc[ids[i]] == kNoLoc ? kDeadId : ids[i];
     }
     const size_t ids_bytes = ((size_t)n * 4 + 255) / 256 * 256;

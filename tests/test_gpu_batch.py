@@ -159,3 +159,24 @@ def test_batch_with_queued_deltas_and_their_errors():
         _check_all(items, counts)
     for it in items:
         it[1].close()
+
+
+def test_batch_refuses_a_member_with_an_async_test_in_flight():
+    """The batched test would overwrite the report segments of a member whose own
+    asynchronous test is still pending: it is refused before anything is queued,
+    and the member's test completes with its own records."""
+    _, items = _make(7)
+    w, ctx, vals = items[1]
+    with gss.Batch([it[1] for it in items]) as b:
+        ctx.test_async(0)
+        with pytest.raises(gss.GssError) as e:
+            b.test(0)
+        assert e.value.code == gss.GSS_ERR_STATE
+        n = ctx.test_wait()
+        got = _dense(ctx, w.n_clauses)
+        assert int(np.count_nonzero(got)) == int(n)
+        want = oracle.masks(w.lits, w.offsets, vals)
+        assert np.array_equal(got, want), mismatch_summary(got, want)
+        counts = b.test(0)
+        _check_all(items, counts)
+

@@ -48,6 +48,31 @@ def test_tiny_dense_output():
     _check(got, oracle.masks(w.lits, w.offsets, w.values))
 
 
+def test_fetch_masks_of_a_clause_added_after_the_dense_test():
+    """A dense test writes rows for the ids issued at that moment; a clause added
+    afterwards has no row, and asking for it is a state error raised on the host
+    (nothing is read from the device), however many ids the buffer's slack holds."""
+    w = gen.tiny(2, n_clauses=3000, n_vars=300)
+    with new_context(w.n_vars, 64) as ctx:
+        ids = ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, w.values)
+        assert ctx.test(gss.GSS_TEST_DENSE) == 0
+        before = ctx.fetch_masks(ids)
+        new = ctx.add_clauses(np.array([1, -2, 3], np.int32), np.array([0, 3], np.int64))
+        with pytest.raises(gss.GssError) as e:
+            ctx.fetch_masks(new)
+        assert e.value.code == gss.GSS_ERR_STATE
+        with pytest.raises(gss.GssError) as e:
+            ctx.fetch_masks(np.array([0, int(new[0])], np.uint32))
+        assert e.value.code == gss.GSS_ERR_STATE
+        # the rows of the earlier ids are still there, and a new dense test covers the new id
+        _check(ctx.fetch_masks(ids), before)
+        assert ctx.test(gss.GSS_TEST_DENSE) == 0
+        lits = np.concatenate([w.lits, np.array([1, -2, 3], np.int32)])
+        offsets = np.concatenate([w.offsets, [w.offsets[-1] + 3]]).astype(np.int64)
+        _check(ctx.fetch_masks(np.arange(len(offsets) - 1, dtype=np.uint32)), oracle.masks(lits, offsets, w.values))
+
+
 # ---------------------------------------------------------------------------
 # every lanes-per-clause width, partial slot ranges, several tiles + ragged tails
 # ---------------------------------------------------------------------------

@@ -59,9 +59,10 @@ def test_golden_examples(name):
     c_masks = {m: oracle.masks(lits, offsets, values, mode=m) for m in ("falsified", "trigger")}
     for i, (clause, expect) in enumerate(g["clauses"]):
         for key, want in expect.items():
-            if key == "trigger_aggregate":
+            if key in ("trigger_aggregate", "falsified_aggregate"):
                 G = oracle.py_aggregate(asg, {abs(l) for l in clause})
-                assert [int(oracle.py_trigger_aggregate(clause, G))] == want, (name, clause)
+                fn = oracle.py_trigger_aggregate if key == "trigger_aggregate" else oracle.py_falsified_aggregate
+                assert [int(fn(clause, G))] == want, (name, clause, key)
                 continue
             py = oracle.py_trigger if key == "trigger" else oracle.py_falsified
             assert [int(py(clause, a)) for a in asg] == want, (name, clause, key, "python")
@@ -267,6 +268,68 @@ def test_theorem1_individual_implies_aggregate(inst, n_groups):
         for gi, group in enumerate(groups):
             mask = sum(1 << j for j, a in enumerate(group) if one(clause, a))
             assert got.get(gi, 0) == mask
+
+
+# ---------------------------------------------------------------------------
+# aggregate tests (Section 4.2, Definition 7) by enumeration of choices
+# ---------------------------------------------------------------------------
+
+_SUBSETS = [frozenset(s) for r in (1, 2, 3) for s in itertools.combinations((T, F, U), r)]
+
+
+def _choices(G, vars_):
+    """Every assignment that takes, for each variable, one value of its aggregate."""
+    for vals in itertools.product(*(sorted(G[v]) for v in vars_)):
+        yield dict(zip(vars_, vals))
+
+
+def _clauses_over(vars_, max_len):
+    """Every clause of 1..max_len literals over the variables (repeats allowed)."""
+    lits = [l for v in vars_ for l in (v, -v)]
+    for n in range(1, max_len + 1):
+        yield from itertools.combinations_with_replacement(lits, n)
+
+
+def test_aggregate_tests_by_enumeration():
+    """For a clause whose variables are distinct, the aggregate test is positive
+    exactly when some assignment drawing each variable's value from its aggregate
+    is positive: a literal that may be F can be made F independently of the
+    others.  For any clause (repeats included) each literal is looked at on its
+    own: the falsified half is positive exactly when every literal is F under
+    some such assignment, and the trigger test exactly when every literal is F
+    or U under some assignment and at most one literal is F under none."""
+    for n_vars in (1, 2, 3):
+        vars_ = list(range(1, n_vars + 1))
+        choices_by_G = {}
+        for gs in itertools.product(_SUBSETS, repeat=n_vars):
+            G = dict(zip(vars_, gs))
+            choices_by_G[gs] = (G, list(_choices(G, vars_)))
+        for clause in _clauses_over(vars_, 3):
+            distinct = len({abs(l) for l in clause}) == len(clause)
+            for G, choices in choices_by_G.values():
+                fa = oracle.py_falsified_aggregate(clause, G)
+                ta = oracle.py_trigger_aggregate(clause, G)
+                if distinct:
+                    assert fa == any(oracle.py_falsified(clause, a) for a in choices), (clause, G)
+                    assert ta == any(oracle.py_trigger(clause, a) for a in choices), (clause, G)
+                vals = [[oracle.py_literal_value(a, l) for a in choices] for l in clause]
+                assert fa == all(F in v for v in vals), (clause, G)
+                not_f = sum(F not in v for v in vals)
+                assert ta == (all((F in v) or (U in v) for v in vals) and not_f <= 1), (clause, G)
+
+
+def test_aggregate_of_a_group_is_tight():
+    """Every aggregate assignment over distinct variables is the aggregate of the
+    group of all its choices, and for such a group the aggregate test is positive
+    exactly when some member of the group is (the converse of Theorem 1 fails
+    only across members, as Example 5 shows, never within one member)."""
+    vars_ = [1, 2]
+    for gs in itertools.product(_SUBSETS, repeat=2):
+        G = dict(zip(vars_, gs))
+        group = list(_choices(G, vars_))
+        assert oracle.py_aggregate(group, vars_) == G
+        for clause in ([1, 2], [1, -2], [-1, -2], [1], [-2]):
+            assert oracle.py_falsified_aggregate(clause, G) == any(oracle.py_falsified(clause, a) for a in group)
 
 
 # ---------------------------------------------------------------------------

@@ -1,7 +1,8 @@
 """Pins of the learned-priority oracle (CPU): the gradient against central
 finite differences and against torch's autograd in float64, closed forms of the
-network and of the loss, the first Adam step in closed form, and the feature and
-schedule definitions on hand-checked cases."""
+network and of the loss, the first two Adam steps in closed form and five steps
+against torch.optim.Adam, and the feature and schedule definitions on
+hand-checked cases."""
 import numpy as np
 import pytest
 
@@ -81,6 +82,53 @@ def test_first_adam_step_closed_form():
     # bias-corrected moments of one step are g and g^2
     np.testing.assert_allclose(theta, params - lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
     assert losses.shape == (1,)
+
+
+def test_two_adam_steps_closed_form():
+    """Two steps with unequal moment decays: after gradients g1 then g2 the
+    moments are m = b1 (1 - b1) g1 + (1 - b1) g2 and v = b2 (1 - b2) g1^2 +
+    (1 - b2) g2^2, divided by 1 - b1^2 and 1 - b2^2 before the step.  Swapping
+    the two decays changes the result, unlike the first step."""
+    params, x, y = _random_problem(5)
+    lr, b1, b2, eps = 3e-3, 0.8, 0.95, 1e-7
+    idx = [np.arange(0, 12), np.arange(12, 24)]
+    _, g1 = P.loss_grad(params, x[idx[0]], y[idx[0]])
+    theta1 = params - lr * g1 / (np.abs(g1) + eps)
+    _, g2 = P.loss_grad(theta1, x[idx[1]], y[idx[1]])
+    m = (b1 * (1 - b1) * g1 + (1 - b1) * g2) / (1 - b1 ** 2)
+    v = (b2 * (1 - b2) * g1 ** 2 + (1 - b2) * g2 ** 2) / (1 - b2 ** 2)
+    want = theta1 - lr * m / (np.sqrt(v) + eps)
+    got, losses = P.adam(params, x, y, idx, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-15)
+    assert losses.shape == (2,)
+    swapped, _ = P.adam(params, x, y, idx, lr=lr, beta1=b2, beta2=b1, eps=eps)
+    assert np.max(np.abs(swapped - want)) > 1e-6
+
+
+def test_adam_matches_torch_optim_over_several_steps():
+    """Five minibatch steps with non-default decays against torch.optim.Adam in
+    float64, the gradient of each step taken by torch's autograd."""
+    torch = pytest.importorskip("torch")
+    params, x, y = _random_problem(6, n=40)
+    lr, b1, b2, eps = 5e-3, 0.7, 0.9, 1e-6
+    batches = [np.arange(i, 40, 5) for i in range(5)]
+    got, losses = P.adam(params, x, y, batches, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    t = {k: torch.tensor(v.copy(), dtype=torch.float64, requires_grad=True) for k, v in P.unpack(params).items()}
+    opt = torch.optim.Adam(list(t.values()), lr=lr, betas=(b1, b2), eps=eps)
+    xt, yt = torch.tensor(x), torch.tensor(y)
+    want_losses = []
+    for idx in batches:
+        opt.zero_grad()
+        h1 = torch.relu(xt[idx] @ t["W1"] + t["b1"])
+        h2 = torch.relu(h1 @ t["W2"] + t["b2"])
+        z3 = h2 @ t["w3"] + t["b3"][0]
+        lt = torch.nn.functional.binary_cross_entropy_with_logits(z3, yt[idx])
+        lt.backward()
+        want_losses.append(lt.item())
+        opt.step()
+    want = P.pack({k: v.detach().numpy() for k, v in t.items()})
+    np.testing.assert_allclose(losses, want_losses, rtol=1e-12)
+    np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-12)
 
 
 def test_features_by_hand():
