@@ -56,14 +56,14 @@ def make_workload(args):
 
 
 def stage_rounds(w, n_rounds, seed, torch):
-    """Per round, the flipped variables and their new values (var-major), on the GPU."""
+    """Per round, the flipped variables and their new values (var-major), on the
+    GPU: n_rounds distinct rounds, each applied on top of the previous one."""
     from paper_2012_03119_amd import gen
-    vals = w.values.copy()
+    vm = np.ascontiguousarray(w.values.T)  # var-major: a round's delta is a set of rows
     rounds = []
-    for flip in gen.flip_rounds(seed + 1000, w.n_vars, n_rounds + 1):
-        gen.apply_flips(vals, flip)
-        delta = np.ascontiguousarray(vals[:, flip - 1].T)
-        rounds.append((flip.astype(np.uint32), torch.from_numpy(delta).cuda()))
+    for flip in gen.flip_rounds(seed + 1000, w.n_vars, n_rounds + 1):  # rounds 1..n_rounds
+        vm[flip - 1] = -vm[flip - 1]
+        rounds.append((flip.astype(np.uint32), torch.from_numpy(np.ascontiguousarray(vm[flip - 1])).cuda()))
     return rounds
 
 
@@ -580,7 +580,8 @@ def main():
     w, desc = make_workload(args)
     log(f"workload ready in {time.perf_counter() - t0:.1f} s: {w.n_clauses} clauses, {len(w.lits)} literals")
     need_rounds = args.warmup + args.steps if args.workload == "paper" else 0
-    rounds = stage_rounds(w, min(need_rounds, 19), args.seed, torch) if need_rounds else []
+    # every step applies a round of its own: nothing is recycled
+    rounds = stage_rounds(w, need_rounds, args.seed, torch) if need_rounds else []
 
     flags = 0
     if args.no_early_exit:
@@ -607,7 +608,7 @@ def main():
     # applies it while the host collects test i's count and queues test i+1.
     def queue_delta(i):
         if rounds:
-            vs, delta = rounds[i % len(rounds)]
+            vs, delta = rounds[i]
             ctx.set_var_values_async(0, vs, delta)
 
     def run_steps(first, n):

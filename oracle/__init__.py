@@ -23,6 +23,8 @@ Definitions followed (GpuShareSat):
 * Section 4.3 (the group-testing procedure): test the aggregate of each group
   first and test the individual assignments of a group only where the aggregate
   test is positive.
+* Section 7 (future work, aggregates of aggregates): the same procedure one
+  level up, on the aggregate of several groups' aggregates.
 
 Every function here is pinned by ``tests/test_oracle_pins.py`` against the
 paper's worked examples, brute force over all partial assignments of small
@@ -257,6 +259,45 @@ def py_group_test(clause: Sequence[int], groups: Sequence[Sequence[Mapping[int, 
                 mask |= 1 << j
         if mask:
             out.append((gi, mask))
+    return out
+
+
+def py_aggregate_of_aggregates(aggregates: Sequence[Mapping[int, frozenset]]) -> Dict[int, frozenset]:
+    """Section 7 (future work): the aggregate of several aggregate assignments
+    takes, per variable, every value any of them allows -- the aggregate
+    (Definition 6) of all the assignments of their groups together."""
+    out: Dict[int, frozenset] = {}
+    for G in aggregates:
+        for v, g in G.items():
+            out[v] = out.get(v, frozenset()) | g
+    return out
+
+
+def py_group_test_levels(clause: Sequence[int], super_groups: Sequence[Sequence[Sequence[Mapping[int, object]]]],
+                         mode: str = "trigger") -> List[Tuple[int, int, int]]:
+    """Group testing one level up (Section 4.3 applied to aggregates, as Section 7
+    proposes): a super-group is a list of groups of assignments.  Test the clause
+    on the aggregate of each super-group's group aggregates; where that is
+    positive, on each group's aggregate; where that is positive, on the group's
+    assignments one by one.  Reports (super-group, group, mask) for every group
+    with a positive assignment."""
+    agg_test = {"trigger": py_trigger_aggregate, "falsified": py_falsified_aggregate}[mode]
+    one_test = {"trigger": py_trigger, "falsified": py_falsified}[mode]
+    vars_ = {abs(l) for l in clause}
+    out = []
+    for si, groups in enumerate(super_groups):
+        aggs = [py_aggregate(group, vars_) for group in groups]
+        if not aggs or not agg_test(clause, py_aggregate_of_aggregates(aggs)):
+            continue
+        for gi, (group, G) in enumerate(zip(groups, aggs)):
+            if not agg_test(clause, G):
+                continue
+            mask = 0
+            for j, a in enumerate(group):
+                if one_test(clause, a):
+                    mask |= 1 << j
+            if mask:
+                out.append((si, gi, mask))
     return out
 
 

@@ -417,6 +417,7 @@ extern "C" gss_status gss_batch_create(gss_ctx *const *ctxs, uint32_t n, gss_bat
         for (Ctx *c : b->ctxs) {
             GSS_REQUIRE(c->device == c0.device, GSS_ERR_INVALID_ARG, "contexts on different devices");
             GSS_REQUIRE(c->stream == c0.stream, GSS_ERR_INVALID_ARG, "contexts on different streams");
+            GSS_REQUIRE(c->G == 1, GSS_ERR_INVALID_ARG, "a batch takes contexts of at most 4096 slots");
         }
         b->d_stores = (StoreDesc *)c0.dalloc((size_t)n * sizeof(StoreDesc));
         b->d_descs = (BucketDesc *)c0.dalloc((size_t)n * kMaxBuckets * sizeof(BucketDesc));

@@ -293,6 +293,8 @@ static void destroy_ctx(Ctx *c) {
     c->dfree(c->planes);
     c->dfree(c->agg);
     c->dfree(c->aggu);
+    c->dfree(c->sagg);
+    c->dfree(c->saggu);
     c->dfree(c->var_bits);
     c->dfree(c->active);
     c->dfree(c->reports);
@@ -329,8 +331,8 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         g_create_error = "num_vars must be in 1..2^30";
         return GSS_ERR_INVALID_ARG;
     }
-    if (cfg->max_slots < 64 || cfg->max_slots > 4096 || cfg->max_slots % 64 != 0) {
-        g_create_error = "max_slots must be a multiple of 64 in 64..4096";
+    if (cfg->max_slots < 64 || cfg->max_slots > kMaxSlots || cfg->max_slots % 64 != 0) {
+        g_create_error = "max_slots must be a multiple of 64 in 64.." + std::to_string(kMaxSlots);
         return GSS_ERR_INVALID_ARG;
     }
     if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) {
@@ -352,26 +354,37 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         c->W = cfg->max_slots / 64;
         c->RW = 1;
         while (c->RW < c->W) c->RW <<= 1;
-        c->LPC = c->RW <= 4 ? 1 : c->RW / 4;  // one lane per 32-byte sector of a row
+        c->RWc = std::min(c->RW, kChunkWords);
+        c->G = c->RW / c->RWc;
+        c->LPC = c->RWc <= 4 ? 1 : c->RWc / 4;  // one lane per 32-byte sector of a row's chunk
         c->T = 64 / c->LPC;
-        // the test kernel addresses the plane table with 32-bit byte offsets
-        if (2ull * ((uint64_t)cfg->num_vars + 1) * c->RW * 8 >= (1ull << 32))
-            throw Error(GSS_ERR_INVALID_ARG, "num_vars x max_slots too large: the plane table must stay under 4 GiB");
-        // LDS staging: rows of variables 0..hot_vars, at most 64 KiB per workgroup
-        uint64_t max_rows = 65536 / (8ull * c->RW);
-        uint64_t rows = cfg->hot_vars ? 2ull * ((uint64_t)cfg->hot_vars + 1) : 0;
+        const uint64_t n_rows = 2ull * ((uint64_t)cfg->num_vars + 1);
+        c->n_rows = n_rows;
+        c->chunk_elems = n_rows * c->RWc;
+        // a one-chunk table is addressed with 32-bit byte offsets by the test kernel
+        if (c->G == 1 && n_rows * c->RW * 8 >= (1ull << 32))
+            throw Error(GSS_ERR_INVALID_ARG, "num_vars x max_slots too large: a plane table of at most 4096 slots "
+                                             "must stay under 4 GiB");
+        // LDS staging: rows of variables 0..hot_vars, at most 64 KiB per workgroup (one chunk only)
+        uint64_t max_rows = 65536 / (8ull * c->RWc);
+        uint64_t rows = cfg->hot_vars && c->G == 1 ? 2ull * ((uint64_t)cfg->hot_vars + 1) : 0;
         if (rows > max_rows) rows = max_rows & ~1ull;
-        if (rows > 2ull * ((uint64_t)cfg->num_vars + 1)) rows = 2ull * ((uint64_t)cfg->num_vars + 1);
+        if (rows > n_rows) rows = n_rows;
         c->hot_rows = (uint32_t)rows;
         for (int b = 0; b < kMaxBuckets; ++b) c->buckets[b].stride_log2 = (uint32_t)b;
 
-        const uint64_t n_rows = 2ull * ((uint64_t)cfg->num_vars + 1);
         c->planes = (uint64_t *)c->dalloc(n_rows * c->RW * sizeof(uint64_t));
         launch_fill_u64(*c, c->planes, n_rows * c->RW, 0);
-        launch_fill_u64(*c, c->planes, c->RW, ~0ull);  // row 0: always F
-        c->agg = c->dalloc(n_rows * agg_elem_bytes(c->RW));
-        launch_fill_u32(*c, (uint32_t *)c->agg, (n_rows * agg_elem_bytes(c->RW) + 3) / 4, 0);
+        for (uint32_t g = 0; g < c->G; ++g)  // row 0 of every chunk: always F
+            launch_fill_u64(*c, c->planes + g * c->chunk_elems, c->RWc, ~0ull);
+        const uint64_t agg_bytes = (uint64_t)c->G * n_rows * agg_elem_bytes(c->RWc);
+        c->agg = c->dalloc(agg_bytes);
+        launch_fill_u32(*c, (uint32_t *)c->agg, (agg_bytes + 3) / 4, 0);
         agg_rebuild(*c, 0, 2);
+        if (c->G > 1) {
+            c->sagg = (uint64_t *)c->dalloc(n_rows * 8);
+            launch_fill_u64(*c, c->sagg, n_rows, 0);
+        }
         c->active = (uint64_t *)c->dalloc(c->W * sizeof(uint64_t));
         launch_fill_u64(*c, c->active, c->W, 0);
         c->h_active.assign(c->W, 0);

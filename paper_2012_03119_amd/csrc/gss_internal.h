@@ -50,6 +50,18 @@ __host__ __device__ inline uint32_t lit_code(int32_t lit) {
     return lit > 0 ? 2u * (uint32_t)lit : 2u * (uint32_t)(-lit) + 1u;
 }
 
+// Plane rows wider than 64 words (4096 slots) are stored in chunks of 64 words:
+// chunk g holds words [64g, 64g + 64) of every row, one row after the other, so
+// that every chunk has the layout of a 64-word table.  A chunk's slots form a
+// super-group (the aggregate of up to 64 word aggregates).  With at most 64
+// words there is one chunk and word w of row r sits at r * RW + w.
+constexpr uint32_t kChunkWords = 64;
+constexpr uint32_t kMaxSlots = 64u * 64u * 64u;  // 64 super-groups of 64 words
+
+__host__ __device__ inline uint64_t plane_index(uint64_t row, uint32_t w, uint32_t RWc, uint64_t chunk_elems) {
+    return (uint64_t)(w / kChunkWords) * chunk_elems + row * RWc + (w % kChunkWords);
+}
+
 constexpr int kMaxBuckets = 17;              // length classes 4, 8, ..., 65536 (classes 0-1 unused)
 constexpr int kMinClass = 2;                 // strides start at 4 codes: one 16-byte load
 constexpr uint32_t kMaxClauseLen = 65536;
@@ -91,17 +103,23 @@ struct TestArgs {
     BucketDesc b[kMaxBuckets];
     uint32_t n_buckets;
     uint32_t n_tiles;
-    const uint64_t *planes;   // [2 * (num_vars + 1)][RW], RW = lanes per clause >= W
+    const uint64_t *planes;   // [G][2 * (num_vars + 1)][RWc], RWc = min(RW, 64), RW = lanes per clause >= W
     const uint64_t *active;   // [W]
     uint32_t W;
+    uint32_t G;               // chunks (super-groups) of a plane row: 1, or RW / 64
+    uint64_t chunk_elems;     // words of one chunk: 2 * (num_vars + 1) * RWc
     uint32_t hot_rows;        // rows [0, hot_rows) are staged in LDS (0 = off)
     gss_report *reports;      // n_waves segments of seg_cap records, one per wavefront
     uint32_t *seg_counts;     // [n_waves]: records produced by each wavefront (beyond seg_cap: counted only)
     uint32_t seg_cap;
     uint64_t *dense;          // GSS_TEST_DENSE: [n_ids][W]
     uint32_t sched_run;       // schedule: a low-priority clause is tested when (sched_run + id) % 4 == 0
-    const void *agg;          // aggregate bits per row (element of 2, 4 or 8 bytes by RW); null: no pre-test
-    const void *aggu;         // trigger mode: per variable, bit w = word w has an active slot where it is U
+    const void *agg;          // aggregate bits per row (element of 2, 4 or 8 bytes by RWc; [G][rows]); null: no pre-test
+    const void *aggu;         // trigger mode: per variable, bit w = word w has an active slot where it is U ([G][vars])
+    const uint64_t *sagg;     // G > 1: per row, bit g = the row's literal is F in some slot of super-group g
+    const uint64_t *saggu;    // G > 1, trigger mode: per variable, bit g = U in some active slot of super-group g
+    uint64_t n_rows;          // rows of the plane table (the stride of the aggregate chunks)
+    uint64_t gmask;           // super-groups holding an active slot (bit g: words 64g .. 64g + 63)
 };
 
 // ---------------------------------------------------------------------------
@@ -133,7 +151,11 @@ struct Ctx {
     bool own_stream = false;
     uint32_t W = 0;     // 64-slot words in use per plane row
     uint32_t RW = 0;    // stored words per plane row (power of two >= W; words >= W stay zero)
-    uint32_t LPC = 0;   // lanes per clause in the test kernel (RW / words per lane)
+    uint32_t RWc = 0;   // words of a row in one chunk: min(RW, 64)
+    uint32_t G = 1;     // chunks (super-groups) of a row: RW / RWc
+    uint64_t n_rows = 0;       // plane rows: 2 * (num_vars + 1)
+    uint64_t chunk_elems = 0;  // words of one chunk: n_rows * RWc
+    uint32_t LPC = 0;   // lanes per clause in the test kernel (RWc / words per lane)
     uint32_t T = 0;     // clauses per tile = 64 / LPC
     uint32_t hot_rows = 0;
 
@@ -145,6 +167,10 @@ struct Ctx {
     bool agg_valid = true;  // false after bulk plane updates: rebuilt by the next aggregate test
     void *aggu = nullptr;   // per variable: bit w set when some active slot of word w has it U
     bool aggu_valid = false;
+    uint64_t *sagg = nullptr;   // G > 1: per row, one bit per super-group (from agg)
+    uint64_t *saggu = nullptr;  // G > 1: per variable, one bit per super-group (from aggu)
+    bool sagg_valid = false;    // sagg reflects agg
+    bool saggu_valid = false;   // saggu reflects aggu
     uint64_t *active = nullptr;
     std::vector<uint64_t> h_active;
     std::vector<uint64_t> var_seen;  // scratch bitmap for argument checks (kept all-zero)
@@ -270,12 +296,15 @@ __device__ inline bool values_invalid(const int8_t *v, uint64_t n, uint64_t tid,
     return found != 0;
 }
 
-// Bytes of one row's aggregate bits: 2 up to 16 words per row, 4 up to 32, else 8.
-inline uint32_t agg_elem_bytes(uint32_t RW) { return RW <= 16 ? 2u : RW <= 32 ? 4u : 8u; }
-// recomputes the aggregate bits of rows [lo, hi)
+// Bytes of one row's aggregate bits in one chunk: 2 up to 16 words, 4 up to 32, else 8.
+inline uint32_t agg_elem_bytes(uint32_t RWc) { return RWc <= 16 ? 2u : RWc <= 32 ? 4u : 8u; }
+// recomputes the aggregate bits of rows [lo, hi) in every chunk
 void agg_rebuild(Ctx &c, uint64_t lo, uint64_t hi);
 // recomputes the per-variable U bits (trigger-mode aggregates) of every variable
 void aggu_rebuild(Ctx &c);
+// G > 1: recomputes the super-group bits from the word bits (sagg, and saggu when
+// the trigger-mode bits are wanted)
+void super_rebuild(Ctx &c, bool with_u);
 
 // kernels / launchers (defined in the .hip files)
 void launch_fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t value);

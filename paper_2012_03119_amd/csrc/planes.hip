@@ -16,72 +16,121 @@
 
 namespace gss {
 
-// ---- aggregate bits (Section 4): per row, bit w = some slot of word w has the
-//      row's literal F.  Packed word deltas keep them in step; bulk updates
-//      (full sets, var-major deltas, cleared slots) mark them stale, and the next
-//      aggregate test rebuilds them.
+// ---- aggregate bits (Section 4): per row and chunk, bit w = some slot of word
+//      w of the chunk has the row's literal F (element g * n_rows + row).  Packed
+//      word deltas keep them in step; bulk updates (full sets, var-major deltas,
+//      cleared slots) mark them stale, and the next aggregate test rebuilds them.
+//      Above them, with more than one chunk, one bit per row and chunk (the
+//      super-group: the aggregate of the chunk's word aggregates), rebuilt from
+//      the word bits before an aggregate test when they changed.
 
-__device__ inline uint64_t agg_get(const void *agg, uint32_t RW, uint64_t row) {
-    if (RW <= 16) return reinterpret_cast<const uint16_t *>(agg)[row];
-    if (RW <= 32) return reinterpret_cast<const uint32_t *>(agg)[row];
-    return reinterpret_cast<const uint64_t *>(agg)[row];
+__device__ inline uint64_t agg_get(const void *agg, uint32_t RWc, uint64_t i) {
+    if (RWc <= 16) return reinterpret_cast<const uint16_t *>(agg)[i];
+    if (RWc <= 32) return reinterpret_cast<const uint32_t *>(agg)[i];
+    return reinterpret_cast<const uint64_t *>(agg)[i];
 }
 
-__device__ inline void agg_put(void *agg, uint32_t RW, uint64_t row, uint64_t bits) {
-    if (RW <= 16)
-        reinterpret_cast<uint16_t *>(agg)[row] = (uint16_t)bits;
-    else if (RW <= 32)
-        reinterpret_cast<uint32_t *>(agg)[row] = (uint32_t)bits;
+__device__ inline void agg_put(void *agg, uint32_t RWc, uint64_t i, uint64_t bits) {
+    if (RWc <= 16)
+        reinterpret_cast<uint16_t *>(agg)[i] = (uint16_t)bits;
+    else if (RWc <= 32)
+        reinterpret_cast<uint32_t *>(agg)[i] = (uint32_t)bits;
     else
-        reinterpret_cast<uint64_t *>(agg)[row] = bits;
+        reinterpret_cast<uint64_t *>(agg)[i] = bits;
 }
 
-__device__ inline uint64_t row_nonzero_words(const uint64_t *planes, uint32_t RW, uint64_t row) {
+// bit w = word w of chunk g of the row is nonzero
+__device__ inline uint64_t row_nonzero_words(const uint64_t *planes, uint32_t RWc, uint64_t chunk, uint32_t g,
+                                             uint64_t row) {
+    const uint64_t *p = planes + g * chunk + row * RWc;
     uint64_t bits = 0;
-    for (uint32_t w = 0; w < RW; ++w) bits |= (uint64_t)(planes[row * RW + w] != 0) << w;
+    for (uint32_t w = 0; w < RWc; ++w) bits |= (uint64_t)(p[w] != 0) << w;
     return bits;
 }
 
-__global__ void k_agg_rows(const uint64_t *planes, uint32_t RW, void *agg, uint64_t lo, uint64_t hi) {
-    for (uint64_t r = lo + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < hi; r += (uint64_t)gridDim.x * blockDim.x)
-        agg_put(agg, RW, r, row_nonzero_words(planes, RW, r));
+// Thread per (chunk, row) of rows [lo, hi).  Aggregates are stored [G][n_rows].
+__global__ void k_agg_rows(const uint64_t *planes, uint32_t RWc, uint64_t chunk, uint32_t G, uint64_t n_rows, void *agg,
+                           uint64_t lo, uint64_t hi) {
+    const uint64_t span = hi - lo, total = span * G;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t g = (uint32_t)(x / span);
+        const uint64_t r = lo + x % span;
+        agg_put(agg, RWc, g * n_rows + r, row_nonzero_words(planes, RWc, chunk, g, r));
+    }
 }
 
 // Trigger-mode aggregate of each variable: bit w = some active slot of word w
-// has the variable U (neither row set there).
-__global__ void k_aggu_rows(const uint64_t *planes, uint32_t RW, const uint64_t *active, uint32_t W, void *aggu,
-                            uint64_t n_vars1) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n_vars1; v += (uint64_t)gridDim.x * blockDim.x) {
+// has the variable U (neither row set there); thread per (chunk, variable),
+// stored [G][n_vars + 1].
+__global__ void k_aggu_rows(const uint64_t *planes, uint32_t RWc, uint64_t chunk, uint32_t G, const uint64_t *active,
+                            uint32_t W, void *aggu, uint64_t n_vars1) {
+    const uint64_t total = n_vars1 * G;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t g = (uint32_t)(x / n_vars1);
+        const uint64_t v = x % n_vars1;
+        const uint64_t *pf = planes + g * chunk + (2 * v) * RWc, *pt = pf + RWc;
         uint64_t bits = 0;
-        for (uint32_t w = 0; w < RW; ++w) {
-            const uint64_t act = w < W ? active[w] : 0ull;
-            const uint64_t set = planes[(2 * v) * RW + w] | planes[(2 * v + 1) * RW + w];
-            bits |= (uint64_t)((set & act) != act) << w;
+        for (uint32_t w = 0; w < RWc; ++w) {
+            const uint32_t gw = g * RWc + w;
+            const uint64_t act = gw < W ? active[gw] : 0ull;
+            bits |= (uint64_t)(((pf[w] | pt[w]) & act) != act) << w;
         }
-        agg_put(aggu, RW, v, bits);
+        agg_put(aggu, RWc, g * n_vars1 + v, bits);
+    }
+}
+
+// Super-group bits (G > 1): bit g of out[i] = the 64-word aggregate in[g][i] is nonzero.
+__global__ void k_super_bits(const uint64_t *in, uint32_t G, uint64_t n, uint64_t *out) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t bits = 0;
+        for (uint32_t g = 0; g < G; ++g) bits |= (uint64_t)(in[g * n + i] != 0) << g;
+        out[i] = bits;
     }
 }
 
 void aggu_rebuild(Ctx &c) {
     const uint64_t n = (uint64_t)c.cfg.num_vars + 1;
-    if (!c.aggu) c.aggu = c.dalloc(n * agg_elem_bytes(c.RW));
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 65536));
-    hipLaunchKernelGGL(k_aggu_rows, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, c.active, c.W, c.aggu, n);
+    if (!c.aggu) c.aggu = c.dalloc((uint64_t)c.G * n * agg_elem_bytes(c.RWc));
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n * c.G + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_aggu_rows, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RWc, c.chunk_elems, c.G, c.active,
+                       c.W, c.aggu, n);
     GSS_HIP(hipGetLastError());
     c.aggu_valid = true;
+    c.saggu_valid = false;
 }
 
 void agg_rebuild(Ctx &c, uint64_t lo, uint64_t hi) {
     if (hi <= lo) return;
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((hi - lo + 255) / 256, 65536));
-    hipLaunchKernelGGL(k_agg_rows, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, c.agg, lo, hi);
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(((hi - lo) * c.G + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_agg_rows, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RWc, c.chunk_elems, c.G, c.n_rows,
+                       c.agg, lo, hi);
     GSS_HIP(hipGetLastError());
+    c.sagg_valid = false;
+}
+
+void super_rebuild(Ctx &c, bool with_u) {
+    if (c.G == 1) return;
+    if (!c.sagg_valid) {
+        hipLaunchKernelGGL(k_super_bits, dim3(fill_grid(c.n_rows)), dim3(256), 0, c.stream,
+                           (const uint64_t *)c.agg, c.G, c.n_rows, c.sagg);
+        GSS_HIP(hipGetLastError());
+        c.sagg_valid = true;
+    }
+    if (with_u && !c.saggu_valid) {
+        const uint64_t n = (uint64_t)c.cfg.num_vars + 1;
+        if (!c.saggu) c.saggu = (uint64_t *)c.dalloc(n * 8);
+        hipLaunchKernelGGL(k_super_bits, dim3(fill_grid(n)), dim3(256), 0, c.stream, (const uint64_t *)c.aggu, c.G, n,
+                           c.saggu);
+        GSS_HIP(hipGetLastError());
+        c.saggu_valid = true;
+    }
 }
 
 // Packs the slots of word w from a slot-major staging block.  One wavefront per
 // 64 variables; lane b reads slot 64*w + b.  Staging row r holds slot s_lo + r,
 // `pitch` bytes per row (a multiple of 64), byte v-1 = value of variable v.
-__global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RW, uint32_t w, uint32_t num_vars,
+__global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RWc, uint64_t chunk, uint32_t w,
+                                                  uint32_t num_vars,
                                                   const int8_t *stage, uint64_t pitch, uint32_t s_lo, uint32_t s_hi,
                                                   const uint32_t *bad) {
     if (*bad) return;  // the inputs failed validation: apply nothing
@@ -111,7 +160,7 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RW,
     }
     const uint32_t v = v0 + lane;
     if (v <= num_vars) {
-        const uint64_t r0 = (uint64_t)(2 * v) * RW + w, r1 = r0 + RW;
+        const uint64_t r0 = plane_index(2ull * v, w, RWc, chunk), r1 = r0 + RWc;
         if (sm != ~0ull) {
             f = (planes[r0] & ~sm) | (f & sm);
             t = (planes[r1] & ~sm) | (t & sm);
@@ -130,7 +179,8 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RW,
 // [n_vars][n_slots]; nw = words touched.
 // With clear_bits != null, the thread of each variable's first word also clears
 // the variable's word of the duplicate bitmap (left zero for the next check).
-__global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RW, const uint32_t *vars, uint32_t n_vars,
+__global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RWc, uint64_t chunk, const uint32_t *vars,
+                                                  uint32_t n_vars,
                                                   const int8_t *vals, uint32_t first, uint32_t n_slots, uint32_t nw,
                                                   const uint32_t *bad, uint32_t *clear_bits) {
     const uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -162,7 +212,7 @@ __global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RW,
             t |= (uint64_t)(x == 1) << (s - 64 * w);
         }
     }
-    const uint64_t r0 = (uint64_t)(2 * vars[i]) * RW + w, r1 = r0 + RW;
+    const uint64_t r0 = plane_index(2ull * vars[i], w, RWc, chunk), r1 = r0 + RWc;
     if (hi - lo != 64) {
         const uint64_t sm = ((1ull << (hi - lo)) - 1) << (lo - 64 * w);  // hi - lo < 64 here
         f = (planes[r0] & ~sm) | (f & sm);
@@ -175,23 +225,25 @@ __global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RW,
 // Packed delta: new plane words of listed variables in one 64-slot word.  Thread
 // per variable; f = slots where the variable is F, t = slots where it is T.
 // The variables of one launch are distinct, so each thread owns its two rows'
-// aggregate bits (bit `word`), updated in place.
-__global__ void k_set_words(uint64_t *planes, uint32_t RW, uint32_t word, const uint32_t *vars, const uint64_t *f,
-                            const uint64_t *t, uint32_t n, void *agg) {
+// aggregate bits (bit `word` of the word's chunk), updated in place.
+__global__ void k_set_words(uint64_t *planes, uint32_t RWc, uint64_t chunk, uint64_t n_rows, uint32_t word,
+                            const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n, void *agg) {
+    const uint64_t a_base = (uint64_t)(word / kChunkWords) * n_rows;
+    const uint64_t bit = 1ull << (word % kChunkWords);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint64_t row = 2ull * vars[i];
-        const uint64_t r0 = row * RW + word;
+        const uint64_t r0 = plane_index(row, word, RWc, chunk);
         planes[r0] = f[i];
-        planes[r0 + RW] = t[i];
-        const uint64_t bit = 1ull << word;
-        const uint64_t a0 = agg_get(agg, RW, row), a1 = agg_get(agg, RW, row + 1);
-        agg_put(agg, RW, row, f[i] ? (a0 | bit) : (a0 & ~bit));
-        agg_put(agg, RW, row + 1, t[i] ? (a1 | bit) : (a1 & ~bit));
+        planes[r0 + RWc] = t[i];
+        const uint64_t a0 = agg_get(agg, RWc, a_base + row), a1 = agg_get(agg, RWc, a_base + row + 1);
+        agg_put(agg, RWc, a_base + row, f[i] ? (a0 | bit) : (a0 & ~bit));
+        agg_put(agg, RWc, a_base + row + 1, t[i] ? (a1 | bit) : (a1 & ~bit));
     }
 }
 
 // Clears slots [first, first+n) in every row of real variables (rows >= 2).
-__global__ void k_clear_slots(uint64_t *planes, uint32_t RW, uint64_t n_rows, uint32_t first, uint32_t n_slots) {
+__global__ void k_clear_slots(uint64_t *planes, uint32_t RWc, uint64_t chunk, uint64_t n_rows, uint32_t first,
+                              uint32_t n_slots) {
     const uint32_t w_lo = first / 64, w_hi = (first + n_slots - 1) / 64, nw = w_hi - w_lo + 1;
     const uint64_t total = (n_rows - 2) * nw;
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
@@ -199,15 +251,17 @@ __global__ void k_clear_slots(uint64_t *planes, uint32_t RW, uint64_t n_rows, ui
         const uint32_t w = w_lo + (uint32_t)(x % nw);
         const uint32_t a = std::max(first, 64 * w), b = std::min(first + n_slots, 64 * w + 64);
         const uint64_t sm = (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1) << (a - 64 * w));
-        planes[row * RW + w] &= ~sm;
+        planes[plane_index(row, w, RWc, chunk)] &= ~sm;
     }
 }
 
 void launch_set_words(Ctx &c, uint32_t word, const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n) {
     if (n == 0) return;
     c.aggu_valid = false;
+    c.sagg_valid = false;
     const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, word, vars, f, t, n, c.agg);
+    hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RWc, c.chunk_elems, c.n_rows, word,
+                       vars, f, t, n, c.agg);
     GSS_HIP(hipGetLastError());
     c.mutations++;
 }
@@ -298,8 +352,8 @@ static void launch_set_vars(Ctx &c, const uint32_t *d_vars, uint32_t n_vars, con
                             uint32_t n_slots, const uint32_t *bad, uint32_t *clear_bits) {
     const uint32_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
     const uint64_t threads = (uint64_t)n_vars * nw;
-    hipLaunchKernelGGL(k_set_vars, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, c.stream, c.planes, c.RW,
-                       d_vars, n_vars, d_vals, first_slot, n_slots, nw, bad, clear_bits);
+    hipLaunchKernelGGL(k_set_vars, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, c.stream, c.planes, c.RWc,
+                       c.chunk_elems, d_vars, n_vars, d_vals, first_slot, n_slots, nw, bad, clear_bits);
     GSS_HIP(hipGetLastError());
 }
 
@@ -345,8 +399,8 @@ extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uin
         const int8_t *src = values + (uint64_t)(s_lo - first_slot) * V;
         GSS_HIP(hipMemcpy2DAsync(stage, pitch, src, V, V, s_hi - s_lo,
                                  dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.stream));
-        hipLaunchKernelGGL(k_pack_word, dim3((unsigned)((V + 63) / 64)), dim3(64), 0, c.stream, c.planes, c.RW, w,
-                           (uint32_t)V, stage, pitch, s_lo, s_hi, bad);
+        hipLaunchKernelGGL(k_pack_word, dim3((unsigned)((V + 63) / 64)), dim3(64), 0, c.stream, c.planes, c.RWc,
+                           c.chunk_elems, w, (uint32_t)V, stage, pitch, s_lo, s_hi, bad);
         GSS_HIP(hipGetLastError());
     }
     if (dev) check_flag(c);  // throws, having applied nothing, if a value was invalid
@@ -447,7 +501,8 @@ extern "C" gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_
     const uint64_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
     const uint64_t total = (n_rows - 2) * nw;
     const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
-    hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RW, n_rows, first_slot, n_slots);
+    hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RWc, c.chunk_elems, n_rows,
+                       first_slot, n_slots);
     GSS_HIP(hipGetLastError());
     c.agg_valid = false;
     c.aggu_valid = false;

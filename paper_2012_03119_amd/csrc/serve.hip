@@ -539,6 +539,7 @@ extern "C" gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cf
     Ctx &c = *c_;
     GSS_REQUIRE(cfg && out, GSS_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
+    GSS_REQUIRE(c.G == 1, GSS_ERR_INVALID_ARG, "a server takes a context of at most 4096 slots");
     GSS_REQUIRE(cfg->n_producers >= 1 && cfg->n_producers <= c.W, GSS_ERR_INVALID_ARG,
                 "n_producers must be in 1..max_slots/64 (one 64-slot word each)");
     const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_HOT | GSS_TEST_AGGREGATE;

@@ -9,6 +9,7 @@
 
 namespace gss {
 
+
 using KernelFn = void (*)(const BucketDesc *, const TestArgs, uint32_t, uint32_t);
 
 // row words RW (power of two) -> lanes per clause and words per lane (a lane
@@ -32,7 +33,12 @@ static KernelFn pick_mode(uint32_t rw, int mode, bool hot) {
     return hot ? pick_rw<1, true, AGG>(rw) : pick_rw<1, false, AGG>(rw);
 }
 
-static KernelFn pick_kernel(uint32_t rw, int mode, bool hot, bool agg) {
+// rw: words of a row in one chunk; wide: more than one chunk (no LDS staging then)
+static KernelFn pick_kernel(uint32_t rw, int mode, bool hot, bool agg, bool wide) {
+    if (wide) {
+        if (mode == 0) return agg ? k_test<16, 4, 0, false, true, true> : k_test<16, 4, 0, false, false, true>;
+        return agg ? k_test<16, 4, 1, false, true, true> : k_test<16, 4, 1, false, false, true>;
+    }
     return agg ? pick_mode<true>(rw, mode, hot) : pick_mode<false>(rw, mode, hot);
 }
 
@@ -75,6 +81,14 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     a.planes = c.planes;
     a.active = c.active;
     a.W = c.W;
+    a.G = c.G;
+    a.chunk_elems = c.chunk_elems;
+    a.n_rows = c.n_rows;
+    a.gmask = 0;
+    for (uint32_t w = 0; w < c.W; ++w)
+        if (c.h_active[w]) a.gmask |= 1ull << (w / kChunkWords);
+    a.sagg = nullptr;
+    a.saggu = nullptr;
     const bool hot = c.hot_rows > 0 && !(flags & GSS_TEST_NO_HOT);
     a.hot_rows = hot ? c.hot_rows : 0;
     a.reports = c.reports;
@@ -93,6 +107,11 @@ static Launch prepare(Ctx &c, uint32_t flags) {
             if (!c.aggu_valid) aggu_rebuild(c);
             a.aggu = c.aggu;
         }
+        if (c.G > 1) {  // the super-group bits above the word bits
+            super_rebuild(c, (flags & GSS_TEST_TRIGGER) != 0);
+            a.sagg = c.sagg;
+            a.saggu = c.saggu;
+        }
     }
     // the device copy stays valid while the store is unchanged (schedule bits may move: always upload then)
     if (nb && (sched || c.desc_version != c.version)) {
@@ -100,7 +119,7 @@ static Launch prepare(Ctx &c, uint32_t flags) {
         c.desc_version = sched ? ~0ull : c.version;
     }
     L.descs = (const BucketDesc *)c.d_desc;
-    L.fn = pick_kernel(c.RW, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot, a.agg != nullptr);
+    L.fn = pick_kernel(c.RWc, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot, a.agg != nullptr, c.G > 1);
     if (hot) L.lds = (size_t)a.hot_rows * c.RW * 8;
     // persistent: exactly as many workgroups as fit on the device at once
     if (c.occ_fn != (const void *)L.fn || c.occ_lds != L.lds) {  // the query costs host time: cache it

@@ -11,12 +11,12 @@ namespace gss {
 
 // Each wavefront walks the tiles t = wave, wave + N, ... (N wavefronts in the
 // grid) and prefetches the next tile's metadata and first codes while it tests
-// the current one.
-template <int LPC, int WPL, int MODE, bool HOT, bool AGG>
+// the current one.  WIDE: plane rows of more than 64 words (several chunks).
+template <int LPC, int WPL, int MODE, bool HOT, bool AGG, bool WIDE = false>
 __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDesc *__restrict__ descs,
                                                                    const TestArgs a, uint32_t early_exit,
                                                                    uint32_t dense) {
-    using Ts = Tester<LPC, WPL, MODE, HOT, AGG>;
+    using Ts = Tester<LPC, WPL, MODE, HOT, AGG, WIDE>;
     extern __shared__ uint64_t lds_rows[];
     if constexpr (HOT) {
         const uint32_t n = a.hot_rows * Ts::RW;
@@ -24,13 +24,15 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
         __syncthreads();
     }
     const uint32_t lane = threadIdx.x & 63;
-    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, a.sched_run, a.agg, a.aggu);
+    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, a.sched_run, a.agg, a.aggu, a.G, a.chunk_elems,
+                a.n_rows, a.sagg, a.saggu);
     const uint32_t waves_per_block = blockDim.x / 64;
     const uint32_t n_waves = gridDim.x * waves_per_block;
     // wave-uniform by construction; readfirstlane lets the compiler keep it in SGPRs
     const uint32_t wave = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * waves_per_block +
                                                          threadIdx.x / 64);
     gss_report *const seg = a.reports + (uint64_t)wave * a.seg_cap;
+    const uint32_t seg_cap = a.seg_cap;
     uint64_t *const dense_out = dense ? a.dense : nullptr;
     uint32_t produced = 0;  // records of this wavefront (uniform)
     uint32_t bi = 0;
@@ -43,7 +45,18 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
         const uint32_t tn = t + n_waves;
         typename Ts::Tile nxt;
         ts.open(descs, a.n_buckets, bi, tn < a.n_tiles ? tn : last, nxt);  // prefetch, unconditionally
-        produced = ts.run(cur, seg, a.seg_cap, produced, early_exit, dense_out);
+        if constexpr (!WIDE) {
+            produced = ts.run(cur, seg, seg_cap, produced, early_exit, dense_out);
+        } else {
+            // rows of more than 64 words: the tile is tested chunk by chunk, each
+            // chunk's 4096 slots a super-group; with the aggregate pre-test, first
+            // on the super-groups' aggregates, then only on the chunks where some
+            // clause of the tile can still be falsified (or trigger)
+            const uint64_t sup = AGG ? ts.super_mask(cur, a.gmask) : a.gmask;
+            for (uint32_t g = 0; g < a.G; ++g)
+                if (__ballot((sup >> g) & 1u))
+                    produced = ts.run(cur, seg, seg_cap, produced, early_exit, dense_out, g, sup);
+        }
         t = tn;
         cur = nxt;
     }

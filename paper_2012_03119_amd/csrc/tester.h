@@ -97,7 +97,7 @@ __device__ inline Words<WPL> load_words(const char *p) {
 
 // One store's clause test for one lane: LPC lanes per clause, WPL words per lane,
 // a plane row of RW = LPC * WPL words.  MODE 0 = falsified, 1 = trigger.
-template <int LPC, int WPL, int MODE, bool HOT, bool AGG = false>
+template <int LPC, int WPL, int MODE, bool HOT, bool AGG = false, bool WIDE = false>
 struct Tester {
     static constexpr uint32_t kGroup = kGroupOf<AGG>;
     static constexpr uint32_t T = 64 / LPC;                 // clauses per wavefront (and per tile)
@@ -119,39 +119,46 @@ struct Tester {
     };
 
     uint32_t j;    // clause of this lane within the tile
-    uint32_t w0;   // first word of this lane
+    uint32_t w0;   // first word of this lane within a chunk
     uint32_t W;    // words in use
     uint32_t hot_rows;
     uint32_t sched_run;
-    bool lane_ok;  // this lane owns at least one word in use
-    uint64_t act[WPL];
+    uint32_t G;    // chunks of a row (super-groups of 64 words); 1 up to 64 words
+    uint64_t act[WPL];  // active words of this lane in chunk 0
+    const uint64_t *active;
     const char *pbase;
+    uint64_t chunk_bytes;
     const uint64_t *lds;
-    const AggT *agg;   // AGG: per literal code, words with an F slot
-    const AggT *aggu;  // AGG in trigger mode: per variable, words with an active U slot
+    const AggT *agg;   // AGG: per chunk and literal code, words with an F slot ([G][n_rows])
+    const AggT *aggu;  // AGG in trigger mode: per chunk and variable, words with an active U slot
+    const uint64_t *sagg;   // G > 1: per code, super-groups with an F slot
+    const uint64_t *saggu;  // G > 1, trigger mode: per variable, super-groups with an active U slot
+    uint64_t n_rows;
 
-    __device__ Tester(uint32_t lane, const uint64_t *planes, const uint64_t *active, uint32_t W_, uint32_t hot_rows_,
-                      const uint64_t *lds_, uint32_t sched_run_, const void *agg_, const void *aggu_)
-        : j(lane / LPC), w0((lane % LPC) * WPL), W(W_), hot_rows(hot_rows_), sched_run(sched_run_), lds(lds_),
-          agg(static_cast<const AggT *>(agg_)), aggu(static_cast<const AggT *>(aggu_)) {
-        lane_ok = w0 < W;
+    __device__ Tester(uint32_t lane, const uint64_t *planes, const uint64_t *active_, uint32_t W_, uint32_t hot_rows_,
+                      const uint64_t *lds_, uint32_t sched_run_, const void *agg_, const void *aggu_, uint32_t G_ = 1,
+                      uint64_t chunk_elems = 0, uint64_t n_rows_ = 0, const uint64_t *sagg_ = nullptr,
+                      const uint64_t *saggu_ = nullptr)
+        : j(lane / LPC), w0((lane % LPC) * WPL), W(W_), hot_rows(hot_rows_), sched_run(sched_run_), G(G_),
+          active(active_), chunk_bytes(chunk_elems * 8), lds(lds_), agg(static_cast<const AggT *>(agg_)),
+          aggu(static_cast<const AggT *>(aggu_)), sagg(sagg_), saggu(saggu_), n_rows(n_rows_) {
 #pragma unroll
         for (int i = 0; i < WPL; ++i) act[i] = (w0 + i < W) ? active[w0 + i] : 0;
         pbase = reinterpret_cast<const char *>(planes) + w0 * 8;
     }
 
-    // This lane's words of plane row `code`.  Code 0 is the all-ones row, the
-    // identity of the AND: literals past a clause's end read it.
+    // This lane's words of plane row `code` in the chunk at pb.  Code 0 is the
+    // all-ones row, the identity of the AND: literals past a clause's end read it.
     // A hot row is read from LDS through the same generic load: the address is
     // chosen per lane, so a wavefront whose lanes mix hot and cold rows issues one
     // load instead of splitting into an LDS path and a global path.
-    __device__ Words<WPL> gather(uint32_t code) const {
+    __device__ Words<WPL> gather(const char *pb, uint32_t code) const {
+        // a one-chunk table stays under 4 GiB: 32-bit row offsets
+        const char *p = WIDE ? pb + ((uint64_t)code << ROW_SHIFT) : pb + (code << ROW_SHIFT);
         if constexpr (HOT) {
-            const char *p = code < hot_rows ? reinterpret_cast<const char *>(lds + code * RW + w0)
-                                            : pbase + (code << ROW_SHIFT);
-            return load_words<WPL>(p);
+            if (code < hot_rows) p = reinterpret_cast<const char *>(lds + code * RW + w0);
         }
-        return load_words<WPL>(pbase + (code << ROW_SHIFT));
+        return load_words<WPL>(p);
     }
 
     // Locates tile t (bi: bucket cursor, only ever advanced) and issues the loads
@@ -173,19 +180,66 @@ struct Tester {
                            : 0u;
     }
 
-    // Tests the clauses of an opened tile.  Records go to seg (capacity seg_cap)
-    // after the `produced` records already there; returns the new count.  With
-    // dense != nullptr, writes each clause's mask row there instead.
-    __device__ uint32_t run(const Tile &cur, gss_report *seg, uint32_t seg_cap, uint32_t produced, uint32_t early_exit,
-                            uint64_t *dense) const {
-        // a low-priority clause sits out the runs where (run + id) % 4 != 0
+    // The top level of the aggregate test (G > 1): for this lane's clause, the
+    // super-groups (chunks of 64 words) on whose aggregate the clause can be
+    // falsified (MODE 0: every literal F in some slot of the super-group) or
+    // trigger (MODE 1: the recurrence of Section 4.3 on canBeFalse and
+    // canBeUndef), among `groups`.  The lanes of a clause compute the same mask
+    // (their loads coincide); the wavefront stops reading literals once every
+    // clause's mask is zero.
+    __device__ uint64_t super_mask(const Tile &cur, uint64_t groups) const {
         const bool skip = ((cur.lowword >> cur.lowshift) & 1u) && ((sched_run + cur.meta.y) & 3u) != 0;
         const uint32_t len = skip ? 0u : cur.meta.x;
         const uint32_t S = 1u << cur.s_log2;
+        uint64_t af = len ? groups : 0ull, ou = 0;
+        uint4 c = cur.c0;
+        for (uint32_t k = 0;; k += 4) {
+            if (!__ballot(k < len && (af | ou) != 0)) break;
+            uint4 cn = make_uint4(0, 0, 0, 0);
+            if (k + 4 < S) {
+                const auto q = __builtin_amdgcn_raw_buffer_load_b128(cur.lits, cur.code_off + ((k + 4) >> 2) * (T * 16u),
+                                                                     0, 0);
+                cn = make_uint4(q[0], q[1], q[2], q[3]);
+            }
+            const uint32_t cs[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                if (k + u < len && (af | ou) != 0) {
+                    const uint64_t cf = sagg[cs[u]];
+                    if constexpr (MODE == 1) {
+                        const uint64_t cu = saggu[cs[u] >> 1];
+                        ou = (af & cu) | (ou & cf);
+                    }
+                    af &= cf;
+                }
+            }
+            c = cn;
+        }
+        return af | ou;
+    }
+
+    // Tests the clauses of an opened tile on chunk g of the rows.  Records go to
+    // seg (capacity seg_cap) after the `produced` records already there; returns
+    // the new count.  With dense != nullptr, writes each clause's mask row there
+    // instead.  sup: the clause's super-group mask (bit g clear: not tested).
+    __device__ uint32_t run(const Tile &cur, gss_report *seg, uint32_t seg_cap, uint32_t produced, uint32_t early_exit,
+                            uint64_t *dense, uint32_t g = 0, uint64_t sup = ~0ull) const {
+        // a low-priority clause sits out the runs where (run + id) % 4 != 0
+        const bool skip = ((cur.lowword >> cur.lowshift) & 1u) && ((sched_run + cur.meta.y) & 3u) != 0;
+        // chunk g: this lane's words g * RW + w0 .. (a clause whose super-group test
+        // was negative for g takes no part)
+        const uint32_t len = (skip || !((sup >> g) & 1u)) ? 0u : cur.meta.x;
+        const uint32_t S = 1u << cur.s_log2;
+        const uint32_t gw0 = WIDE ? g * RW + w0 : w0;
+        const bool lane_ok = gw0 < W;
+        const char *const pb = WIDE ? pbase + g * chunk_bytes : pbase;
+        const AggT *const ag = WIDE ? agg + g * n_rows : agg;
+        const AggT *const agu = WIDE ? aggu + g * (n_rows / 2) : aggu;
         uint64_t af[WPL], ou[WPL];  // allFalse, oneUndef (trigger mode)
 #pragma unroll
         for (int i = 0; i < WPL; ++i) {
-            af[i] = len ? act[i] : 0;
+            const uint64_t a = WIDE ? (gw0 + i < W ? active[gw0 + i] : 0ull) : act[i];
+            af[i] = len ? a : 0;
             ou[i] = 0;
         }
         // aggregate recurrence of the trigger test (Section 4.3), one bit per word of this lane
@@ -222,7 +276,7 @@ struct Tester {
 #pragma unroll
                         for (uint32_t u = 0; u < kGroup; ++u) {
                             const uint32_t code = (k + g0 + u < len) ? cs[g0 + u] : 0u;
-                            keep &= (uint32_t)(agg[code] >> w0);
+                            keep &= (uint32_t)(ag[code] >> w0);
                         }
 #pragma unroll
                         for (int i = 0; i < WPL; ++i)
@@ -237,7 +291,7 @@ struct Tester {
 #pragma unroll
                         for (uint32_t u = 0; u < kGroup; ++u) {
                             const uint32_t code = (k + g0 + u < len) ? cs[g0 + u] : 0u;
-                            const uint32_t cf = (uint32_t)(agg[code] >> w0), cu = (uint32_t)(aggu[code >> 1] >> w0);
+                            const uint32_t cf = (uint32_t)(ag[code] >> w0), cu = (uint32_t)(agu[code >> 1] >> w0);
                             agg_ou = (agg_af & cu) | (agg_ou & cf);
                             agg_af &= cf;
                         }
@@ -256,8 +310,8 @@ struct Tester {
 #pragma unroll
                     for (uint32_t u = 0; u < kGroup; ++u) {
                         const uint32_t code = (k + g0 + u < len) ? cs[g0 + u] : 0u;
-                        gf[u] = gather(code);
-                        if constexpr (MODE == 1) gt[u] = gather(code ^ 1u);
+                        gf[u] = gather(pb, code);
+                        if constexpr (MODE == 1) gt[u] = gather(pb, code ^ 1u);
                     }
 #pragma unroll
                     for (uint32_t u = 0; u < kGroup; ++u) {
@@ -279,7 +333,7 @@ struct Tester {
             if (len) {
 #pragma unroll
                 for (int i = 0; i < WPL; ++i)
-                    if (w0 + i < W) dense[(uint64_t)cur.meta.y * W + w0 + i] = af[i] | ou[i];
+                    if (gw0 + i < W) dense[(uint64_t)cur.meta.y * W + gw0 + i] = af[i] | ou[i];
             }
             return produced;
         }
@@ -291,7 +345,7 @@ struct Tester {
             if (has) {
                 const uint32_t pos = produced + lanes_below(bal);
                 if (pos < seg_cap) {
-                    const u32x4 rec = {cur.meta.y, w0 + i, (uint32_t)res, (uint32_t)(res >> 32)};
+                    const u32x4 rec = {cur.meta.y, gw0 + i, (uint32_t)res, (uint32_t)(res >> 32)};
                     __builtin_nontemporal_store(rec, reinterpret_cast<u32x4 *>(seg) + pos);
                 }
             }

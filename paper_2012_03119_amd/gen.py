@@ -216,6 +216,37 @@ def assignments_table1(rng, n_slots: int, n_vars: int) -> np.ndarray:
     return out
 
 
+def assignments_hierarchical(rng, n_super: int, n_vars: int, words_per_super: int = 64,
+                             keep: float = 0.7) -> np.ndarray:
+    """Assignments for aggregates of aggregates: n_super super-groups of
+    words_per_super 64-slot groups.  Each variable draws a value subset per
+    super-group with the Table 1 ratios; each group keeps every value of it with
+    probability `keep` (at least one); each slot draws its value uniformly in its
+    group's subset.  Returns int8 [n_super * words_per_super * 64][n_vars]."""
+    vals_of = {m: np.array([v for bit, v in ((1, T), (2, F), (4, U)) if m & bit], dtype=np.int8) for m in range(1, 8)}
+    sub_mask = np.array([sum({T: 1, F: 2, U: 4}[x] for x in sub) for sub, _ in TABLE1_SUBSETS], dtype=np.int64)
+    p = np.array([w for _, w in TABLE1_SUBSETS], dtype=np.float64)
+    p /= p.sum()
+    out = np.empty((n_super * words_per_super * 64, n_vars), dtype=np.int8)
+    for s in range(n_super):
+        base = sub_mask[rng.choice(len(p), size=n_vars, p=p)]
+        for w in range(words_per_super):
+            kept = np.zeros(n_vars, dtype=np.int64)
+            for bit in (1, 2, 4):
+                kept |= np.where(rng.random(n_vars) < keep, bit, 0)
+            mask = base & kept
+            lowest = base & -base
+            mask = np.where(mask == 0, lowest, mask)
+            r = rng.random((64, n_vars))
+            block = out[(s * words_per_super + w) * 64:(s * words_per_super + w + 1) * 64]
+            for m, vals in vals_of.items():
+                cols = np.flatnonzero(mask == m)
+                if len(cols):
+                    idx = np.minimum((r[:, cols] * len(vals)).astype(np.int64), len(vals) - 1)
+                    block[:, cols] = vals[idx]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # planting
 # ---------------------------------------------------------------------------

@@ -64,7 +64,7 @@ def test_create_rejects_bad_config_without_device(lib_path):
     # argument validation happens before any HIP call
     from paper_2012_03119_amd import gss
     lib = gss.load_library(lib_path)
-    for nv, ms in ((0, 64), (10, 0), (10, 100), (10, 8192)):
+    for nv, ms in ((0, 64), (10, 0), (10, 100), (10, 64 * 64 * 64 + 64)):
         cfg = gss.gss_config()
         cfg.num_vars, cfg.max_slots = nv, ms
         out = ctypes.c_void_p()

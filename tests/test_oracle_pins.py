@@ -332,6 +332,56 @@ def test_aggregate_of_a_group_is_tight():
             assert oracle.py_falsified_aggregate(clause, G) == any(oracle.py_falsified(clause, a) for a in group)
 
 
+@settings(max_examples=120, deadline=None)
+@given(instance(max_slots=16), st.integers(1, 3), st.integers(1, 3))
+def test_three_level_group_testing(inst, n_super, n_groups):
+    """The aggregate of the group aggregates is the aggregate of all the
+    super-group's assignments; a positive individual makes its group aggregate
+    and its super-group aggregate positive (Theorem 1 twice); and three-level
+    group testing finds exactly the individual results."""
+    values, clause = inst
+    dicts = oracle.values_to_dicts(values)
+    vars_ = {abs(l) for l in clause}
+    sgs = [[dicts[s::n_super][g::n_groups] for g in range(n_groups)] for s in range(n_super)]
+    for mode, one, agg in (("trigger", oracle.py_trigger, oracle.py_trigger_aggregate),
+                           ("falsified", oracle.py_falsified, oracle.py_falsified_aggregate)):
+        got = {(s, g): m for s, g, m in oracle.py_group_test_levels(clause, sgs, mode)}
+        for si, groups in enumerate(sgs):
+            members = [a for group in groups for a in group]
+            if not members:
+                continue
+            top = oracle.py_aggregate_of_aggregates([oracle.py_aggregate(group, vars_) for group in groups if group])
+            assert top == oracle.py_aggregate(members, vars_)
+            if any(one(clause, a) for a in members):
+                assert agg(clause, top)
+            for gi, group in enumerate(groups):
+                mask = sum(1 << j for j, a in enumerate(group) if one(clause, a))
+                assert got.get((si, gi), 0) == mask
+
+
+def test_three_level_filters_at_the_top():
+    """A super-group whose aggregate test is negative is not looked into: with the
+    top-level test replaced by one that is always negative, nothing is found,
+    while the individuals are positive (the filter is really applied)."""
+    clause = [1, 2]
+    sgs = [[[{1: F, 2: F}], [{1: T, 2: F}]]]
+    assert oracle.py_group_test_levels(clause, sgs, "falsified") == [(0, 0, 1)]
+    real = oracle.py_falsified_aggregate
+    calls = []
+
+    def spy(c, G):
+        calls.append(G)
+        return real(c, G)
+
+    oracle.py_falsified_aggregate = spy
+    try:
+        oracle.py_group_test_levels(clause, sgs, "falsified")
+    finally:
+        oracle.py_falsified_aggregate = real
+    # the top-level aggregate is tested first: A may be T or F, B only F
+    assert calls[0] == {1: frozenset({T, F}), 2: frozenset({F})}
+
+
 # ---------------------------------------------------------------------------
 # seeded workloads: planted pairs, chance hits, an independent formulation
 # ---------------------------------------------------------------------------
