@@ -77,7 +77,7 @@ typedef void (*gss_dev_free_fn)(void *ptr, void *stream, void *user);
 
 typedef struct gss_config {
     uint32_t num_vars;          /* variables 1..num_vars (>= 1) */
-    uint32_t max_slots;         /* assignment capacity: multiple of 64, 64..4096 (W = max_slots/64 words) */
+    uint32_t max_slots;         /* assignment capacity: multiple of 64, 64..262144 (W = max_slots/64 words) */
     uint64_t hbm_budget_bytes;  /* cap on the context's device memory; 0 = no cap */
     uint64_t report_capacity;   /* initial report buffer entries, split evenly over the test kernel's
                                    wavefronts (at least 16 each); grown by gss_test unless GSS_TEST_NO_REGROW */
@@ -236,6 +236,32 @@ gss_status gss_fetch_reports(gss_ctx *ctx, gss_report *out, uint64_t cap, uint64
  * (which has no row for them) are GSS_ERR_STATE.  Both are checked on the host
  * before anything is queued. */
 gss_status gss_fetch_masks(gss_ctx *ctx, const uint32_t *ids, uint32_t n, uint64_t *out);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): gss_test followed by
+ * gss_fetch_reports into device memory, with no hipMalloc, hipFree or
+ * allocating library call.  The test kernel's report segments, their counts and
+ * offsets live in a 64 MiB scratch array that the library holds once per GPU
+ * (from its first context on that GPU until the process ends); the records are
+ * then stitched into out (device memory, room for cap records; NULL when cap is
+ * 0).  *out_n_reports receives the exact number of records.  flags:
+ * GSS_TEST_TRIGGER, GSS_TEST_NO_EARLY_EXIT, GSS_TEST_NO_HOT, GSS_TEST_AGGREGATE
+ * (GSS_TEST_NO_REGROW is accepted and changes nothing: nothing is ever grown);
+ * other flags are INVALID_ARG.  GSS_TEST_TRIGGER | GSS_TEST_AGGREGATE is
+ * GSS_ERR_STATE until one gss_test with those flags has allocated the
+ * canBeUndef bits.  Errors:
+ *  - CAPACITY: the launch has too many wavefronts for 16 records each in the
+ *    scratch array (nothing is run);
+ *  - REPORT_OVERFLOW: a wavefront found more records than its share of the
+ *    scratch array (the array holds about 4 M records spread evenly over the
+ *    wavefronts), or more than cap; out holds min(cap, kept) records and
+ *    *out_n_reports the exact count.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (from contexts on different streams or
+ * threads) race and must be serialised by the caller.  The call synchronises
+ * the context's stream.  Afterwards gss_fetch_reports is GSS_ERR_STATE until the
+ * next gss_test (the records went to out only). */
+gss_status gss_test_noalloc(gss_ctx *ctx, uint32_t flags, gss_report *out, uint64_t cap, uint64_t *out_n_reports);
 
 /* Counters and timings of the context. */
 typedef struct gss_stats {

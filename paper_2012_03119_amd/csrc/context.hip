@@ -344,6 +344,7 @@ extern "C" gss_status gss_create(const gss_config *cfg, gss_ctx **out) {
         c = new Ctx();
         c->cfg = *cfg;
         GSS_HIP(hipGetDevice(&c->device));
+        scratch_setup(c->device);
         GSS_HIP(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
         if (cfg->stream) {
             c->stream = (hipStream_t)cfg->stream;

@@ -72,6 +72,8 @@ constexpr uint64_t kNoLoc = ~0ull;
 constexpr uint32_t kTestWavesPerBlock = 4;
 constexpr uint32_t kTestBlocksPerCU = 8;
 constexpr uint32_t kMinSegment = 16;   // smallest report segment per wavefront (grown on demand)
+constexpr uint64_t kScratchBytes = 64ull << 20;  // gss_test_noalloc's segments, per GPU
+constexpr int kMaxDevices = 64;
 
 // length class: smallest c >= kMinClass with 2^c >= len
 inline int length_class(uint32_t len) {
@@ -320,6 +322,7 @@ void copy_in(Ctx &c, void *dst, const void *src_hd, size_t bytes);
 // Queues the copy of the last test's first n kept records, as one list, into
 // device memory dst (on the context's stream).
 void queue_stitch(Ctx &c, gss_report *dst, uint64_t n);
+void scratch_setup(int device);  // once per device, from gss_create
 // Writes the n records at src (device) into dst (device) ordered by (clause id,
 // word); synchronises the stream.
 void sort_records(Ctx &c, const gss_report *src, uint64_t n, gss_report *dst);

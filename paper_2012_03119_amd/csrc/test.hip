@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <mutex>
 
 namespace gss {
 
@@ -134,8 +135,21 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     return L;
 }
 
-// Queues the test kernel, the finalize kernel and the copy of the summary.
-static void launch(Ctx &c, const Launch &L, uint32_t flags) {
+// Report segments of one launch: the records of each wavefront, their counts and
+// the exclusive prefix of the kept records.  The context's own buffers, or the
+// scratch array of gss_test_noalloc.
+struct Segments {
+    gss_report *reports;
+    uint32_t *counts;
+    uint64_t *offsets;
+    uint32_t cap;
+};
+
+static Segments context_segments(Ctx &c) { return Segments{c.reports, c.seg_counts, c.seg_offsets, c.seg_cap}; }
+
+// Queues the test kernel and the finalize kernel, which writes the summary and
+// the test's serial into pinned host memory.
+static void launch(Ctx &c, const Launch &L, uint32_t flags, const Segments &sg) {
     // timing events around the kernel (attaching them to the dispatch instead,
     // with hipExtLaunchKernel, measured slower: 24 against 10 us of host time per
     // launch, on the path between two tests)
@@ -146,7 +160,7 @@ static void launch(Ctx &c, const Launch &L, uint32_t flags) {
     GSS_HIP(hipEventRecord(c.ev_stop, c.stream));
     const uint32_t n_waves = L.grid * kTestWavesPerBlock;
     const uint64_t serial = c.tests_launched + 1;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, c.stream, c.seg_counts, n_waves, c.seg_cap, c.seg_offsets,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, c.stream, sg.counts, n_waves, sg.cap, sg.offsets,
                        c.d_summary, deferred_flag(c), c.hd_summary, (unsigned long long)serial);
     GSS_HIP(hipGetLastError());
     c.tests_launched = serial;
@@ -225,7 +239,7 @@ static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
         c.last_waves = 0;
         return false;
     }
-    launch(c, L, flags);
+    launch(c, L, flags, context_segments(c));
     return true;
 }
 
@@ -257,7 +271,7 @@ static uint64_t end_test(Ctx &c, uint32_t flags, bool launched) {
             if (grown && c.mutations == c.launch_mutations) {
                 c.stats.regrows++;
                 Launch L = prepare(c, flags);
-                launch(c, L, flags);
+                launch(c, L, flags, context_segments(c));
                 complete(c);
                 n = c.h_summary[0];
                 kept = c.h_summary[2];
@@ -281,13 +295,15 @@ static uint64_t end_test(Ctx &c, uint32_t flags, bool launched) {
     return n;
 }
 
-void queue_stitch(Ctx &c, gss_report *dst, uint64_t n) {
+static void queue_stitch(Ctx &c, const Segments &sg, gss_report *dst, uint64_t n) {
     if (!n) return;
     const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>(c.last_waves, 65535));
-    hipLaunchKernelGGL(k_stitch, dim3(grid), dim3(256), 0, c.stream, c.reports, c.seg_counts, c.seg_offsets, c.seg_cap,
+    hipLaunchKernelGGL(k_stitch, dim3(grid), dim3(256), 0, c.stream, sg.reports, sg.counts, sg.offsets, sg.cap,
                        c.last_waves, n, dst);
     GSS_HIP(hipGetLastError());
 }
+
+void queue_stitch(Ctx &c, gss_report *dst, uint64_t n) { queue_stitch(c, context_segments(c), dst, n); }
 
 }  // namespace gss
 
@@ -423,5 +439,121 @@ extern "C" gss_status gss_fetch_masks(gss_ctx *ctx, const uint32_t *ids, uint32_
     GSS_HIP(hipGetLastError());
     GSS_HIP(hipMemcpyAsync(out, d + ids_bytes, out_bytes, hipMemcpyDefault, c.stream));
     c.sync();
+    GSS_API_END
+}
+
+// ---------------------------------------------------------------------------
+// A test that allocates nothing, for callers that cannot allocate device memory.
+// Its report segments, their counts and offsets live in a file-scope device
+// array: one copy per GPU, held from the library's first context on that GPU
+// until the process ends.
+// ---------------------------------------------------------------------------
+
+namespace gss {
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices] = {};  // device address of `scratch` per GPU
+
+// Called by gss_create with the context's device current.  Host code uses the
+// address returned here, never the array's name (a host-side stand-in).
+void scratch_setup(int device) {
+    GSS_REQUIRE(device >= 0 && device < kMaxDevices, GSS_ERR_DEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+        throw Error(GSS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[device] = p;
+}
+
+static void *scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < kMaxDevices ? g_scratch[device] : nullptr;
+}
+
+// Carves the segments of a launch of n_waves wavefronts out of the scratch array:
+// counts, offsets, then records.  Too many wavefronts for kMinSegment records
+// each: GSS_ERR_CAPACITY.
+static Segments scratch_segments(void *base, uint32_t n_waves) {
+    const uint64_t counts_bytes = ((uint64_t)n_waves * 4 + 255) / 256 * 256;
+    const uint64_t offsets_bytes = (((uint64_t)n_waves + 1) * 8 + 255) / 256 * 256;
+    const uint64_t head = counts_bytes + offsets_bytes;
+    const uint64_t per_wave = head < kScratchBytes ? (kScratchBytes - head) / sizeof(gss_report) / n_waves : 0;
+    GSS_REQUIRE(per_wave >= kMinSegment, GSS_ERR_CAPACITY,
+                "a test of " + std::to_string(n_waves) + " wavefronts needs more than the " +
+                    std::to_string(kScratchBytes) + " bytes of scratch memory");
+    char *p = static_cast<char *>(base);
+    Segments sg;
+    sg.counts = reinterpret_cast<uint32_t *>(p);
+    sg.offsets = reinterpret_cast<uint64_t *>(p + counts_bytes);
+    sg.reports = reinterpret_cast<gss_report *>(p + head);
+    sg.cap = (uint32_t)std::min<uint64_t>(per_wave, 0xFFFFFFFFull);
+    return sg;
+}
+
+}  // namespace gss
+
+extern "C" gss_status gss_test_noalloc(gss_ctx *ctx, uint32_t flags, gss_report *out, uint64_t cap,
+                                       uint64_t *out_n_reports) {
+    GSS_API_BEGIN(ctx)
+    Ctx &c = *c_;
+    if (out_n_reports) *out_n_reports = 0;
+    const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT |
+                           GSS_TEST_AGGREGATE;
+    GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG,
+                "gss_test_noalloc takes GSS_TEST_TRIGGER, NO_EARLY_EXIT, NO_REGROW, NO_HOT and AGGREGATE only");
+    GSS_REQUIRE(out_n_reports != nullptr, GSS_ERR_INVALID_ARG, "null argument");
+    GSS_REQUIRE(cap == 0 || (out != nullptr && is_device_pointer(out)), GSS_ERR_INVALID_ARG,
+                "out must be device memory with room for cap records");
+    GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is already in flight (call gss_test_wait)");
+    // the trigger form of the aggregate pre-test needs bits the context allocates
+    // on its first use
+    if ((flags & GSS_TEST_AGGREGATE) && (flags & GSS_TEST_TRIGGER))
+        GSS_REQUIRE(c.aggu != nullptr && (c.G == 1 || c.saggu != nullptr), GSS_ERR_STATE,
+                    "run one gss_test with GSS_TEST_TRIGGER | GSS_TEST_AGGREGATE first (it allocates the "
+                    "canBeUndef bits)");
+    void *base = scratch_of(c.device);
+    GSS_REQUIRE(base != nullptr, GSS_ERR_STATE, "scratch memory was not set up on this device");
+    uint64_t act = 0;
+    for (uint64_t x : c.h_active) act += __builtin_popcountll(x);
+    uint64_t lits = 0;
+    for (const auto &B : c.buckets) lits += B.n_lits;
+    c.stats.last_pairs = c.live * act;
+    c.stats.last_literals = lits;
+
+    Launch L = prepare(c, flags);
+    uint64_t n = 0, kept = 0;
+    if (L.args.n_tiles) {
+        const Segments sg = scratch_segments(base, L.grid * kTestWavesPerBlock);
+        L.args.reports = sg.reports;
+        L.args.seg_counts = sg.counts;
+        L.args.seg_cap = sg.cap;
+        // the context's records of an earlier test are not touched; they are no
+        // longer the last test's
+        c.tested = false;
+        launch(c, L, flags, sg);
+        complete(c);
+        n = c.h_summary[0];
+        kept = c.h_summary[2];
+        const uint64_t m = std::min(kept, cap);
+        queue_stitch(c, sg, out, m);
+        c.sync();
+        report_deferred(c, (uint32_t)c.h_summary[3]);
+    } else {
+        c.last_waves = 0;
+        c.tested = false;
+        report_deferred(c, read_deferred(c));
+    }
+    c.stats.tests_run++;
+    c.stats.last_reports = n;
+    c.test_serial++;
+    *out_n_reports = n;
+    GSS_REQUIRE(kept == n, GSS_ERR_REPORT_OVERFLOW,
+                "the scratch segments kept " + std::to_string(kept) + " of " + std::to_string(n) + " records");
+    GSS_REQUIRE(n <= cap, GSS_ERR_REPORT_OVERFLOW,
+                "out holds " + std::to_string(cap) + " of " + std::to_string(n) + " records");
     GSS_API_END
 }

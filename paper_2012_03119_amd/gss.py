@@ -161,6 +161,7 @@ def load_library(path: Optional[str] = None):
         "gss_set_var_values_async": ([P, u32, u32, u32, P, P], ctypes.c_int32),
         "gss_clear_slots": ([P, u32, u32], ctypes.c_int32),
         "gss_test": ([P, u32, P], ctypes.c_int32),
+        "gss_test_noalloc": ([P, u32, P, u64, P], ctypes.c_int32),
         "gss_fetch_reports": ([P, P, u64, P], ctypes.c_int32),
         "gss_fetch_masks": ([P, P, u32, P], ctypes.c_int32),
         "gss_get_stats": ([P, ctypes.POINTER(gss_stats)], ctypes.c_int32),
@@ -357,6 +358,15 @@ def gss_clear_slots(ctx, first_slot: int, n_slots: int) -> None:
 def gss_test(ctx, flags: int = 0) -> int:
     n = ctypes.c_uint64()
     _check(ctx, load_library().gss_test(ctx, flags, ctypes.byref(n)))
+    return n.value
+
+
+def gss_test_noalloc(ctx, flags: int, ptr: int, cap: int) -> int:
+    """The test with its records stitched into device memory at address ptr
+    (room for cap 16-byte records); returns the exact number of records."""
+    n = ctypes.c_uint64()
+    _check(ctx, load_library().gss_test_noalloc(ctx, flags, ctypes.c_void_p(ptr) if cap else None, cap,
+                                                ctypes.byref(n)))
     return n.value
 
 
@@ -672,6 +682,16 @@ class Context:
 
     def test(self, flags: int = 0) -> int:
         n = gss_test(self.ctx, flags)  # on an error the queued inputs stay held (harmless if applied)
+        self._held = []
+        return n
+
+    def test_noalloc(self, flags: int, out) -> int:
+        """gss_test_noalloc into `out`, a contiguous CUDA tensor whose bytes hold
+        len(out bytes) // 16 records; returns the exact number of records."""
+        if not (out.is_cuda and out.is_contiguous()):
+            raise ValueError("out must be a contiguous CUDA tensor")
+        cap = out.numel() * out.element_size() // 16
+        n = gss_test_noalloc(self.ctx, flags, out.data_ptr(), cap)
         self._held = []
         return n
 
