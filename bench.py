@@ -46,12 +46,14 @@ def make_workload(args):
     from paper_2012_03119_amd import gen
     if args.workload == "tiny":
         return gen.tiny(args.seed), "plain test, tiny: 20k clauses x 2k vars, 64 assignments"
-    weights = gen.zipf_weights(args.vars, args.zipf) if args.zipf else None
+    shuffle = args.seed + 77 if args.zipf_shuffle else None
+    weights = gen.zipf_weights(args.vars, args.zipf, shuffle) if args.zipf else None
     w = gen.paper(args.seed, n_clauses=args.clauses, n_vars=args.vars, n_slots=args.slots, var_weights=weights)
     desc = (f"plain test, paper scale: {args.clauses} clauses x {args.vars} vars, {args.slots} assignments, "
             f"length mix 50%[2,10] 40%[11,50] 10%[51,300], 5% variable flips per round")
     if args.zipf:
-        desc += f", Zipf({args.zipf}) variable frequencies (variable 1 most frequent)"
+        desc += (f", Zipf({args.zipf}) variable frequencies "
+                 + ("over shuffled variable numbers" if args.zipf_shuffle else "(variable 1 most frequent)"))
     return w, desc
 
 
@@ -220,15 +222,18 @@ def bench_served(args, torch, gss):
     rng = np.random.default_rng(args.seed + 400)
     lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, n0), V)
     log(f"served store generated in {time.perf_counter() - t0:.1f} s: {n0} clauses, {len(lits)} literals")
-    ctx = gss.Context(V, P * 64, hbm_budget_bytes=64 << 30, report_capacity=1 << 22)
+    budget = int(args.serve_budget_gb * 2**30)
+    ctx = gss.Context(V, P * 64, hbm_budget_bytes=budget, report_capacity=1 << 22)
     ctx.add_clauses(lits, offs)
     del lits, offs
     log(f"store resident ({ctx.store_info()['device_bytes'] / 2**30:.2f} GiB); serving for {args.serve_seconds:.0f} s")
     res = ctx.serve_simulate(n_threads=P, duration_s=args.serve_seconds, snapshot_rate=200.0, redraw_fraction=0.05,
                              insert_rate=20_000.0, delete_fraction=0.02, seed=args.seed + 401,
-                             test_flags=gss.GSS_TEST_AGGREGATE if args.aggregate else 0)
+                             test_flags=gss.GSS_TEST_AGGREGATE if args.aggregate else 0,
+                             evict_keep=args.evict_keep)
     log(f"served: {res['runs']} runs, {res['tested']} snapshots tested, {res['dropped']} dropped, "
-        f"p50 {res['p50_ms']:.2f} ms p99 {res['p99_ms']:.2f} ms, {res['live_end']} live clauses")
+        f"p50 {res['p50_ms']:.2f} ms p99 {res['p99_ms']:.2f} ms, {res['live_end']} live clauses, "
+        f"{res['evictions']} evictions ({res['evicted']} clauses)")
     # the plain test on the final store, every word active
     ctx.set_active(np.full(P, 2**64 - 1, dtype=np.uint64))
     flags = gss.GSS_TEST_AGGREGATE if args.aggregate else 0
@@ -253,10 +258,12 @@ def bench_served(args, torch, gss):
         "config": {"workload": "served: 32 solver threads x 200 snapshots/s of 64 assignments (5% of 2M variables "
                                "redrawn per snapshot, Table 1 values), 20k inserts/s/thread (length mix), 2%/s "
                                "removals, 8M-clause resident store, 64 GB budget",
-                   "seconds": args.serve_seconds, "initial_clauses": n0},
+                   "seconds": args.serve_seconds, "initial_clauses": n0, "budget_bytes": budget,
+                   "evict_keep": args.evict_keep},
         "latency_ms": {k: res[k + "_ms"] for k in ("p50", "p99", "mean", "max")},
         "served": {k: res[k] for k in ("snapshots", "tested", "dropped", "runs", "overflowed_runs", "inserted",
-                                       "refused", "deleted", "reports", "live_end", "delta_bytes", "gpu_ms")},
+                                       "refused", "deleted", "reports", "live_end", "delta_bytes", "gpu_ms",
+                                       "evictions", "evicted", "device_bytes_end")},
         "manager_ms": {k: round(res[k + "_ms"], 1) for k in ("admit", "wait", "fetch", "route", "store", "launch")},
         "dropped_ratio": res["dropped"] / max(res["snapshots"], 1),
         "gpu_busy": res["gpu_ms"] / (res["wall_s"] * 1e3),
@@ -523,6 +530,10 @@ def main():
                     help="threshold: the score under which this fraction of the training positives fall")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-clauses", type=int, default=8_000_000)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM admission budget of the served store")
+    ap.add_argument("--evict-keep", type=float, default=0.0,
+                    help="served: when an insert does not fit the budget, evict the least active clauses down to "
+                         "this fraction (0 = inserts wait)")
     ap.add_argument("--clauses", type=int, default=4_000_000)
     ap.add_argument("--vars", type=int, default=1_000_000)
     ap.add_argument("--slots", type=int, default=1024)
@@ -530,6 +541,10 @@ def main():
     ap.add_argument("--hot-vars", type=int, default=0, help="variables whose plane rows are staged in LDS")
     ap.add_argument("--zipf", type=float, default=0.0,
                     help="Zipf exponent of the variable frequencies (0: uniform, as in the paper-scale workload)")
+    ap.add_argument("--stitch-steps", type=int, default=5,
+                    help="extra steps that also stitch the records into one device list (timed apart)")
+    ap.add_argument("--zipf-shuffle", action="store_true",
+                    help="deal the Zipf frequencies to the variables in a random order")
     ap.add_argument("--report-capacity", type=int, default=1 << 20)
     ap.add_argument("--no-early-exit", action="store_true")
     ap.add_argument("--trigger", action="store_true")
@@ -579,7 +594,7 @@ def main():
     t0 = time.perf_counter()
     w, desc = make_workload(args)
     log(f"workload ready in {time.perf_counter() - t0:.1f} s: {w.n_clauses} clauses, {len(w.lits)} literals")
-    need_rounds = args.warmup + args.steps if args.workload == "paper" else 0
+    need_rounds = args.warmup + args.steps + args.stitch_steps if args.workload == "paper" else 0
     # every step applies a round of its own: nothing is recycled
     rounds = stage_rounds(w, need_rounds, args.seed, torch) if need_rounds else []
 
@@ -639,6 +654,28 @@ def main():
     value = pairs / (elapsed / args.steps)
     kernel_ms = st["total_kernel_ms"] / max(1, st["timed_launches"])
 
+    # the same steps with each test's records also stitched into one device
+    # list (the fetch the timed steps leave for the caller): not pipelined, so
+    # this measures the step plus the stitch and the extra synchronisation
+    stitch_ms = None
+    if args.workload == "paper" and args.stitch_steps:
+        k = min(args.stitch_steps, len(rounds) - args.warmup - args.steps) if rounds else 0
+        dev = torch.empty((max(n_rep, 1) * 5 // 4 + 4096) * 2, dtype=torch.int64, device="cuda")
+        if k > 0:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(args.warmup + args.steps, args.warmup + args.steps + k):
+                queue_delta(i)
+                n_i = ctx.test(flags)
+                gss.gss_fetch_reports_into(ctx.ctx, dev.data_ptr(), min(n_i, dev.numel() // 2))
+            torch.cuda.synchronize()
+            stitch_ms = (time.perf_counter() - t0) * 1e3 / k
+            log(f"{k} steps with the records stitched into one device list: {stitch_ms:.3f} ms/step")
+    hot_share = None
+    if args.hot_vars:
+        hot, stored = ctx.rank_vars()
+        hot_share = hot / stored if stored else None
+
     W = w.n_slots // 64
     table_bytes = 2 * (w.n_vars + 1) * W * 8
     alg_bytes = 4 * st["last_literals"] + 8 * st["live_clauses"] + table_bytes + 16 * st["last_reports"]
@@ -669,7 +706,10 @@ def main():
                    "seed": args.seed, "flags": flags, "hot_vars": args.hot_vars,
                    "reports_per_test": n_rep, "gpu": torch.cuda.get_device_name(0)},
         "roofline": roofline,
+        "ms_per_step_with_stitch": round(stitch_ms, 4) if stitch_ms else None,
     }
+    if hot_share is not None:
+        out["config"]["hot_literal_share"] = round(hot_share, 4)
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")

@@ -85,7 +85,8 @@ typedef struct gss_config {
     gss_dev_alloc_fn dev_alloc; /* optional, see above */
     gss_dev_free_fn dev_free;
     void *alloc_user;
-    uint32_t hot_vars;          /* LDS staging: rows of variables 1..hot_vars are kept in LDS (0 = off) */
+    uint32_t hot_vars;          /* LDS staging of the rows of the hot_vars most frequent variables (0 = off);
+                                   see gss_rank_vars */
     uint32_t reserved;
 } gss_config;
 
@@ -190,6 +191,11 @@ gss_status gss_clear_slots(gss_ctx *ctx, uint32_t first_slot, uint32_t n_slots);
  * result is the same as without the flag; it is faster when the assignments of a
  * word are similar (as successive assignments of one solver thread are). */
 #define GSS_TEST_AGGREGATE 256u
+/* Counts what the test kernel did (gss_get_stats, last_* fields below): the
+ * plane-row gathers its lanes issued and the (clause, word) pairs the aggregate
+ * pre-test settled.  Costs a few instructions per gather and a synchronisation
+ * when the test completes. */
+#define GSS_TEST_COUNT 512u
 
 /* Tests every live clause against every active slot (Section 3.6: a GPU run tests
  * all clauses against all assignments not yet tested and reports every hit).
@@ -237,6 +243,21 @@ gss_status gss_fetch_reports(gss_ctx *ctx, gss_report *out, uint64_t cap, uint64
  * before anything is queued. */
 gss_status gss_fetch_masks(gss_ctx *ctx, const uint32_t *ids, uint32_t n, uint64_t *out);
 
+/* Hot variables (Section 7, Conclusion: keep some variables' values in shared
+ * memory).  With hot_vars > 0 the test kernel stages the plane rows of hot_vars
+ * variables in LDS.  The library picks them: it counts on the device how often
+ * each variable occurs in the live clauses and renumbers its variables
+ * internally so that the hot_vars most frequent ones own the staged rows.  The
+ * renumbering is invisible at this interface (variables keep their numbers in
+ * every call, ids and records are unchanged).  gss_test ranks by itself on its
+ * first run with staging and whenever the stored literals have doubled since
+ * the last ranking (not while a server owns the context); gss_rank_vars ranks
+ * now.  *out_hot_lits and *out_lits (either may be NULL) receive the literal
+ * occurrences on the staged variables and in the store at the last ranking.
+ * No staging (hot_vars 0, or rows of more than 4096 slots): nothing is ranked
+ * and both counts are 0.  GSS_ERR_STATE with a test in flight or a server. */
+gss_status gss_rank_vars(gss_ctx *ctx, uint64_t *out_hot_lits, uint64_t *out_lits);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid allocation): gss_test followed by
  * gss_fetch_reports into device memory, with no hipMalloc, hipFree or
@@ -278,6 +299,14 @@ typedef struct gss_stats {
     double last_kernel_ms;      /* duration of the last test kernel, from HIP events on the context stream */
     double total_kernel_ms;     /* sum over test kernel launches since the last reset */
     uint64_t timed_launches;    /* launches summed in total_kernel_ms */
+    /* the last test, when it ran with GSS_TEST_COUNT (else 0): */
+    uint64_t last_gathers;      /* plane-row reads of the kernel's lanes: a lane reads its (up to 4) words of the
+                                   row of each literal it tests (with GSS_TEST_AGGREGATE, of each literal of a
+                                   group of four, padding past the clause's end included); trigger mode reads the
+                                   opposite literal's row beside it, counted once */
+    uint64_t last_gather_bytes; /* bytes those reads asked for */
+    uint64_t last_agg_settled;  /* (clause, word) pairs the aggregate pre-test settled before the plane words
+                                   did: no further gathers for them (GSS_TEST_AGGREGATE) */
 } gss_stats;
 
 gss_status gss_get_stats(const gss_ctx *ctx, gss_stats *out);
@@ -452,7 +481,8 @@ gss_status gss_priority_info(const gss_ctx *ctx, uint32_t *out_run, uint64_t *ou
  *    (continuous batching).  A snapshot superseded before a run took it is
  *    dropped, as the paper drops assignments the GPU cannot take.
  *  - gss_server_insert queues learned clauses; they are admitted between runs
- *    within the context's HBM budget (held back while it is full).
+ *    within the context's HBM budget: while it is full they are held back, or,
+ *    with evict_keep, the least active clauses make room (Section 3.7).
  *  - a fraction of the live clauses is removed each second at random (the
  *    simulated clause-database reduction of the solvers).
  *  - the records of each run are routed by word to their producer, who collects
@@ -472,7 +502,12 @@ typedef struct gss_server_config {
     const char *log_path;     /* NULL, or a text file receiving every change, run and record in the
                                  order the device applies them (for replay against a reference) */
     uint64_t max_queued_lits; /* inserts waiting for admission, in literals (0 = 1 << 26); beyond: refused */
-    uint64_t reserved[3];
+    double evict_keep;        /* activity eviction (Section 3.7): when an insert does not fit the HBM budget,
+                                 the least active live clauses are removed until this fraction of them is
+                                 left, and the insert is retried (0 = off: inserts wait for removals).
+                                 In [0, 1).  Enables the context's learned priority if it is not (its
+                                 activities: every run bumps the clauses with a record) */
+    uint64_t reserved[2];
 } gss_server_config;
 
 typedef struct gss_serve_result {
@@ -489,6 +524,8 @@ typedef struct gss_serve_result {
     uint64_t live_end;        /* live clauses at the end */
     uint64_t device_bytes_end;
     uint64_t delta_bytes;     /* bytes of deltas uploaded */
+    uint64_t evicted;         /* clauses removed by activity eviction */
+    uint64_t evictions;       /* activity evictions (each removes down to evict_keep of the live clauses) */
     double wall_s;            /* from start to stop */
     double gpu_ms;            /* test kernel time, summed over runs */
     double mean_ms, p50_ms, p99_ms, max_ms; /* notify latency */
@@ -549,7 +586,8 @@ typedef struct gss_sim_config {
     double delete_fraction;
     uint64_t seed;
     const char *log_path;
-    uint64_t reserved[4];
+    double evict_keep;        /* as gss_server_config.evict_keep */
+    uint64_t reserved[3];
 } gss_sim_config;
 
 gss_status gss_serve_simulate(gss_ctx *ctx, const gss_sim_config *cfg, gss_serve_result *out);

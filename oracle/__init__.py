@@ -64,9 +64,12 @@ def build(verbose: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-            build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("ORACLE_LIBRARY")  # another build of oracle.c (e.g. with sanitizers)
+        if not path:
+            path = _LIB_PATH
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+                build()
+        lib = ctypes.CDLL(path)
         p = ctypes.c_void_p
         i64 = ctypes.c_int64
         lib.oracle_transpose.argtypes = [i64, i64, p, p]

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgss.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["context.hip", "store.hip", "planes.hip", "test.hip", "batch.hip", "serve.hip", "simulate.hip", "mlp.hip", "priority.hip", "sort.hip"]
+SOURCES = ["context.hip", "store.hip", "planes.hip", "test.hip", "batch.hip", "serve.hip", "simulate.hip", "mlp.hip", "priority.hip", "sort.hip", "rank.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -48,7 +48,8 @@ __device__ uint32_t batch_tile(const StoreDesc &st, uint32_t tile, gss_report *s
     uint32_t bi = 0;
     typename Ts::Tile cur;
     ts.open(st.descs, st.n_buckets, bi, tile, cur);
-    return ts.run(cur, seg, st.seg_cap, produced, early_exit, nullptr);
+    Counts none;
+    return ts.run(cur, seg, st.seg_cap, produced, early_exit, nullptr, none);
 }
 
 template <int MODE>

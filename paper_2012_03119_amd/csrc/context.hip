@@ -296,6 +296,8 @@ static void destroy_ctx(Ctx *c) {
     c->dfree(c->sagg);
     c->dfree(c->saggu);
     c->dfree(c->var_bits);
+    c->dfree(c->d_perm);
+    c->dfree(c->wave_stats);
     c->dfree(c->active);
     c->dfree(c->reports);
     c->dfree(c->seg_counts);

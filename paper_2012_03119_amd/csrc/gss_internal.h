@@ -62,6 +62,9 @@ __host__ __device__ inline uint64_t plane_index(uint64_t row, uint32_t w, uint32
     return (uint64_t)(w / kChunkWords) * chunk_elems + row * RWc + (w % kChunkWords);
 }
 
+// Plane row variable of external variable v (identity until a ranking moved it).
+__host__ __device__ inline uint32_t internal_var(const uint32_t *perm, uint32_t v) { return perm ? perm[v] : v; }
+
 constexpr int kMaxBuckets = 17;              // length classes 4, 8, ..., 65536 (classes 0-1 unused)
 constexpr int kMinClass = 2;                 // strides start at 4 codes: one 16-byte load
 constexpr uint32_t kMaxClauseLen = 65536;
@@ -122,6 +125,7 @@ struct TestArgs {
     const uint64_t *saggu;    // G > 1, trigger mode: per variable, bit g = U in some active slot of super-group g
     uint64_t n_rows;          // rows of the plane table (the stride of the aggregate chunks)
     uint64_t gmask;           // super-groups holding an active slot (bit g: words 64g .. 64g + 63)
+    uint32_t *wave_stats;     // GSS_TEST_COUNT: [n_waves][2] gathers, pre-test settled words; null: not counted
 };
 
 // ---------------------------------------------------------------------------
@@ -206,6 +210,20 @@ struct Ctx {
     uint64_t n_kept = 0;     // records stored (fewer on overflow)
     bool tested = false;
     uint32_t last_flags = 0;
+
+    // internal variable numbers (hot-variable ranking): external v -> perm[v];
+    // empty / null until the first ranking that moves a variable (identity)
+    std::vector<uint32_t> h_perm;
+    std::vector<uint32_t> h_iperm;  // internal -> external
+    uint32_t *d_perm = nullptr;
+    uint64_t ranked_lits = 0;  // literals stored at the last ranking
+    uint64_t hot_lits = 0;     // of them, on the staged variables
+    uint64_t rankings = 0;
+    bool serving = false;      // a server owns the context (no ranking then)
+    const uint32_t *perm() const { return h_perm.empty() ? nullptr : h_perm.data(); }
+    uint32_t external_var(uint32_t v) const { return h_iperm.empty() ? v : h_iperm[v]; }
+
+    uint32_t *wave_stats = nullptr;  // [max_waves][2], allocated by the first counted test
 
     uint64_t *dense = nullptr;
     uint64_t dense_rows = 0;
@@ -323,6 +341,16 @@ void copy_in(Ctx &c, void *dst, const void *src_hd, size_t bytes);
 // device memory dst (on the context's stream).
 void queue_stitch(Ctx &c, gss_report *dst, uint64_t n);
 void scratch_setup(int device);  // once per device, from gss_create
+// Activity (learned priority enabled): state for ids below n_ids (validate
+// before an insert changes anything); bump the clauses with a record in the
+// last test; remove the least active live clauses until `keep` remain, returning
+// their ids (may run while a test is in flight: it synchronises the stream).
+void priority_reserve(Ctx &c, uint64_t n_ids);
+void priority_bump_hits(Ctx &c);
+std::vector<uint32_t> priority_evict(Ctx &c, uint64_t keep);
+// Ranks the variables by occurrences in the live clauses and renumbers them so
+// that the most frequent own the LDS-staged rows; false when nothing moved.
+bool rank_vars(Ctx &c);
 // Writes the n records at src (device) into dst (device) ordered by (clause id,
 // word); synchronises the stream.
 void sort_records(Ctx &c, const gss_report *src, uint64_t n, gss_report *dst);
@@ -330,9 +358,9 @@ uint32_t *deferred_flag(Ctx &c);
 uint32_t read_deferred(Ctx &c);
 void report_deferred(Ctx &c, uint32_t verdict);
 // Clause ingest in two parts.  prepare_clauses validates DIMACS clauses and
-// encodes them (codes 2v+neg, the lead -- smallest code -- first, the length
-// class and lead of each clause); it touches no context and may run on any
-// thread.  commit_clauses assigns ids in batch order and uploads the batch, laid
+// encodes them (codes 2v+neg of the internal variable number perm[v], or v
+// without a map; the lead -- smallest code -- first; the length class and lead
+// of each clause); it touches no context and may run on any thread.  commit_clauses assigns ids in batch order and uploads the batch, laid
 // out by length class and lead.  Both throw Error.
 struct Prepared {
     std::vector<uint32_t> codes;
@@ -348,7 +376,8 @@ struct Prepared {
     }
     void append(const Prepared &o);
 };
-void prepare_clauses(int64_t num_vars, const int32_t *lits, const uint64_t *offsets, uint32_t n, Prepared &out);
+void prepare_clauses(int64_t num_vars, const int32_t *lits, const uint64_t *offsets, uint32_t n, Prepared &out,
+                     const uint32_t *perm);
 void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids);
 
 // learned priority hooks: clauses added (ids first..first+n, lengths from offsets),

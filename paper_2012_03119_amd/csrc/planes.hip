@@ -132,7 +132,7 @@ void super_rebuild(Ctx &c, bool with_u) {
 __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RWc, uint64_t chunk, uint32_t w,
                                                   uint32_t num_vars,
                                                   const int8_t *stage, uint64_t pitch, uint32_t s_lo, uint32_t s_hi,
-                                                  const uint32_t *bad) {
+                                                  const uint32_t *bad, const uint32_t *perm) {
     if (*bad) return;  // the inputs failed validation: apply nothing
     const uint32_t lane = threadIdx.x;
     const uint32_t v0 = 1 + 64 * blockIdx.x;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RWc
     }
     const uint32_t v = v0 + lane;
     if (v <= num_vars) {
-        const uint64_t r0 = plane_index(2ull * v, w, RWc, chunk), r1 = r0 + RWc;
+        const uint64_t r0 = plane_index(2ull * internal_var(perm, v), w, RWc, chunk), r1 = r0 + RWc;
         if (sm != ~0ull) {
             f = (planes[r0] & ~sm) | (f & sm);
             t = (planes[r1] & ~sm) | (t & sm);
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(64) void k_pack_word(uint64_t *planes, uint32_t RWc
 __global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RWc, uint64_t chunk, const uint32_t *vars,
                                                   uint32_t n_vars,
                                                   const int8_t *vals, uint32_t first, uint32_t n_slots, uint32_t nw,
-                                                  const uint32_t *bad, uint32_t *clear_bits) {
+                                                  const uint32_t *bad, uint32_t *clear_bits, const uint32_t *perm) {
     const uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (x >= (uint64_t)n_vars * nw) return;
     const uint32_t i = (uint32_t)(x / nw);
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RWc
             t |= (uint64_t)(x == 1) << (s - 64 * w);
         }
     }
-    const uint64_t r0 = plane_index(2ull * vars[i], w, RWc, chunk), r1 = r0 + RWc;
+    const uint64_t r0 = plane_index(2ull * internal_var(perm, vars[i]), w, RWc, chunk), r1 = r0 + RWc;
     if (hi - lo != 64) {
         const uint64_t sm = ((1ull << (hi - lo)) - 1) << (lo - 64 * w);  // hi - lo < 64 here
         f = (planes[r0] & ~sm) | (f & sm);
@@ -227,11 +227,12 @@ __global__ __launch_bounds__(256) void k_set_vars(uint64_t *planes, uint32_t RWc
 // The variables of one launch are distinct, so each thread owns its two rows'
 // aggregate bits (bit `word` of the word's chunk), updated in place.
 __global__ void k_set_words(uint64_t *planes, uint32_t RWc, uint64_t chunk, uint64_t n_rows, uint32_t word,
-                            const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n, void *agg) {
+                            const uint32_t *vars, const uint64_t *f, const uint64_t *t, uint32_t n, void *agg,
+                            const uint32_t *perm) {
     const uint64_t a_base = (uint64_t)(word / kChunkWords) * n_rows;
     const uint64_t bit = 1ull << (word % kChunkWords);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint64_t row = 2ull * vars[i];
+        const uint64_t row = 2ull * internal_var(perm, vars[i]);
         const uint64_t r0 = plane_index(row, word, RWc, chunk);
         planes[r0] = f[i];
         planes[r0 + RWc] = t[i];
@@ -261,7 +262,7 @@ void launch_set_words(Ctx &c, uint32_t word, const uint32_t *vars, const uint64_
     c.sagg_valid = false;
     const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 255) / 256, 4096));
     hipLaunchKernelGGL(k_set_words, dim3(grid), dim3(256), 0, c.stream, c.planes, c.RWc, c.chunk_elems, c.n_rows, word,
-                       vars, f, t, n, c.agg);
+                       vars, f, t, n, c.agg, c.d_perm);
     GSS_HIP(hipGetLastError());
     c.mutations++;
 }
@@ -353,7 +354,7 @@ static void launch_set_vars(Ctx &c, const uint32_t *d_vars, uint32_t n_vars, con
     const uint32_t nw = (first_slot + n_slots - 1) / 64 - first_slot / 64 + 1;
     const uint64_t threads = (uint64_t)n_vars * nw;
     hipLaunchKernelGGL(k_set_vars, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, c.stream, c.planes, c.RWc,
-                       c.chunk_elems, d_vars, n_vars, d_vals, first_slot, n_slots, nw, bad, clear_bits);
+                       c.chunk_elems, d_vars, n_vars, d_vals, first_slot, n_slots, nw, bad, clear_bits, c.d_perm);
     GSS_HIP(hipGetLastError());
 }
 
@@ -400,7 +401,7 @@ extern "C" gss_status gss_set_assignments(gss_ctx *ctx, uint32_t first_slot, uin
         GSS_HIP(hipMemcpy2DAsync(stage, pitch, src, V, V, s_hi - s_lo,
                                  dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.stream));
         hipLaunchKernelGGL(k_pack_word, dim3((unsigned)((V + 63) / 64)), dim3(64), 0, c.stream, c.planes, c.RWc,
-                           c.chunk_elems, w, (uint32_t)V, stage, pitch, s_lo, s_hi, bad);
+                           c.chunk_elems, w, (uint32_t)V, stage, pitch, s_lo, s_hi, bad, c.d_perm);
         GSS_HIP(hipGetLastError());
     }
     if (dev) check_flag(c);  // throws, having applied nothing, if a value was invalid

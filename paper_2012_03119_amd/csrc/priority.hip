@@ -242,6 +242,21 @@ __global__ __launch_bounds__(256) void k_prio_observe(ProbeArgs a, uint64_t n_id
     }
 }
 
+// The light form of an observation (activity only): every clause with a record
+// in the last test gets the current bump once, and its hit count is cleared.
+// Runs after k_prio_hits over the same segments.
+__global__ void k_prio_bump(ProbeArgs a, const gss_report *reports, const uint32_t *counts, uint32_t seg_cap,
+                            uint32_t n_segments, float bump) {
+    for (uint32_t s = blockIdx.x; s < n_segments; s += gridDim.x) {
+        const uint32_t n = min(counts[s], seg_cap);
+        const gss_report *seg = reports + (uint64_t)s * seg_cap;
+        for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
+            const uint32_t id = seg[r].clause_id;
+            if (atomicExch(&a.hits[id], 0u) != 0u) a.act[id] += bump;  // the first record of the clause
+        }
+    }
+}
+
 __global__ void k_prio_scale(float *act, uint64_t n, float f) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         act[i] *= f;
@@ -426,6 +441,63 @@ void priority_removed(Ctx &c, const uint32_t *ids, uint32_t n) {
     c.stage_done(st);
 }
 
+void priority_reserve(Ctx &c, uint64_t n_ids) {
+    if (c.prio) grow(c, *c.prio, n_ids);
+}
+
+// Grows the bump by 1/decay after an observed run; activities and bump are
+// scaled by 1e-20 together once the bump passes 1e20 (float range).
+static void next_bump(Ctx &c, Priority &p) {
+    p.run++;
+    p.bump /= p.decay;
+    if (p.bump > 1e20) {
+        if (p.n_ids)
+            hipLaunchKernelGGL(k_prio_scale, dim3((unsigned)std::min<uint64_t>(grid_of(p.n_ids), 65536)), dim3(256), 0,
+                               c.stream, p.act, p.n_ids, 1e-20f);
+        GSS_HIP(hipGetLastError());
+        p.bump *= 1e-20;
+    }
+}
+
+void priority_bump_hits(Ctx &c) {
+    Priority &p = need_prio(c);
+    if (c.last_waves && c.n_reports) {
+        const dim3 grid(std::min<uint32_t>(c.last_waves, 65535));
+        hipLaunchKernelGGL(k_prio_hits, grid, dim3(256), 0, c.stream, args_of(p), c.reports, c.seg_counts, c.seg_cap,
+                           c.last_waves);
+        GSS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_prio_bump, grid, dim3(256), 0, c.stream, args_of(p), c.reports, c.seg_counts, c.seg_cap,
+                           c.last_waves, (float)p.bump);
+        GSS_HIP(hipGetLastError());
+    }
+    p.observed_serial = c.test_serial;
+    next_bump(c, p);
+}
+
+std::vector<uint32_t> priority_evict(Ctx &c, uint64_t keep) {
+    Priority &p = need_prio(c);
+    if (c.live <= keep) return {};
+    // activities of every issued id to the host; the live ones sorted, least active first
+    std::vector<float> act(p.n_ids);
+    if (p.n_ids) GSS_HIP(hipMemcpyAsync(act.data(), p.act, p.n_ids * 4, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    std::vector<uint32_t> live;
+    live.reserve(c.live);
+    for (uint64_t id = 0; id < c.id_loc.size(); ++id)
+        if (c.id_loc[id] != kNoLoc) live.push_back((uint32_t)id);
+    const uint64_t n_rm = live.size() - keep;
+    auto before = [&](uint32_t x, uint32_t y) { return act[x] != act[y] ? act[x] < act[y] : x < y; };
+    std::nth_element(live.begin(), live.begin() + (ptrdiff_t)(n_rm - 1), live.end(), before);
+    std::vector<uint32_t> rm(live.begin(), live.begin() + (ptrdiff_t)n_rm);
+    gss_ctx *ctx = reinterpret_cast<gss_ctx *>(&c);
+    for (uint64_t k = 0; k < n_rm; k += 1u << 24) {
+        const uint32_t m = (uint32_t)std::min<uint64_t>(n_rm - k, 1u << 24);
+        const gss_status rc = gss_remove_clauses(ctx, rm.data() + k, m);
+        if (rc != GSS_OK) throw Error(rc, c.last_error);
+    }
+    return rm;
+}
+
 uint32_t priority_schedule(Ctx &c) {
     Priority &p = need_prio(c);
     GSS_REQUIRE(p.score_epoch > 0, GSS_ERR_STATE, "a scheduled test needs a scoring first (gss_priority_score)");
@@ -579,15 +651,7 @@ extern "C" gss_status gss_priority_observe(gss_ctx *ctx) {
                            p.cfg.seed, p.sx, p.sy, p.cfg.sample_capacity, p.counters, (float)p.bump);
     GSS_HIP(hipGetLastError());
     p.observed_serial = c.test_serial;
-    p.run++;
-    p.bump /= p.decay;
-    if (p.bump > 1e20) {  // keep activities in float range: scale all of them and the bump
-        if (p.n_ids)
-            hipLaunchKernelGGL(k_prio_scale, dim3((unsigned)std::min<uint64_t>(grid_of(p.n_ids), 65536)), dim3(256), 0,
-                               c.stream, p.act, p.n_ids, 1e-20f);
-        GSS_HIP(hipGetLastError());
-        p.bump *= 1e-20;
-    }
+    next_bump(c, p);
     GSS_API_END
 }
 
@@ -766,25 +830,9 @@ extern "C" gss_status gss_priority_reduce(gss_ctx *ctx, uint64_t keep, uint64_t 
     Ctx &c = *c_;
     Priority &p = need_prio(c);
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    (void)p;
     if (out_removed) *out_removed = 0;
-    if (c.live <= keep) return GSS_OK;
-    // activities of every issued id to the host; the live ones sorted, least active first
-    std::vector<float> act(p.n_ids);
-    if (p.n_ids) GSS_HIP(hipMemcpyAsync(act.data(), p.act, p.n_ids * 4, hipMemcpyDeviceToHost, c.stream));
-    c.sync();
-    std::vector<uint32_t> live;
-    live.reserve(c.live);
-    for (uint64_t id = 0; id < c.id_loc.size(); ++id)
-        if (c.id_loc[id] != kNoLoc) live.push_back((uint32_t)id);
-    const uint64_t n_rm = live.size() - keep;
-    auto before = [&](uint32_t x, uint32_t y) { return act[x] != act[y] ? act[x] < act[y] : x < y; };
-    std::nth_element(live.begin(), live.begin() + (ptrdiff_t)(n_rm - 1), live.end(), before);
-    std::vector<uint32_t> rm(live.begin(), live.begin() + (ptrdiff_t)n_rm);
-    for (uint64_t k = 0; k < n_rm; k += 1u << 24) {
-        const uint32_t m = (uint32_t)std::min<uint64_t>(n_rm - k, 1u << 24);
-        const gss_status rc = gss_remove_clauses(ctx, rm.data() + k, m);
-        if (rc != GSS_OK) throw Error(rc, c.last_error);
-    }
+    const uint64_t n_rm = priority_evict(c, keep).size();
     if (out_removed) *out_removed = n_rm;
     GSS_API_END
 }

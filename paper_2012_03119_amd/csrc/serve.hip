@@ -183,6 +183,7 @@ void gss_server::run() {
     Prepared ins;
     std::vector<uint32_t> ids;
     bool held = false;  // inserts held back by the HBM budget until something is removed
+    bool evict_spent = false;
     bool pending = false;
     uint64_t run_id = 0;
     double del_due = 0.0, last = now();
@@ -278,6 +279,24 @@ void gss_server::run() {
         }
     };
 
+    // Activity eviction: removes the least active live clauses until evict_keep
+    // of them are left; logged as a "V n" line followed by the removal.
+    auto evict = [&]() {
+        const uint64_t keep = (uint64_t)std::floor(cfg.evict_keep * (double)C.live);
+        const std::vector<uint32_t> out = priority_evict(C, keep);
+        if (out.empty()) return;
+        res.evicted += out.size();
+        res.evictions++;
+        if (log) {
+            std::fprintf(log, "V %zu\nR %zu", out.size(), out.size());
+            for (uint32_t id : out) std::fprintf(log, " %u", id);
+            std::fputc('\n', log);
+        }
+        live.clear();  // rebuilt from the store: evictions are rare
+        for (uint64_t id = 0; id < C.id_loc.size(); ++id)
+            if (C.id_loc[id] != kNoLoc) live.push_back((uint32_t)id);
+    };
+
     // Store changes are queued once per run, behind the run just launched, so
     // their host work overlaps it (and the upload ring is not drained).
     auto change_store = [&]() {
@@ -322,6 +341,20 @@ void gss_server::run() {
                     if (e.code != GSS_ERR_CAPACITY) throw;
                     admitted = false;
                 }
+                if (!admitted && cfg.evict_keep > 0 && !evict_spent) {
+                    // Section 3.7: the least active clauses leave to make room (the
+                    // activities of the runs completed so far), then the insert is retried
+                    evict();
+                    admitted = true;
+                    try {
+                        commit_clauses(C, ins, ids.data());
+                    } catch (const Error &e) {
+                        if (e.code != GSS_ERR_CAPACITY) throw;
+                        admitted = false;
+                    }
+                }
+                // an eviction that made no room is not repeated until an insert is admitted
+                evict_spent = !admitted && cfg.evict_keep > 0;
                 if (admitted) {
                     res.inserted += n;
                     live.insert(live.end(), ids.begin(), ids.end());
@@ -330,7 +363,9 @@ void gss_server::run() {
                             std::fprintf(log, "A %u %llu", ids[i], (unsigned long long)(ins.offs[i + 1] - ins.offs[i]));
                             for (uint64_t k = ins.offs[i]; k < ins.offs[i + 1]; ++k) {
                                 const uint32_t code = ins.codes[k];
-                                std::fprintf(log, " %d", (code & 1) ? -(int32_t)(code >> 1) : (int32_t)(code >> 1));
+                                // the caller's variable numbers, not the internal ones
+                                const int32_t v = (int32_t)C.external_var(code >> 1);
+                                std::fprintf(log, " %d", (code & 1) ? -v : v);
                             }
                             std::fputc('\n', log);
                         }
@@ -417,6 +452,12 @@ void gss_server::run() {
                     inflight[p] = -1.0;
                 }
             return;
+        }
+        // activities (Section 3.7): every clause with a record in this run is
+        // bumped, queued before the next run overwrites the segments
+        if (cfg.evict_keep > 0) {
+            priority_bump_hits(C);
+            if (log) std::fprintf(log, "B %llu\n", (unsigned long long)this_run);
         }
         // routes the records of the run fetched before this one, then starts this
         // run's fetch; the next run is launched without waiting for it
@@ -546,7 +587,15 @@ extern "C" gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cf
     GSS_REQUIRE((cfg->test_flags & ~known) == 0, GSS_ERR_INVALID_ARG, "test flag not allowed for served runs");
     GSS_REQUIRE(cfg->delete_fraction >= 0 && cfg->delete_fraction <= 1, GSS_ERR_INVALID_ARG,
                 "delete_fraction must be in [0, 1]");
+    GSS_REQUIRE(cfg->evict_keep >= 0 && cfg->evict_keep < 1, GSS_ERR_INVALID_ARG, "evict_keep must be in [0, 1)");
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
+    if (cfg->evict_keep > 0 && !c.prio) {  // activities live in the priority state
+        gss_priority_config pc{};
+        pc.n_sources = cfg->n_producers;
+        pc.seed = cfg->seed;
+        const gss_status rc = gss_priority_enable(ctx, &pc);
+        if (rc != GSS_OK) throw Error(rc, c.last_error);
+    }
     auto s = std::make_unique<gss_server>();
     s->c = &c;
     s->cfg = *cfg;
@@ -589,6 +638,7 @@ extern "C" gss_status gss_server_start(gss_ctx *ctx, const gss_server_config *cf
         throw;
     }
     s->t0 = Clock::now();
+    c.serving = true;
     gss_server *raw = s.release();
     raw->manager = std::thread([raw] { raw->run(); });
     *out = raw;
@@ -659,7 +709,7 @@ extern "C" gss_status gss_server_insert(gss_server *s, uint32_t producer, const 
     GSS_REQUIRE(offsets[0] == 0, GSS_ERR_INVALID_ARG, "offsets[0] must be 0");
     const int64_t V = s->V;
     Prepared p;  // validation and encoding here, on the producer's thread
-    prepare_clauses(V, lits, offsets, n, p);
+    prepare_clauses(V, lits, offsets, n, p, s->c->perm());
     std::lock_guard<std::mutex> g(s->imu);
     if (s->queue.codes.size() + p.codes.size() > s->q_limit) {
         s->n_refused += n;
@@ -694,6 +744,7 @@ extern "C" gss_status gss_server_stop(gss_server *s, gss_serve_result *out) {
     s->stop = true;
     if (s->manager.joinable()) s->manager.join();
     Ctx &c = *s->c;
+    c.serving = false;
     gss_serve_result r = s->res;
     r.snapshots = s->n_snapshots.load();
     r.refused = s->n_refused.load();

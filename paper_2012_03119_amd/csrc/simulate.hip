@@ -218,6 +218,7 @@ extern "C" gss_status gss_serve_simulate(gss_ctx *ctx, const gss_sim_config *cfg
     sc.delete_fraction = cfg->delete_fraction;
     sc.seed = cfg->seed;
     sc.log_path = cfg->log_path;
+    sc.evict_keep = cfg->evict_keep;
     gss_server *srv = nullptr;
     gss_status rc = gss_server_start(ctx, &sc, &srv);
     if (rc != GSS_OK) return rc;

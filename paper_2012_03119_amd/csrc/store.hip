@@ -184,7 +184,8 @@ static bool compact_bucket(Ctx &c, int bi) {
 }
 
 // ---- ingest, part 1: validation and encoding (no context state; any thread)
-void prepare_clauses(int64_t num_vars, const int32_t *lits, const uint64_t *offsets, uint32_t n, Prepared &p) {
+void prepare_clauses(int64_t num_vars, const int32_t *lits, const uint64_t *offsets, uint32_t n, Prepared &p,
+                     const uint32_t *perm) {
     p.clear();
     if (n == 0) return;
     GSS_REQUIRE(lits && offsets, GSS_ERR_INVALID_ARG, "null argument");
@@ -214,7 +215,7 @@ void prepare_clauses(int64_t num_vars, const int32_t *lits, const uint64_t *offs
                 const int64_t l = lits[offsets[i] + k];
                 const int64_t v = l < 0 ? -l : l;
                 ok &= v >= 1 && v <= num_vars;
-                dst[k] = lit_code((int32_t)l);
+                dst[k] = (perm && ok) ? 2u * perm[v] + (l < 0 ? 1u : 0u) : lit_code((int32_t)l);
             }
             if (!ok) {
                 std::lock_guard<std::mutex> g(mu);
@@ -334,6 +335,9 @@ void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
         c.host_stage(stage_bytes);
     }
 
+    // the priority state of the new ids first: its growth may fail on the budget
+    priority_reserve(c, next + n);
+
     // ---- capacity: every bucket that must grow, checked against the budget up front
     uint64_t new_cap[kMaxBuckets] = {0};
     uint64_t grow_bytes = 0;
@@ -436,7 +440,7 @@ extern "C" gss_status gss_add_clauses(gss_ctx *ctx, const int32_t *lits, const u
     if (n == 0) return GSS_OK;
     GSS_REQUIRE(lits && offsets && out_ids, GSS_ERR_INVALID_ARG, "null argument");
     Prepared p;
-    prepare_clauses(c.cfg.num_vars, lits, offsets, n, p);
+    prepare_clauses(c.cfg.num_vars, lits, offsets, n, p, c.perm());
     commit_clauses(c, p, out_ids);
     GSS_API_END
 }

@@ -98,6 +98,7 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     a.dense = c.dense;
     a.agg = nullptr;
     a.aggu = nullptr;
+    a.wave_stats = (flags & GSS_TEST_COUNT) ? c.wave_stats : nullptr;
     if (flags & GSS_TEST_AGGREGATE) {
         if (!c.agg_valid) {
             agg_rebuild(c, 0, 2ull * ((uint64_t)c.cfg.num_vars + 1));
@@ -210,7 +211,8 @@ static void complete(Ctx &c) {
 // Checks flags and prepares a test; returns false when there is nothing to launch.
 static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
     const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_SORTED | GSS_TEST_DENSE |
-                           GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT | GSS_TEST_SCHEDULED | GSS_TEST_AGGREGATE;
+                           GSS_TEST_NO_REGROW | GSS_TEST_NO_HOT | GSS_TEST_SCHEDULED | GSS_TEST_AGGREGATE |
+                           GSS_TEST_COUNT;
     GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "unknown gss_test flag");
     GSS_REQUIRE(!((flags & GSS_TEST_SORTED) && (flags & GSS_TEST_DENSE)), GSS_ERR_INVALID_ARG,
                 "GSS_TEST_SORTED orders records; GSS_TEST_DENSE produces none");
@@ -227,10 +229,14 @@ static bool begin_test(Ctx &c, uint32_t flags, Launch &L) {
         launch_fill_u64(c, c.dense, c.dense_rows * c.W, 0);
         c.dense_ids = c.id_loc.size();
     }
+    if ((flags & GSS_TEST_COUNT) && !c.wave_stats) c.wave_stats = (uint32_t *)c.dalloc((uint64_t)c.max_waves * 8);
     uint64_t act = 0;
     for (uint64_t x : c.h_active) act += __builtin_popcountll(x);
     uint64_t lits = 0;
     for (const auto &B : c.buckets) lits += B.n_lits;
+    // hot rows: ranked by occurrences the first time, and again whenever the
+    // store has doubled since (never while a server owns the context)
+    if (c.hot_rows && !(flags & GSS_TEST_NO_HOT) && !c.serving && lits > 2 * c.ranked_lits) rank_vars(c);
     c.stats.last_pairs = c.live * act;
     c.stats.last_literals = lits;
     c.tested = false;
@@ -277,6 +283,19 @@ static uint64_t end_test(Ctx &c, uint32_t flags, bool launched) {
                 kept = c.h_summary[2];
             }
         }
+    }
+    c.stats.last_gathers = c.stats.last_gather_bytes = c.stats.last_agg_settled = 0;
+    if (launched && (flags & GSS_TEST_COUNT)) {  // the kernel's own counts, summed over its wavefronts
+        std::vector<uint32_t> ws(2ull * c.last_waves);
+        GSS_HIP(hipMemcpyAsync(ws.data(), c.wave_stats, ws.size() * 4, hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+        for (size_t i = 0; i < ws.size(); i += 2) {
+            c.stats.last_gathers += ws[i];
+            c.stats.last_agg_settled += ws[i + 1];
+        }
+        // a lane reads min(row words, 4) words of a row per gather; trigger mode two rows
+        const uint64_t per = 8ull * std::min<uint32_t>(c.RWc, 4) * ((flags & GSS_TEST_TRIGGER) ? 2 : 1);
+        c.stats.last_gather_bytes = c.stats.last_gathers * per;
     }
     c.stats.tests_run++;
     c.test_serial++;

@@ -36,6 +36,8 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
     uint64_t *const dense_out = dense ? a.dense : nullptr;
     uint32_t produced = 0;  // records of this wavefront (uniform)
     uint32_t bi = 0;
+    Counts cnt;  // GSS_TEST_COUNT (uniform)
+    cnt.on = a.wave_stats != nullptr;
 
     const uint32_t last = a.n_tiles - 1;
     uint32_t t = wave;
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
         typename Ts::Tile nxt;
         ts.open(descs, a.n_buckets, bi, tn < a.n_tiles ? tn : last, nxt);  // prefetch, unconditionally
         if constexpr (!WIDE) {
-            produced = ts.run(cur, seg, seg_cap, produced, early_exit, dense_out);
+            produced = ts.run(cur, seg, seg_cap, produced, early_exit, dense_out, cnt);
         } else {
             // rows of more than 64 words: the tile is tested chunk by chunk, each
             // chunk's 4096 slots a super-group; with the aggregate pre-test, first
@@ -55,12 +57,18 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
             const uint64_t sup = AGG ? ts.super_mask(cur, a.gmask) : a.gmask;
             for (uint32_t g = 0; g < a.G; ++g)
                 if (__ballot((sup >> g) & 1u))
-                    produced = ts.run(cur, seg, seg_cap, produced, early_exit, dense_out, g, sup);
+                    produced = ts.run(cur, seg, seg_cap, produced, early_exit, dense_out, cnt, g, sup);
         }
         t = tn;
         cur = nxt;
     }
-    if (lane == 0) a.seg_counts[wave] = produced;
+    if (lane == 0) {
+        a.seg_counts[wave] = produced;
+        if (a.wave_stats) {
+            a.wave_stats[2 * wave] = cnt.gathers;
+            a.wave_stats[2 * wave + 1] = cnt.settled;
+        }
+    }
 }
 
 // summary[3] receives the verdict of the asynchronous updates queued before the

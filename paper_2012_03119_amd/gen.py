@@ -319,10 +319,13 @@ def paper(seed: int = 2, n_clauses: int = 4_000_000, n_vars: int = 1_000_000, n_
                     meta=dict(assigned_fraction=frac, planted_rate=planted_rate))
 
 
-def zipf_weights(n_vars: int, s: float = 1.1) -> np.ndarray:
-    """Cumulative Zipf(s) distribution over variables 1..n_vars (variable 1 most
-    frequent)."""
+def zipf_weights(n_vars: int, s: float = 1.1, shuffle_seed=None) -> np.ndarray:
+    """Cumulative Zipf(s) distribution over variables 1..n_vars: variable 1 most
+    frequent, or, with ``shuffle_seed``, the same frequencies dealt to the
+    variables in a seeded random order."""
     w = 1.0 / np.arange(1, n_vars + 1, dtype=np.float64) ** s
+    if shuffle_seed is not None:
+        w = w[np.random.default_rng(shuffle_seed).permutation(n_vars)]
     c = np.cumsum(w)
     return c / c[-1]
 

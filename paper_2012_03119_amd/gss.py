@@ -82,7 +82,8 @@ class gss_stats(ctypes.Structure):
         "tests_run", "last_pairs", "last_reports", "last_literals", "live_clauses", "active_slots",
         "device_bytes", "compactions", "regrows", "kernel_launches")] + [
         ("last_kernel_ms", ctypes.c_double), ("total_kernel_ms", ctypes.c_double),
-        ("timed_launches", ctypes.c_uint64)]
+        ("timed_launches", ctypes.c_uint64), ("last_gathers", ctypes.c_uint64),
+        ("last_gather_bytes", ctypes.c_uint64), ("last_agg_settled", ctypes.c_uint64)]
 
 
 class gss_schedule(ctypes.Structure):
@@ -105,17 +106,19 @@ MLP_FEATURES = 12
 MLP_PARAMS = 5057
 GSS_TEST_SCHEDULED = 128
 GSS_TEST_AGGREGATE = 256
+GSS_TEST_COUNT = 512
 
 
 class gss_server_config(ctypes.Structure):
     _fields_ = [("n_producers", ctypes.c_uint32), ("test_flags", ctypes.c_uint32),
                 ("delete_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("log_path", ctypes.c_char_p), ("max_queued_lits", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint64 * 3)]
+                ("evict_keep", ctypes.c_double), ("reserved", ctypes.c_uint64 * 2)]
 
 
 SERVE_RESULT_COUNTS = ("snapshots", "tested", "dropped", "runs", "overflowed_runs", "inserted", "refused",
-                       "deleted", "reports", "pairs", "live_end", "device_bytes_end", "delta_bytes")
+                       "deleted", "reports", "pairs", "live_end", "device_bytes_end", "delta_bytes", "evicted",
+                       "evictions")
 SERVE_RESULT_TIMES = ("wall_s", "gpu_ms", "mean_ms", "p50_ms", "p99_ms", "max_ms", "admit_ms", "wait_ms",
                       "fetch_ms", "route_ms", "store_ms", "launch_ms")
 
@@ -132,7 +135,7 @@ class gss_sim_config(ctypes.Structure):
                 ("duration_s", ctypes.c_double), ("snapshot_rate", ctypes.c_double),
                 ("redraw_fraction", ctypes.c_double), ("insert_rate", ctypes.c_double),
                 ("delete_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("log_path", ctypes.c_char_p), ("reserved", ctypes.c_uint64 * 4)]
+                ("log_path", ctypes.c_char_p), ("evict_keep", ctypes.c_double), ("reserved", ctypes.c_uint64 * 3)]
 
 
 _lib = None
@@ -162,6 +165,7 @@ def load_library(path: Optional[str] = None):
         "gss_clear_slots": ([P, u32, u32], ctypes.c_int32),
         "gss_test": ([P, u32, P], ctypes.c_int32),
         "gss_test_noalloc": ([P, u32, P, u64, P], ctypes.c_int32),
+        "gss_rank_vars": ([P, P, P], ctypes.c_int32),
         "gss_fetch_reports": ([P, P, u64, P], ctypes.c_int32),
         "gss_fetch_masks": ([P, P, u32, P], ctypes.c_int32),
         "gss_get_stats": ([P, ctypes.POINTER(gss_stats)], ctypes.c_int32),
@@ -361,6 +365,14 @@ def gss_test(ctx, flags: int = 0) -> int:
     return n.value
 
 
+def gss_rank_vars(ctx):
+    """Ranks the variables for LDS staging now; returns (literal occurrences on
+    the staged variables, literals stored) at that ranking."""
+    hot, lits = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(ctx, load_library().gss_rank_vars(ctx, ctypes.byref(hot), ctypes.byref(lits)))
+    return hot.value, lits.value
+
+
 def gss_test_noalloc(ctx, flags: int, ptr: int, cap: int) -> int:
     """The test with its records stitched into device memory at address ptr
     (room for cap 16-byte records); returns the exact number of records."""
@@ -496,9 +508,9 @@ def gss_mlp_train(ctx, params, x, y, order, *, batch: int, lr: float = 1e-3, bet
 
 
 def gss_server_start(ctx, n_producers: int, *, test_flags: int = 0, delete_fraction: float = 0.0, seed: int = 0,
-                     log_path: Optional[str] = None, max_queued_lits: int = 0):
+                     log_path: Optional[str] = None, max_queued_lits: int = 0, evict_keep: float = 0.0):
     cfg = gss_server_config(n_producers, test_flags, delete_fraction, seed,
-                            log_path.encode() if log_path else None, max_queued_lits)
+                            log_path.encode() if log_path else None, max_queued_lits, evict_keep)
     srv = ctypes.c_void_p()
     _check(ctx, load_library().gss_server_start(ctx, ctypes.byref(cfg), ctypes.byref(srv)))
     return srv
@@ -543,9 +555,9 @@ def gss_server_stop(ctx, srv) -> dict:
 
 def gss_serve_simulate(ctx, *, n_threads: int, duration_s: float, snapshot_rate: float, redraw_fraction: float,
                        insert_rate: float, delete_fraction: float, seed: int, test_flags: int = 0,
-                       log_path: Optional[str] = None) -> dict:
+                       log_path: Optional[str] = None, evict_keep: float = 0.0) -> dict:
     cfg = gss_sim_config(n_threads, test_flags, duration_s, snapshot_rate, redraw_fraction, insert_rate,
-                         delete_fraction, seed, log_path.encode() if log_path else None)
+                         delete_fraction, seed, log_path.encode() if log_path else None, evict_keep)
     r = gss_serve_result()
     _check(ctx, load_library().gss_serve_simulate(ctx, ctypes.byref(cfg), ctypes.byref(r)))
     return r.as_dict()
@@ -684,6 +696,9 @@ class Context:
         n = gss_test(self.ctx, flags)  # on an error the queued inputs stay held (harmless if applied)
         self._held = []
         return n
+
+    def rank_vars(self):
+        return gss_rank_vars(self.ctx)
 
     def test_noalloc(self, flags: int, out) -> int:
         """gss_test_noalloc into `out`, a contiguous CUDA tensor whose bytes hold

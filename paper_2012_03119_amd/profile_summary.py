@@ -4,6 +4,8 @@
   traffic  FETCH_SIZE / WRITE_SIZE counter runs of a workload and of a plain
            device copy of known size -> HBM bytes per launch of one kernel, with
            the counters scaled by what they read for the copy
+  counters any --pmc runs -> per-launch averages of one kernel's counters, with
+           bytes by request size and the L2 hit rate where those were taken
 
 Usage:
   python -m paper_2012_03119_amd.profile_summary stats DIR --command "..." > out.md
@@ -122,6 +124,46 @@ def traffic(args) -> None:
     print(f"| traffic / algorithmic | {rec['traffic_over_alg']:.2f} |")
 
 
+def counters(args) -> None:
+    """Per-launch averages of every counter in the given --pmc runs for one kernel,
+    and what they add up to: bytes read from the memory fabric by request size,
+    the L2 hit rate, and the sectors the L1s asked the L2 for."""
+    def is_kernel(name, grid):
+        name = name.removeprefix("void ")
+        return name.startswith(f"gss::{args.kernel}<") or name.startswith(f"gss::{args.kernel}(")
+
+    avg = {}
+    for d in args.dirs:
+        names = sorted({r["Counter_Name"] for r in _csv(d, "counter_collection.csv")})
+        for n in names:
+            v = _per_dispatch(d, n, is_kernel)
+            avg[n.removesuffix("_sum")] = (sum(v) / len(v), len(v))
+    print(f"# L2 and memory-fabric counters of gss::{args.kernel}: {args.title}\n")
+    print(f"Command: `{args.command}`\n")
+    print(f"Kernel sources sha256[:16]: `{kernel_hash()}`\n")
+    print("| counter | per launch | launches |")
+    print("|---|---:|---:|")
+    for n, (v, k) in sorted(avg.items()):
+        print(f"| `{n}` | {v:,.0f} | {k} |")
+    g = {n: v for n, (v, _) in avg.items()}
+    rows = []
+    if all(k in g for k in ("TCC_EA0_RDREQ_32B", "TCC_EA0_RDREQ_64B", "TCC_EA0_RDREQ_128B")):
+        rd = 32 * g["TCC_EA0_RDREQ_32B"] + 64 * g["TCC_EA0_RDREQ_64B"] + 128 * g["TCC_EA0_RDREQ_128B"]
+        rows.append(("bytes read from the fabric (32/64/128-byte requests)", f"{rd / 1e6:,.1f} MB"))
+    if "TCC_EA0_WRREQ" in g and "TCC_EA0_WRREQ_64B" in g:
+        wr = 64 * g["TCC_EA0_WRREQ_64B"] + 32 * (g["TCC_EA0_WRREQ"] - g["TCC_EA0_WRREQ_64B"])
+        rows.append(("bytes written to the fabric (64- and 32-byte requests)", f"{wr / 1e6:,.1f} MB"))
+    if "TCC_HIT" in g and "TCC_MISS" in g:
+        rows.append(("L2 hit rate", f"{g['TCC_HIT'] / (g['TCC_HIT'] + g['TCC_MISS']):.3f}"))
+    if "TCC_READ_SECTORS" in g:
+        rows.append(("bytes the L1s asked the L2 for (32-byte sectors)", f"{32 * g['TCC_READ_SECTORS'] / 1e6:,.1f} MB"))
+    if rows:
+        print("\n| derived | value |")
+        print("|---|---:|")
+        for a, b in rows:
+            print(f"| {a} | {b} |")
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -135,8 +177,13 @@ def main(argv=None) -> None:
         t.add_argument(a, required=True)
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
     t.add_argument("--kernel", default="k_test")
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="")
+    c.add_argument("--kernel", default="k_test")
     args = ap.parse_args(argv)
-    {"stats": stats, "traffic": traffic}[args.cmd](args)
+    {"stats": stats, "traffic": traffic, "counters": counters}[args.cmd](args)
 
 
 if __name__ == "__main__":

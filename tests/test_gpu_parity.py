@@ -769,3 +769,50 @@ def test_store_growth_under_a_budget_releases_old_arrays():
         got = gpu_dense(ctx, 120_000)
         assert ctx.store_info()["device_bytes"] <= 2 * final
     _check(got, oracle.masks(lits, offs, vals))
+
+
+def _uniform_word(value, n_vars):
+    """64 slots in which every variable takes `value`."""
+    return np.full((64, n_vars), value, dtype=np.int8)
+
+
+@pytest.mark.parametrize("max_slots", [128, 1024])
+def test_kernel_counts_in_closed_form(max_slots):
+    """GSS_TEST_COUNT: the plane rows the lanes read and the words the aggregate
+    pre-test settled, on assignments where both are known in closed form: every
+    variable F in every slot (every clause of positive literals stays falsified to
+    its end), then every variable T in word 0 and U elsewhere (the first literal
+    kills every word; the pre-test settles every word before any read)."""
+    n_vars = 300
+    rng = np.random.default_rng(17)
+    lengths = rng.integers(1, 30, 2000)
+    lits, offs = gen.random_clauses(rng, lengths, n_vars)
+    lits = np.abs(lits).astype(np.int32)  # positive literals only
+    n, W = len(lengths), max_slots // 64
+    RW = 1 << (W - 1).bit_length()  # stored words per row
+    lanes = max(1, RW // 4)  # lanes per clause: each reads 4 words of a row (the whole row when shorter)
+    per_row = 8 * min(RW, 4)
+    C = gss.GSS_TEST_COUNT
+    with new_context(n_vars, max_slots) as ctx:
+        ctx.add_clauses(lits, offs)
+        ctx.set_assignments(0, np.concatenate([_uniform_word(-1, n_vars)] * W))
+        assert ctx.test(C) == n * W
+        st = ctx.stats()
+        assert st["last_gathers"] == lanes * int(lengths.sum())
+        assert st["last_gather_bytes"] == st["last_gathers"] * per_row and st["last_agg_settled"] == 0
+        assert ctx.test(C | gss.GSS_TEST_AGGREGATE) == n * W
+        st = ctx.stats()
+        assert st["last_gathers"] == lanes * 4 * int(((lengths + 3) // 4).sum())
+        assert st["last_agg_settled"] == 0
+        ctx.set_assignments(0, np.concatenate([_uniform_word(1, n_vars)] + [_uniform_word(0, n_vars)] * (W - 1)))
+        assert ctx.test(C) == 0
+        assert ctx.stats()["last_gathers"] == lanes * n  # one read kills every word
+        assert ctx.test(C | gss.GSS_TEST_NO_EARLY_EXIT) == 0
+        assert ctx.stats()["last_gathers"] == lanes * int(lengths.sum())
+        assert ctx.test(C | gss.GSS_TEST_AGGREGATE) == 0
+        st = ctx.stats()
+        assert st["last_gathers"] == 0 and st["last_agg_settled"] == n * W
+        ctx.test(C | gss.GSS_TEST_TRIGGER)  # (unit clauses trigger on the U words)
+        assert ctx.stats()["last_gather_bytes"] == 2 * ctx.stats()["last_gathers"] * per_row > 0
+        ctx.test()  # without the flag the counts are 0
+        assert ctx.stats()["last_gathers"] == 0

@@ -293,3 +293,93 @@ def test_server_argument_errors():
     n = ctx.test()
     assert n == len(want)
     ctx.close()
+
+
+def check_evictions(path, n_initial, decay=0.999):
+    """Replays the activities of a served log as the device computes them (float32
+    additions of the float32 bump) and checks that every eviction ("V n" and the
+    removal after it) took the n least active live clauses, the older among
+    equals (Section 3.7).  Returns the number of evictions."""
+    with open(path) as fh:
+        lines = fh.read().splitlines()
+    hit = {}  # run -> clauses with a record in it
+    for l in lines:
+        if l.startswith("P "):
+            p = l.split()
+            hit.setdefault(int(p[1]), set()).add(int(p[2]))
+    act = {}
+    live = set(range(n_initial))
+    bump, n_ev, i = 1.0, 0, 0
+    while i < len(lines):
+        p = lines[i].split()
+        i += 1
+        if not p:
+            continue
+        if p[0] == "A":
+            live.add(int(p[1]))
+        elif p[0] == "B":
+            b = np.float32(bump)
+            for cid in hit.get(int(p[1]), ()):
+                act[cid] = np.float32(act.get(cid, np.float32(0)) + b)
+            bump /= decay
+        elif p[0] == "V":
+            n = int(p[1])
+            q = lines[i].split()
+            i += 1
+            assert q[0] == "R" and int(q[1]) == n
+            gone = [int(x) for x in q[2:]]
+            order = sorted(live, key=lambda c: (float(act.get(c, np.float32(0))), c))
+            assert set(gone) == set(order[:n]), "an eviction did not take the least active clauses"
+            live -= set(gone)
+            n_ev += 1
+        elif p[0] == "R":
+            live -= {int(x) for x in p[2:]}
+    return n_ev
+
+
+def _class_bytes(lits_offs, T=64):
+    """Bytes of each length class of a store as the library lays it out: a slot
+    of stride S (the power of two >= max(length, 4)) holds S codes of 4 bytes
+    plus 8 bytes of metadata; slots come in whole tiles of T."""
+    _, offs = lits_offs
+    lengths = np.diff(offs)
+    stride = np.maximum(4, 2 ** np.ceil(np.log2(np.maximum(lengths, 1))).astype(np.int64))
+    out = {}
+    for s in np.unique(stride):
+        n = int((stride == s).sum())
+        out[int(s)] = -(-n // T) * T * (int(s) * 4 + 8)
+    return out
+
+
+def test_activity_eviction_admits_inserts_under_a_tight_budget(tmp_path):
+    W, P, V = 4, 4, 3000
+    lits, offs = _store(51, 20_000, V)
+    # the device bytes of this store with its activity state, and a budget with
+    # room to compact its largest length class but not to grow the classes
+    ctx0 = gss.Context(V, W * 64)
+    ctx0.add_clauses(lits, offs)
+    ctx0.priority_enable(n_sources=P)
+    ctx0.set_active(np.full(W, 2**64 - 1, dtype=np.uint64))
+    ctx0.test()
+    used = ctx0.store_info()["device_bytes"]
+    ctx0.close()
+    largest = max(_class_bytes((lits, offs)).values())
+    budget = used + int(0.9 * largest) + (2 << 20)
+    ctx = gss.Context(V, W * 64, hbm_budget_bytes=budget)
+    ctx.add_clauses(lits, offs)
+    log = tmp_path / "evict.log"
+    print(f"[serve] eviction case: budget {budget} bytes, largest class {largest}", flush=True)
+    res = ctx.serve_simulate(n_threads=P, duration_s=1.5, snapshot_rate=25.0, redraw_fraction=0.05,
+                             insert_rate=2000.0, delete_fraction=0.0, seed=9, log_path=str(log), evict_keep=0.5)
+    counts, clauses, F, T = replay(str(log), lits, offs, V, W)
+    assert res["evictions"] >= 1 and res["evicted"] > 0
+    assert counts.get("V", 0) == res["evictions"]
+    assert counts["B"] == counts["E"] >= 5  # every completed run bumped the activities
+    assert check_evictions(str(log), len(offs) - 1) == res["evictions"]
+    # inserts went on after the budget first bound
+    assert res["inserted"] == counts["A"] > 0
+    tags = [l.split(" ", 1)[0] for l in log.read_text().splitlines()]
+    assert "A" in tags[tags.index("V"):], "no insert was admitted after the first eviction"
+    assert res["live_end"] == ctx.store_info()["live_clauses"] == len(clauses)
+    assert res["device_bytes_end"] <= budget
+    ctx.close()
