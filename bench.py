@@ -379,8 +379,16 @@ def bench_learned(args, torch, gss):
     agg_negative_trigger_ratio = agg_negative_trigger / (n_s * P)
     del s_var, s_pos, s_clause, s_k
     ctx.set_active(np.full(P, 2**64 - 1, dtype=np.uint64))
+    # what the test kernel's pre-test itself settled on the whole store (GSS_TEST_COUNT)
+    settled = {}
+    for name, fl in (("falsified", 0), ("trigger", gss.GSS_TEST_TRIGGER)):
+        ctx.test(fl | gss.GSS_TEST_AGGREGATE | gss.GSS_TEST_COUNT)
+        st = ctx.stats()
+        settled[name] = st["last_agg_settled"] / (st["live_clauses"] * P)
     log(f"learned: store and snapshots ready in {time.perf_counter() - t0:.1f} s; aggregate-negative ratio "
-        f"{agg_negative_ratio:.4f} (trigger {agg_negative_trigger_ratio:.4f}) over {n_s} clauses x {P} words")
+        f"{agg_negative_ratio:.4f} (trigger {agg_negative_trigger_ratio:.4f}) over {n_s} clauses x {P} words; "
+        f"the kernel's pre-test settled {settled['falsified']:.4f} (trigger {settled['trigger']:.4f}) of all "
+        f"(clause, word) pairs")
     blocks = (V + 63) // 64
 
     def advance():  # every word redraws 5% of its variables, in runs of 64
@@ -497,7 +505,12 @@ def bench_learned(args, torch, gss):
                    "rescore_every": K, "update_every": args.learn_update, "aggregate": bool(args.aggregate),
                    "aggregate_negative_ratio": agg_negative_ratio,
                    "aggregate_negative_ratio_trigger": agg_negative_trigger_ratio,
-                   "aggregate_negative_how": f"falsified aggregate test of {n_s} clauses x {P} words, first snapshot"},
+                   "aggregate_negative_how": f"falsified aggregate test of {n_s} clauses x {P} words, first snapshot",
+                   "kernel_pretest_settled_ratio": settled["falsified"],
+                   "kernel_pretest_settled_ratio_trigger": settled["trigger"],
+                   "kernel_pretest_how": "GSS_TEST_COUNT on the whole store, first snapshot: (clause, word) pairs "
+                                         "the test kernel's aggregate pre-test settled before any gather killed "
+                                         "them, over live clauses x words"},
         "plain_kernel_ms": plain_ms, "schedules": out_sched,
         "missed_hit_rate": out_sched["learned"]["missed_hit_rate"],
         "speedup_vs_plain": out_sched["learned"]["speedup_vs_plain"],

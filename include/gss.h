@@ -352,7 +352,9 @@ const char *gss_batch_last_error(const gss_batch *batch);
 gss_status gss_batch_set_schedule(gss_batch *batch, const gss_schedule *schedule);
 
 /* Tests every store of the batch.  flags: GSS_TEST_TRIGGER, GSS_TEST_NO_EARLY_EXIT,
- * GSS_TEST_NO_REGROW, GSS_TEST_GRAPH.  A member with a gss_test_async in flight:
+ * GSS_TEST_NO_REGROW, GSS_TEST_GRAPH, GSS_TEST_AGGREGATE (each store's aggregate
+ * bits are brought up to date before the launch; no LDS staging in a batch, whose
+ * wavefronts move between stores).  A member with a gss_test_async in flight:
  * GSS_ERR_STATE (nothing queued).  out_n_reports (n entries, may be NULL)
  * receives each store's record count.  A store whose report segments overflow is
  * grown and the whole batch repeated (unless GSS_TEST_NO_REGROW: then

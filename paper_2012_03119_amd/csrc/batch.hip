@@ -29,6 +29,8 @@ struct StoreDesc {
     uint32_t seg_cap;
     uint32_t pad;
     const uint32_t *deferred;  // the context's verdict of queued updates (reported after the test)
+    const void *agg;           // GSS_TEST_AGGREGATE: the context's aggregate bits (null otherwise)
+    const void *aggu;          // and, in trigger mode, its canBeUndef bits
 };
 
 // A run of `count` consecutive tiles of one store, starting at its tile `tile0`;
@@ -40,20 +42,37 @@ struct SchedSeg {
     uint32_t count;
 };
 
-template <int LPC, int WPL, int MODE>
-__device__ uint32_t batch_tile(const StoreDesc &st, uint32_t tile, gss_report *seg, uint32_t produced,
-                               uint32_t early_exit) {
-    using Ts = Tester<LPC, WPL, MODE, false>;
-    const Ts ts(threadIdx.x & 63, st.planes, st.active, st.W, 0, nullptr, 0u, nullptr, nullptr);
-    uint32_t bi = 0;
-    typename Ts::Tile cur;
-    ts.open(st.descs, st.n_buckets, bi, tile, cur);
+// Lanes per clause of a store whose rows hold RW words: one per 32-byte sector.
+__device__ inline uint32_t lanes_per_clause(uint32_t RW) { return RW <= 4 ? 1u : RW / 4; }
+
+template <int LPC, int WPL, int MODE, bool AGG>
+__device__ uint32_t batch_run(const StoreDesc &st, const TileRef &cur, gss_report *seg, uint32_t produced,
+                              uint32_t early_exit) {
+    using Ts = Tester<LPC, WPL, MODE, false, AGG>;
+    const Ts ts(threadIdx.x & 63, st.planes, st.active, st.W, 0, nullptr, 0u, st.agg, st.aggu);
     Counts none;
     return ts.run(cur, seg, st.seg_cap, produced, early_exit, nullptr, none);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test_batch(const StoreDesc *__restrict__ stores,
+// The store and store-local tile of global tile g: segs[lo].begin <= g < segs[lo + 1].begin.
+__device__ inline void locate(const SchedSeg *segs, uint32_t n_segs, uint32_t g, uint32_t &store, uint32_t &tile) {
+    uint32_t lo = 0, hi = n_segs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (segs[mid].begin <= g) lo = mid; else hi = mid;
+    }
+    store = segs[lo].store;
+    tile = segs[lo].tile0 + (g - segs[lo].begin);
+}
+
+// Each wavefront walks the global tiles g = wave, wave + N, ... and, like the
+// single-store kernel, opens the next tile (its store located, its metadata and
+// first codes in flight) while it tests the current one.
+// The falsified kernel fits 5 wavefronts per SIMD in 96 registers without
+// spilling (4 unconstrained); the others would spill, and keep their own count.
+template <int MODE, bool AGG>
+__global__ __launch_bounds__(kTestWavesPerBlock * 64)
+__attribute__((amdgpu_waves_per_eu(MODE == 0 && !AGG ? 5 : 1))) void k_test_batch(const StoreDesc *__restrict__ stores,
                                                                          uint32_t n_stores,
                                                                          const SchedSeg *__restrict__ segs,
                                                                          uint32_t n_segs, uint32_t total,
@@ -64,27 +83,37 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test_batch(const St
     __syncthreads();
     const uint32_t n_waves = gridDim.x * kTestWavesPerBlock;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * kTestWavesPerBlock + wib);
-    for (uint32_t g = wave; g < total; g += n_waves) {
-        uint32_t lo = 0, hi = n_segs;  // segs[lo].begin <= g < segs[hi].begin
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (segs[mid].begin <= g) lo = mid; else hi = mid;
-        }
-        const SchedSeg sg = segs[lo];
-        const StoreDesc &st = stores[sg.store];
-        const uint32_t tile = sg.tile0 + (g - sg.begin);
+    auto open = [&](uint32_t g, uint32_t &store, TileRef &tl) {
+        uint32_t tile, bi = 0;
+        locate(segs, n_segs, g, store, tile);
+        const StoreDesc &st = stores[store];
+        const uint32_t lpc = lanes_per_clause(st.RW);
+        open_tile(st.descs, st.n_buckets, bi, tile, lane / lpc, 64 / lpc, tl);
+    };
+    uint32_t g = wave, s_cur = 0;
+    TileRef cur;
+    if (g < total) open(g, s_cur, cur);
+    while (g < total) {
+        const uint32_t gn = g + n_waves;
+        uint32_t s_nxt = s_cur;
+        TileRef nxt = cur;
+        if (gn < total) open(gn, s_nxt, nxt);  // in flight while the current tile is tested
+        const StoreDesc &st = stores[s_cur];
         gss_report *const seg = st.reports + (uint64_t)wave * st.seg_cap;
-        uint32_t produced = counts[wib][sg.store];
+        uint32_t produced = counts[wib][s_cur];
         switch (st.RW) {
-        case 1: produced = batch_tile<1, 1, MODE>(st, tile, seg, produced, early_exit); break;
-        case 2: produced = batch_tile<1, 2, MODE>(st, tile, seg, produced, early_exit); break;
-        case 4: produced = batch_tile<1, 4, MODE>(st, tile, seg, produced, early_exit); break;
-        case 8: produced = batch_tile<2, 4, MODE>(st, tile, seg, produced, early_exit); break;
-        case 16: produced = batch_tile<4, 4, MODE>(st, tile, seg, produced, early_exit); break;
-        case 32: produced = batch_tile<8, 4, MODE>(st, tile, seg, produced, early_exit); break;
-        default: produced = batch_tile<16, 4, MODE>(st, tile, seg, produced, early_exit); break;
+        case 1: produced = batch_run<1, 1, MODE, AGG>(st, cur, seg, produced, early_exit); break;
+        case 2: produced = batch_run<1, 2, MODE, AGG>(st, cur, seg, produced, early_exit); break;
+        case 4: produced = batch_run<1, 4, MODE, AGG>(st, cur, seg, produced, early_exit); break;
+        case 8: produced = batch_run<2, 4, MODE, AGG>(st, cur, seg, produced, early_exit); break;
+        case 16: produced = batch_run<4, 4, MODE, AGG>(st, cur, seg, produced, early_exit); break;
+        case 32: produced = batch_run<8, 4, MODE, AGG>(st, cur, seg, produced, early_exit); break;
+        default: produced = batch_run<16, 4, MODE, AGG>(st, cur, seg, produced, early_exit); break;
         }
-        counts[wib][sg.store] = produced;
+        counts[wib][s_cur] = produced;
+        g = gn;
+        s_cur = s_nxt;
+        cur = nxt;
     }
     for (uint32_t s = lane; s < n_stores; s += 64) stores[s].seg_counts[wave] = counts[wib][s];
 }
@@ -160,7 +189,7 @@ struct Run {
 };
 
 // Fills the descriptor tables of every store and the schedule of global tiles.
-void plan(gss_batch &b) {
+void plan(gss_batch &b, uint32_t flags) {
     const uint32_t n = (uint32_t)b.ctxs.size();
     std::vector<std::vector<Run>> runs(n);
     b.n_tiles.assign(n, 0);
@@ -197,6 +226,8 @@ void plan(gss_batch &b) {
         sd.seg_cap = c.seg_cap;
         sd.pad = 0;
         sd.deferred = deferred_flag(c);
+        sd.agg = (flags & GSS_TEST_AGGREGATE) ? c.agg : nullptr;
+        sd.aggu = (flags & GSS_TEST_AGGREGATE) && (flags & GSS_TEST_TRIGGER) ? c.aggu : nullptr;
     }
 
     std::vector<SchedSeg> segs;
@@ -255,6 +286,31 @@ void plan(gss_batch &b) {
 
 using BatchFn = void (*)(const StoreDesc *, uint32_t, const SchedSeg *, uint32_t, uint32_t, uint32_t);
 
+BatchFn batch_kernel(uint32_t flags) {
+    const bool agg = flags & GSS_TEST_AGGREGATE;
+    if (flags & GSS_TEST_TRIGGER) return agg ? k_test_batch<1, true> : k_test_batch<1, false>;
+    return agg ? k_test_batch<0, true> : k_test_batch<0, false>;
+}
+
+// With the aggregate pre-test: each store's bits brought up to date on the shared
+// stream before the launch (bulk plane updates leave them stale).  Returns true
+// when a store's bits were allocated now (a captured graph holds the old pointers).
+bool refresh_aggregates(gss_batch &b, uint32_t flags) {
+    if (!(flags & GSS_TEST_AGGREGATE)) return false;
+    bool moved = false;
+    for (Ctx *c : b.ctxs) {
+        if (!c->agg_valid) {
+            agg_rebuild(*c, 0, 2ull * ((uint64_t)c->cfg.num_vars + 1));
+            c->agg_valid = true;
+        }
+        if ((flags & GSS_TEST_TRIGGER) && !c->aggu_valid) {
+            moved |= c->aggu == nullptr;
+            aggu_rebuild(*c);
+        }
+    }
+    return moved;
+}
+
 uint32_t grid_for(gss_batch &b, BatchFn fn) {
     Ctx &c0 = *b.ctxs[0];
     int fit = 0;
@@ -273,7 +329,7 @@ void enqueue(gss_batch &b, uint32_t flags) {
                            b.stream));
     GSS_HIP(hipMemcpyAsync(b.d_stores, b.h_stores, (size_t)n * sizeof(StoreDesc), hipMemcpyHostToDevice, b.stream));
     GSS_HIP(hipMemcpyAsync(b.d_segs, b.h_segs, (size_t)b.n_segs * sizeof(SchedSeg), hipMemcpyHostToDevice, b.stream));
-    const BatchFn fn = (flags & GSS_TEST_TRIGGER) ? k_test_batch<1> : k_test_batch<0>;
+    const BatchFn fn = batch_kernel(flags);
     hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kTestWavesPerBlock * 64), 0, b.stream, b.d_stores, n, b.d_segs, b.n_segs,
                        b.total, (flags & GSS_TEST_NO_EARLY_EXIT) ? 0u : 1u);
     GSS_HIP(hipGetLastError());
@@ -294,12 +350,12 @@ bool same_schedule(const gss_schedule &x, const gss_schedule &y) {
 bool run_once(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
     const uint32_t n = (uint32_t)b.ctxs.size();
     const bool use_graph = flags & GSS_TEST_GRAPH;
-    bool valid = use_graph && b.graph_valid && b.graph_flags == flags && same_schedule(b.graph_sched, b.sched);
+    const bool moved = refresh_aggregates(b, flags);
+    bool valid = !moved && use_graph && b.graph_valid && b.graph_flags == flags && same_schedule(b.graph_sched, b.sched);
     for (uint32_t s = 0; valid && s < n; ++s) valid = b.versions[s] == b.ctxs[s]->version;
     if (!valid) {
-        plan(b);
-        const BatchFn fn = (flags & GSS_TEST_TRIGGER) ? k_test_batch<1> : k_test_batch<0>;
-        b.grid = grid_for(b, fn);
+        plan(b, flags);
+        b.grid = grid_for(b, batch_kernel(flags));
     }
     if (use_graph && !valid) {
         free_graph(b);
@@ -458,7 +514,8 @@ extern "C" gss_status gss_batch_set_schedule(gss_batch *b, const gss_schedule *s
 
 extern "C" gss_status gss_batch_test(gss_batch *b, uint32_t flags, uint64_t *out_n_reports) {
     GSS_BATCH_BEGIN(b)
-    const uint32_t known = GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_REGROW | GSS_TEST_GRAPH;
+    const uint32_t known =
+        GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_REGROW | GSS_TEST_GRAPH | GSS_TEST_AGGREGATE;
     GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "flag not supported by gss_batch_test");
     // a member's asynchronous test would have its report segments overwritten
     for (const Ctx *c : b_->ctxs)

@@ -232,32 +232,36 @@ void Ctx::release_deferred() {
     deferred_frees.resize(k);
 }
 
-Ctx::Staged Ctx::stage_upload(size_t bytes) {
+Ctx::Staged Ctx::stage_upload(size_t bytes, bool host_only) {
     const int k = ring_next;
     ring_next = (ring_next + 1) % kRing;
     RingSlot &s = ring[k];
     if (s.busy && tests_completed < s.free_after) sync();  // its readers may still be queued
     s.busy = false;
-    if (bytes > s.bytes) {
-        const size_t want = std::max<size_t>({bytes, 2 * s.bytes, (size_t)1 << 16});
-        char *d = (char *)dalloc(want);  // may raise CAPACITY; the slot is unchanged then
-        char *h = nullptr;
+    const bool grow_d = !host_only && bytes > s.dbytes, grow_h = bytes > s.hbytes;
+    char *d = nullptr, *h = nullptr;
+    void *hd = nullptr;
+    if (grow_d) d = (char *)dalloc(std::max<size_t>({bytes, 2 * s.dbytes, (size_t)1 << 16}));  // may raise CAPACITY
+    if (grow_h) {
+        const size_t want = std::max<size_t>({bytes, 2 * s.hbytes, (size_t)1 << 16});
         if (hipHostMalloc((void **)&h, want, hipHostMallocDefault) != hipSuccess) {
             dfree(d);
             throw Error(GSS_ERR_DEVICE, "hipHostMalloc failed for the upload ring");
         }
-        void *hd = nullptr;
         if (hipHostGetDevicePointer(&hd, h, 0) != hipSuccess) {
             (void)hipHostFree(h);
             dfree(d);
             throw Error(GSS_ERR_DEVICE, "hipHostGetDevicePointer failed for the upload ring");
         }
-        dfree(s.d);
         if (s.h) (void)hipHostFree(s.h);
-        s.d = d;
         s.h = h;
         s.hd = (char *)hd;
-        s.bytes = want;
+        s.hbytes = want;
+    }
+    if (grow_d) {
+        dfree(s.d);
+        s.d = d;
+        s.dbytes = std::max<size_t>({bytes, 2 * s.dbytes, (size_t)1 << 16});
     }
     return Staged{s.h, s.d, k, s.hd};
 }
@@ -298,6 +302,8 @@ static void destroy_ctx(Ctx *c) {
     c->dfree(c->var_bits);
     c->dfree(c->d_perm);
     c->dfree(c->wave_stats);
+    c->dfree(c->sched_list);
+    c->dfree(c->sched_counts);
     c->dfree(c->active);
     c->dfree(c->reports);
     c->dfree(c->seg_counts);
@@ -318,6 +324,11 @@ static void destroy_ctx(Ctx *c) {
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
+    if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
+    if (c->copy_stream) {
+        (void)hipStreamSynchronize(c->copy_stream);
+        (void)hipStreamDestroy(c->copy_stream);
+    }
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

@@ -102,6 +102,10 @@ struct BucketDesc {
     uint32_t tile_begin;   // global index of the bucket's first tile
     const uint32_t *low;   // schedule: bit per slot, set for low-priority clauses (null: no schedule)
     uint64_t low_bytes;
+    // scheduled test: the slots this run tests (a list built on the device) and
+    // their number (null: every slot, the tile order)
+    const uint32_t *list;
+    const uint32_t *list_count;
 };
 
 struct TestArgs {
@@ -224,6 +228,9 @@ struct Ctx {
     uint32_t external_var(uint32_t v) const { return h_iperm.empty() ? v : h_iperm[v]; }
 
     uint32_t *wave_stats = nullptr;  // [max_waves][2], allocated by the first counted test
+    uint32_t *sched_list = nullptr;  // scheduled test: slots tested this run, per length class
+    uint64_t sched_list_cap = 0;
+    uint32_t *sched_counts = nullptr;  // [kMaxBuckets]: their number
 
     uint64_t *dense = nullptr;
     uint64_t dense_rows = 0;
@@ -237,6 +244,10 @@ struct Ctx {
 
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     hipEvent_t ev_stage = nullptr;  // recorded after the last queued use of the staging buffers
+    // queued deltas: their variable lists go up on a copy stream of their own while
+    // the test ahead of them runs (created by the first gss_set_var_values_async)
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_copy = nullptr;
     uint64_t tests_launched = 0;    // serial of the last queued test (its finalize kernel writes it to h_summary[4])
     uint64_t tests_completed = 0;   // serial of the last test seen complete (or of all, after a sync)
     bool pending = false;           // gss_test_async issued, gss_test_wait not yet called
@@ -286,12 +297,16 @@ struct Ctx {
         char *h = nullptr;
         char *hd = nullptr;
         char *d = nullptr;
-        size_t bytes = 0;
+        size_t hbytes = 0;  // pinned host bytes
+        size_t dbytes = 0;  // device bytes (may be fewer: slots taken host-only)
         uint64_t free_after = 0;  // free once this test serial has completed
         bool busy = false;
     } ring[kRing];
     int ring_next = 0;
-    Staged stage_upload(size_t bytes);           // a free slot of at least `bytes`
+    // A free slot of at least `bytes`.  host_only: only its pinned host memory is
+    // used (kernels read it over the bus), so taking it allocates no device memory
+    // and cannot fail on the HBM budget (.d may then be smaller or null).
+    Staged stage_upload(size_t bytes, bool host_only = false);
     void stage_done(const Staged &s);            // its consumers are queued
 };
 
@@ -353,7 +368,7 @@ std::vector<uint32_t> priority_evict(Ctx &c, uint64_t keep);
 bool rank_vars(Ctx &c);
 // Writes the n records at src (device) into dst (device) ordered by (clause id,
 // word); synchronises the stream.
-void sort_records(Ctx &c, const gss_report *src, uint64_t n, gss_report *dst);
+void sort_records(Ctx &c, gss_report *src, uint64_t n, gss_report *dst);  // src is overwritten
 uint32_t *deferred_flag(Ctx &c);
 uint32_t read_deferred(Ctx &c);
 void report_deferred(Ctx &c, uint32_t verdict);

@@ -328,13 +328,10 @@ __global__ void k_check_vars(const uint32_t *vars, uint32_t n, uint32_t *bits, u
 }
 
 // Both checks of a queued delta in one launch: the first var_blocks workgroups
-// (dispatched first: their reads cross the bus) take the variable list, which
-// they read from pinned host memory and copy into the device array the later
-// kernels read (no separate copy to wait for), marking repeats (bit 2 of *bad);
-// the others check the truth values (bit 1).
+// take the variable list (already on the device), marking repeats (bit 2 of
+// *bad); the others check the truth values (bit 1).
 __global__ __launch_bounds__(256) void k_check_delta(const int8_t *vals, uint64_t n_vals, uint32_t var_blocks,
-                                                     const uint32_t *host_vars, uint32_t *vars, uint32_t n,
-                                                     uint32_t *bits, uint32_t *bad) {
+                                                     const uint32_t *vars, uint32_t n, uint32_t *bits, uint32_t *bad) {
     if (blockIdx.x >= var_blocks) {
         const uint32_t b = blockIdx.x - var_blocks, value_blocks = gridDim.x - var_blocks;
         if (values_invalid(vals, n_vals, b * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)value_blocks * blockDim.x))
@@ -343,8 +340,7 @@ __global__ __launch_bounds__(256) void k_check_delta(const int8_t *vals, uint64_
     }
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t v = host_vars[i], m = 1u << (v & 31);
-    vars[i] = v;
+    const uint32_t v = vars[i], m = 1u << (v & 31);
     if (atomicOr(&bits[v >> 5], m) & m) atomicOr(bad, 2u);
 }
 
@@ -473,17 +469,25 @@ extern "C" gss_status gss_set_var_values_async(gss_ctx *ctx, uint32_t first_slot
         c.var_bits = (uint32_t *)c.dalloc(((uint64_t)c.cfg.num_vars / 32 + 1) * 4);
         launch_fill_u32(c, c.var_bits, (uint64_t)c.cfg.num_vars / 32 + 1, 0);
     }
-    // the list goes into a pinned ring slot, read by the checking kernel itself
-    // (a copy queued behind a running test would start only when the test ends)
+    // the list goes up through a pinned ring slot on the copy stream, which runs
+    // while the test ahead of it executes (on the context stream, a copy would
+    // start only when that test ends); the checking kernel waits for it
+    if (!c.copy_stream) {
+        GSS_HIP(hipStreamCreateWithFlags(&c.copy_stream, hipStreamNonBlocking));
+        GSS_HIP(hipEventCreateWithFlags(&c.ev_copy, hipEventDisableTiming));
+    }
     const size_t bytes = (size_t)n_vars * 4;
     const Ctx::Staged st = c.stage_upload(bytes);
     std::memcpy(st.h, vars, bytes);
     uint32_t *dv = (uint32_t *)st.d;
+    GSS_HIP(hipMemcpyAsync(dv, st.h, bytes, hipMemcpyHostToDevice, c.copy_stream));
+    GSS_HIP(hipEventRecord(c.ev_copy, c.copy_stream));
+    GSS_HIP(hipStreamWaitEvent(c.stream, c.ev_copy, 0));
     uint32_t *bad = deferred_flag(c);  // sticky: set by this check or an earlier one not yet reported
     const uint64_t nv = (uint64_t)n_vars * n_slots;
     const uint32_t var_blocks = (n_vars + 255) / 256;
     hipLaunchKernelGGL(k_check_delta, dim3(var_blocks + fill_grid((nv + 15) / 16)), dim3(256), 0, c.stream, values, nv,
-                       var_blocks, (const uint32_t *)st.hd, dv, n_vars, c.var_bits, bad);
+                       var_blocks, dv, n_vars, c.var_bits, bad);
     GSS_HIP(hipGetLastError());
     launch_set_vars(c, dv, n_vars, values, first_slot, n_slots, bad, c.var_bits);
     c.agg_valid = false;

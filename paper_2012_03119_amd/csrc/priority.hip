@@ -433,10 +433,10 @@ void priority_added(Ctx &c, uint64_t first, uint32_t n, const uint64_t *offsets)
 void priority_removed(Ctx &c, const uint32_t *ids, uint32_t n) {
     if (!c.prio || n == 0) return;
     Priority &p = *c.prio;
-    const Ctx::Staged st = c.stage_upload((size_t)n * 4);
+    // read over the bus from pinned memory: a removal takes no device memory
+    const Ctx::Staged st = c.stage_upload((size_t)n * 4, true);
     std::memcpy(st.h, ids, (size_t)n * 4);
-    GSS_HIP(hipMemcpyAsync(st.d, st.h, (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
-    hipLaunchKernelGGL(k_prio_kill, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), (const uint32_t *)st.d, n);
+    hipLaunchKernelGGL(k_prio_kill, dim3(grid_of(n)), dim3(256), 0, c.stream, args_of(p), (const uint32_t *)st.hd, n);
     GSS_HIP(hipGetLastError());
     c.stage_done(st);
 }

@@ -104,6 +104,53 @@ void ensure_host(Mail &m, uint32_t need, uint32_t limit) {
     }
 }
 
+// ---- records routed by word on the device: a counting sort of the run's kept
+//      records by their 64-slot word (a served producer owns one word), so that
+//      the host hands each producer one contiguous block.
+
+// counts[w] += records of word w (counts zeroed before).
+__global__ __launch_bounds__(256) void k_route_count(const gss_report *reports, const uint32_t *seg_counts,
+                                                     uint32_t seg_cap, uint32_t n_segments, uint32_t *counts) {
+    __shared__ uint32_t h[kChunkWords];
+    if (threadIdx.x < kChunkWords) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t s = blockIdx.x; s < n_segments; s += gridDim.x) {
+        const uint32_t n = min(seg_counts[s], seg_cap);
+        const gss_report *seg = reports + (uint64_t)s * seg_cap;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&h[seg[i].word], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kChunkWords && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+}
+
+// One wavefront: offsets[w] = records of the words before w (offsets[W] = all),
+// and the placement cursors start there.
+__global__ void k_route_scan(const uint32_t *counts, uint32_t W, uint32_t *cursor, unsigned long long *offsets) {
+    if (threadIdx.x == 0) {
+        unsigned long long run = 0;
+        for (uint32_t w = 0; w < W; ++w) {
+            offsets[w] = run;
+            cursor[w] = (uint32_t)run;
+            run += counts[w];
+        }
+        offsets[W] = run;
+    }
+}
+
+// Every kept record to its word's block (order inside a block unspecified).
+__global__ __launch_bounds__(256) void k_route_place(const gss_report *reports, const uint32_t *seg_counts,
+                                                     uint32_t seg_cap, uint32_t n_segments, uint32_t *cursor,
+                                                     gss_report *out) {
+    for (uint32_t s = blockIdx.x; s < n_segments; s += gridDim.x) {
+        const uint32_t n = min(seg_counts[s], seg_cap);
+        const gss_report *seg = reports + (uint64_t)s * seg_cap;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const gss_report r = seg[i];
+            out[atomicAdd(&cursor[r.word], 1u)] = r;
+        }
+    }
+}
+
 }  // namespace
 }  // namespace gss
 
@@ -135,6 +182,7 @@ struct gss_server {
     std::thread manager;
     gss_status status = GSS_OK;
     std::string error;
+    std::string manager_error;
     mutable std::mutex emu;
 
     std::atomic<uint64_t> n_snapshots{0}, n_refused{0};
@@ -147,6 +195,7 @@ struct gss_server {
         if (status == GSS_OK) {
             status = code;
             error = msg;
+            manager_error = msg;  // kept: later calls refused by the failed server overwrite `error`
         }
         failed = true;
     }
@@ -162,11 +211,13 @@ void gss_server::run() {
         if (C.id_loc[id] != kNoLoc) live.push_back((uint32_t)id);
     uint64_t rng = cfg.seed * 0x2545F4914F6CDD1Dull + 11;
     std::vector<double> staged(P, -1.0), inflight(P, -1.0);  // arrival of the untested / tested snapshot
-    std::vector<std::vector<gss_report>> route(P);
     // two buffer pairs, used in turn: pinned records (they come back at full link
     // speed) and the device list they are copied from
     gss_report *rec[2] = {nullptr, nullptr}, *fdev[2] = {nullptr, nullptr};
     uint64_t rec_cap[2] = {0, 0}, fdev_cap[2] = {0, 0};
+    // routing by word: device counts, cursors and offsets; pinned copies of the offsets
+    uint32_t *route_dev = nullptr;  // counts [64] | cursor [64] | offsets [65] (u64)
+    unsigned long long *roff[2] = {nullptr, nullptr};
     int next_k = 0;
     struct Fetch {  // the records of a finished run on their way to the host (at most one)
         bool active = false;
@@ -188,6 +239,7 @@ void gss_server::run() {
     uint64_t run_id = 0;
     double del_due = 0.0, last = now();
     const double kernel_ms0 = C.stats.total_kernel_ms;
+    const char *phase = "start";  // what the manager was doing (named in an error)
     auto timed = [&](double &acc, auto &&fn) {
         const double a = now();
         fn();
@@ -334,24 +386,34 @@ void gss_server::run() {
             const uint32_t n = ins.size();
             if (n) {
                 ids.resize(n);
-                bool admitted = true;
-                try {
-                    commit_clauses(C, ins, ids.data());
-                } catch (const Error &e) {
-                    if (e.code != GSS_ERR_CAPACITY) throw;
-                    admitted = false;
-                }
+                // with eviction, the store also leaves room for the manager's own
+                // buffers (records, mailboxes, report segments): a budget that is
+                // nearly used up evicts before the insert
+                const uint64_t budget = C.cfg.hbm_budget_bytes;
+                const uint64_t reserve = cfg.evict_keep > 0 ? budget / 32 : 0;
+                if (cfg.evict_keep > 0 && !evict_spent && budget && C.device_bytes + reserve > budget) evict();
+                // the store may not take the reserve (the budget is lowered during the insert)
+                auto commit = [&]() -> bool {
+                    C.cfg.hbm_budget_bytes = budget - reserve;
+                    try {
+                        commit_clauses(C, ins, ids.data());
+                    } catch (const Error &e) {
+                        C.cfg.hbm_budget_bytes = budget;
+                        if (e.code != GSS_ERR_CAPACITY) throw;
+                        return false;
+                    } catch (...) {
+                        C.cfg.hbm_budget_bytes = budget;
+                        throw;
+                    }
+                    C.cfg.hbm_budget_bytes = budget;
+                    return true;
+                };
+                bool admitted = commit();
                 if (!admitted && cfg.evict_keep > 0 && !evict_spent) {
                     // Section 3.7: the least active clauses leave to make room (the
                     // activities of the runs completed so far), then the insert is retried
                     evict();
-                    admitted = true;
-                    try {
-                        commit_clauses(C, ins, ids.data());
-                    } catch (const Error &e) {
-                        if (e.code != GSS_ERR_CAPACITY) throw;
-                        admitted = false;
-                    }
+                    admitted = commit();
                 }
                 // an eviction that made no room is not repeated until an insert is admitted
                 evict_spent = !admitted && cfg.evict_keep > 0;
@@ -399,9 +461,8 @@ void gss_server::run() {
         }
         const double route_t0 = now();
         const gss_report *r = rec[fq.k];
+        const unsigned long long *off = roff[fq.k];  // producer p's records: r[off[p] .. off[p + 1])
         const uint64_t got = fq.n;
-        for (auto &x : route) x.clear();
-        for (uint64_t i = 0; i < got; ++i) route[r[i].word].push_back(r[i]);
         if (log) {
             for (uint64_t i = 0; i < got; ++i)
                 std::fprintf(log, "P %llu %u %u %llx\n", (unsigned long long)fq.run, r[i].clause_id, r[i].word,
@@ -414,10 +475,7 @@ void gss_server::run() {
             {
                 Producer &pr = prod[p];
                 std::lock_guard<std::mutex> g(pr.omu);
-                if (pr.outbox.empty())
-                    pr.outbox.swap(route[p]);
-                else
-                    pr.outbox.insert(pr.outbox.end(), route[p].begin(), route[p].end());
+                if (got) pr.outbox.insert(pr.outbox.end(), r + off[p], r + off[p + 1]);
                 pr.last_run = fq.run;
             }
             lat.push_back((t - fq.arrivals[p]) * 1e3);
@@ -481,11 +539,24 @@ void gss_server::run() {
             fdev_cap[k] = want;
         }
         timed(res.fetch_ms, [&] {
-            if (n) {
-                queue_stitch(C, fdev[k], n);
+            if (n) {  // the records sorted by word on the device, then to the host with the word offsets
+                uint32_t *counts = route_dev, *cursor = route_dev + kChunkWords;
+                unsigned long long *offs = (unsigned long long *)(route_dev + 2 * kChunkWords);
+                launch_fill_u32(C, counts, kChunkWords, 0);
+                const unsigned grid = std::max<uint32_t>(1, std::min<uint32_t>(C.last_waves, 1024));
+                hipLaunchKernelGGL(k_route_count, dim3(grid), dim3(256), 0, C.stream, C.reports, C.seg_counts,
+                                   C.seg_cap, C.last_waves, counts);
+                GSS_HIP(hipGetLastError());
+                hipLaunchKernelGGL(k_route_scan, dim3(1), dim3(64), 0, C.stream, counts, C.W, cursor, offs);
+                GSS_HIP(hipGetLastError());
+                hipLaunchKernelGGL(k_route_place, dim3(grid), dim3(256), 0, C.stream, C.reports, C.seg_counts,
+                                   C.seg_cap, C.last_waves, cursor, fdev[k]);
+                GSS_HIP(hipGetLastError());
                 GSS_HIP(hipEventRecord(ev_stitched, C.stream));
                 GSS_HIP(hipStreamWaitEvent(fetch_stream, ev_stitched, 0));
                 GSS_HIP(hipMemcpyAsync(rec[k], fdev[k], n * sizeof(gss_report), hipMemcpyDeviceToHost, fetch_stream));
+                GSS_HIP(hipMemcpyAsync(roff[k], offs, (C.W + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                       fetch_stream));
             }
             GSS_HIP(hipEventRecord(ev_fetched[k], fetch_stream));
         });
@@ -499,9 +570,13 @@ void gss_server::run() {
 
     try {
         GSS_HIP(hipSetDevice(C.device));
+        route_dev = (uint32_t *)C.dalloc(2 * kChunkWords * 4 + (kChunkWords + 1) * 8);
+        for (auto &o : roff)
+            GSS_HIP(hipHostMalloc((void **)&o, (kChunkWords + 1) * sizeof(unsigned long long), hipHostMallocDefault));
         double last_change = now();
         for (;;) {
             const bool stopping = stop.load();
+            phase = "taking snapshots";
             if (!stopping) timed(res.admit_ms, admit);
             if (pending) {
                 int done = 0;
@@ -512,6 +587,7 @@ void gss_server::run() {
                     if (!route_fetch(false)) std::this_thread::sleep_for(std::chrono::microseconds(20));
                     continue;
                 }
+                phase = "completing a run";
                 finish();
             }
             if (stopping) {
@@ -531,6 +607,7 @@ void gss_server::run() {
             if (!n_act) {
                 route_fetch(false);
                 if (now() - last_change > 0.005) {
+                    phase = "changing the store";
                     timed(res.store_ms, change_store);
                     last_change = now();
                 }
@@ -538,6 +615,7 @@ void gss_server::run() {
                 continue;
             }
             const double launch_t0 = now();
+            phase = "launching a run";
             apply_deltas();
             gss_status rc = gss_set_active(ctx, act.data());
             if (rc != GSS_OK) throw Error(rc, C.last_error);
@@ -552,11 +630,13 @@ void gss_server::run() {
             pending = true;
             run_id++;
             res.launch_ms += (now() - launch_t0) * 1e3;
+            phase = "changing the store";
             timed(res.store_ms, change_store);
             last_change = now();
         }
     } catch (const Error &e) {
-        fail(e.code, e.what());
+        fail(e.code, std::string(phase) + ": " + e.what() + " (device bytes " + std::to_string(C.device_bytes) +
+                         ", live clauses " + std::to_string(C.live) + ")");
     } catch (const std::bad_alloc &) {
         fail(GSS_ERR_CAPACITY, "host out of memory");
     } catch (const std::exception &e) {
@@ -571,7 +651,9 @@ void gss_server::run() {
     for (int k = 0; k < 2; ++k) {
         if (rec[k]) (void)hipHostFree(rec[k]);
         C.dfree(fdev[k]);
+        if (roff[k]) (void)hipHostFree(roff[k]);
     }
+    C.dfree(route_dev);
     res.gpu_ms = C.stats.total_kernel_ms - kernel_ms0;
 }
 
@@ -773,7 +855,7 @@ extern "C" gss_status gss_server_stop(gss_server *s, gss_serve_result *out) {
     if (s->log) std::fclose(s->log);
     if (out) *out = r;
     const gss_status st = s->status;
-    c.last_error = s->error;
+    c.last_error = st != GSS_OK ? "the server's manager stopped: " + s->manager_error : s->error;
     delete s;
     return st;
 }

@@ -151,8 +151,9 @@ static bool compact_bucket(Ctx &c, int bi) {
     launch_fill_u32(c, lits, cap * S, 0);
     fill_meta(c, meta, cap);
     if (n_new) {
-        // the slot map goes up through a pinned ring slot: nothing waits for the copy
-        const Ctx::Staged st = c.stage_upload(n_new * 8);
+        // the slot map goes up through a pinned ring slot (its host memory only:
+        // within the room checked above): nothing waits for the copy
+        const Ctx::Staged st = c.stage_upload(n_new * 8, true);
         std::memcpy(st.h, old_slot.data(), n_new * 8);
         GSS_HIP(hipMemcpyAsync(dmap, st.h, n_new * 8, hipMemcpyHostToDevice, c.stream));
         c.stage_done(st);
@@ -460,8 +461,10 @@ extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint
         GSS_REQUIRE(i == 0 || sorted[i] != sorted[i - 1], GSS_ERR_UNKNOWN_ID,
                     "clause id " + std::to_string(sorted[i]) + " repeated");
     }
-    // ---- apply (the upload slot first: taking it may raise CAPACITY)
-    const Ctx::Staged st = c.stage_upload((size_t)n * 8);
+    // ---- apply (the kernels read the slot lists from pinned host memory: taking
+    //      the upload slot needs no device memory, so a removal works with the
+    //      HBM budget exhausted)
+    const Ctx::Staged st = c.stage_upload((size_t)n * 8, true);
     std::vector<uint64_t> per[kMaxBuckets];
     for (uint32_t i = 0; i < n; ++i) {
         uint64_t loc = c.id_loc[ids[i]];

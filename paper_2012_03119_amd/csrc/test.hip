@@ -34,8 +34,30 @@ static KernelFn pick_mode(uint32_t rw, int mode, bool hot) {
     return hot ? pick_rw<1, true, AGG>(rw) : pick_rw<1, false, AGG>(rw);
 }
 
-// rw: words of a row in one chunk; wide: more than one chunk (no LDS staging then)
-static KernelFn pick_kernel(uint32_t rw, int mode, bool hot, bool agg, bool wide) {
+// the scheduled test's kernel, which walks the list of the slots a run tests
+template <int MODE, bool HOT, bool AGG>
+static KernelFn pick_rw_list(uint32_t rw) {
+    switch (rw) {
+    case 1: return k_test_list<1, 1, MODE, HOT, AGG>;
+    case 2: return k_test_list<1, 2, MODE, HOT, AGG>;
+    case 4: return k_test_list<1, 4, MODE, HOT, AGG>;
+    case 8: return k_test_list<2, 4, MODE, HOT, AGG>;
+    case 16: return k_test_list<4, 4, MODE, HOT, AGG>;
+    case 32: return k_test_list<8, 4, MODE, HOT, AGG>;
+    default: return k_test_list<16, 4, MODE, HOT, AGG>;
+    }
+}
+
+template <bool AGG>
+static KernelFn pick_mode_list(uint32_t rw, int mode, bool hot) {
+    if (mode == 0) return hot ? pick_rw_list<0, true, AGG>(rw) : pick_rw_list<0, false, AGG>(rw);
+    return hot ? pick_rw_list<1, true, AGG>(rw) : pick_rw_list<1, false, AGG>(rw);
+}
+
+// rw: words of a row in one chunk; wide: more than one chunk (no LDS staging then);
+// listed: a scheduled test that walks the list of the slots it tests
+static KernelFn pick_kernel(uint32_t rw, int mode, bool hot, bool agg, bool wide, bool listed = false) {
+    if (listed) return agg ? pick_mode_list<true>(rw, mode, hot) : pick_mode_list<false>(rw, mode, hot);
     if (wide) {
         if (mode == 0) return agg ? k_test<16, 4, 0, false, true, true> : k_test<16, 4, 0, false, false, true>;
         return agg ? k_test<16, 4, 1, false, true, true> : k_test<16, 4, 1, false, false, true>;
@@ -60,6 +82,23 @@ static Launch prepare(Ctx &c, uint32_t flags) {
     uint32_t nb = 0, tiles = 0;
     const bool sched = (flags & GSS_TEST_SCHEDULED) != 0;
     a.sched_run = sched ? priority_schedule(c) : 0u;
+    // a scheduled test lists the slots it tests (on the device, behind the
+    // schedule bits) so that the clauses sitting out the run take no lanes
+    const bool listed = sched && c.G == 1;
+    uint64_t list_off = 0;
+    if (listed) {
+        uint64_t slots = 0;
+        for (const Bucket &B : c.buckets) slots += B.n_slots;
+        if (slots > c.sched_list_cap) {
+            const uint64_t want = std::max<uint64_t>(slots, c.sched_list_cap + c.sched_list_cap / 2);
+            uint32_t *p = (uint32_t *)c.dalloc(want * 4);
+            c.defer_free(c.sched_list);  // a test queued before may still read it
+            c.sched_list = p;
+            c.sched_list_cap = want;
+        }
+        if (!c.sched_counts) c.sched_counts = (uint32_t *)c.dalloc(kMaxBuckets * 4);
+        launch_fill_u32(c, c.sched_counts, kMaxBuckets, 0);
+    }
     for (int b = 0; b < kMaxBuckets; ++b) {
         const Bucket &B = c.buckets[b];
         if (B.n_slots == 0 || B.n_dead == B.n_slots) continue;
@@ -73,6 +112,15 @@ static Launch prepare(Ctx &c, uint32_t flags) {
         if (sched) {
             d.low = B.low;
             d.low_bytes = B.low_words * 4;
+        }
+        if (listed) {
+            d.list = c.sched_list + list_off;
+            d.list_count = c.sched_counts + nb;
+            const unsigned grid = (unsigned)((B.n_slots + 1023) / 1024);
+            hipLaunchKernelGGL(k_sched_list, dim3(grid), dim3(256), 0, c.stream, B.meta, B.low, B.n_slots, a.sched_run,
+                               c.sched_list + list_off, c.sched_counts + nb);
+            GSS_HIP(hipGetLastError());
+            list_off += B.n_slots;
         }
         h[nb++] = d;
         tiles += (uint32_t)((B.n_slots + c.T - 1) / c.T);
@@ -115,13 +163,13 @@ static Launch prepare(Ctx &c, uint32_t flags) {
             a.saggu = c.saggu;
         }
     }
-    // the device copy stays valid while the store is unchanged (schedule bits may move: always upload then)
+    // the device copy stays valid while the store is unchanged (schedule bits and lists may move: always upload then)
     if (nb && (sched || c.desc_version != c.version)) {
         GSS_HIP(hipMemcpyAsync(c.d_desc, h, nb * sizeof(BucketDesc), hipMemcpyHostToDevice, c.stream));
         c.desc_version = sched ? ~0ull : c.version;
     }
     L.descs = (const BucketDesc *)c.d_desc;
-    L.fn = pick_kernel(c.RWc, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot, a.agg != nullptr, c.G > 1);
+    L.fn = pick_kernel(c.RWc, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot, a.agg != nullptr, c.G > 1, listed);
     if (hot) L.lds = (size_t)a.hot_rows * c.RW * 8;
     // persistent: exactly as many workgroups as fit on the device at once
     if (c.occ_fn != (const void *)L.fn || c.occ_lds != L.lds) {  // the query costs host time: cache it

@@ -71,6 +71,102 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test(const BucketDe
     }
 }
 
+// Scheduled test: the wavefronts walk chunks of T listed slots (the clauses this
+// run tests, k_sched_list) instead of tiles, so that clauses sitting out the run
+// take no lanes.  Otherwise as k_test (no rows of more than 64 words).
+template <int LPC, int WPL, int MODE, bool HOT, bool AGG>
+__global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test_list(const BucketDesc *__restrict__ descs,
+                                                                        const TestArgs a, uint32_t early_exit,
+                                                                        uint32_t dense) {
+    using Ts = Tester<LPC, WPL, MODE, HOT, AGG>;
+    extern __shared__ uint64_t lds_rows[];
+    __shared__ uint32_t chunk_begin[kMaxBuckets + 1], count[kMaxBuckets];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t b = 0; b < a.n_buckets; ++b) {
+            count[b] = *descs[b].list_count;
+            chunk_begin[b] = acc;
+            acc += (count[b] + Ts::T - 1) / Ts::T;
+        }
+        chunk_begin[a.n_buckets] = acc;
+    }
+    if constexpr (HOT) {
+        const uint32_t n = a.hot_rows * Ts::RW;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lds_rows[i] = a.planes[i];
+    }
+    __syncthreads();
+    constexpr uint32_t t_log2 = ilog2<Ts::T>();
+    const uint32_t lane = threadIdx.x & 63, j = lane / LPC;
+    const Ts ts(lane, a.planes, a.active, a.W, a.hot_rows, lds_rows, 0u, a.agg, a.aggu);
+    const uint32_t waves_per_block = blockDim.x / 64;
+    const uint32_t n_waves = gridDim.x * waves_per_block;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * waves_per_block +
+                                                         threadIdx.x / 64);
+    gss_report *const seg = a.reports + (uint64_t)wave * a.seg_cap;
+    uint64_t *const dense_out = dense ? a.dense : nullptr;
+    uint32_t produced = 0;
+    uint32_t bi = 0;
+    Counts cnt;
+    cnt.on = a.wave_stats != nullptr;
+    const uint32_t total = chunk_begin[a.n_buckets];
+    uint32_t c = wave;
+    TileRef cur;
+    if (c < total) open_listed(descs, a.n_buckets, bi, c, chunk_begin, count, j, t_log2, cur);
+    while (c < total) {
+        const uint32_t cn = c + n_waves;
+        TileRef nxt = cur;
+        if (cn < total) open_listed(descs, a.n_buckets, bi, cn, chunk_begin, count, j, t_log2, nxt);
+        produced = ts.run(cur, seg, a.seg_cap, produced, early_exit, dense_out, cnt);
+        c = cn;
+        cur = nxt;
+    }
+    if (lane == 0) {
+        a.seg_counts[wave] = produced;
+        if (a.wave_stats) {
+            a.wave_stats[2 * wave] = cnt.gathers;
+            a.wave_stats[2 * wave + 1] = cnt.settled;
+        }
+    }
+}
+
+// The slots of one length class that a scheduled run tests (alive, and not a
+// low-priority clause off its turn: (run + id) % 4 != 0), in slot order within
+// each workgroup's 1024 slots; a workgroup claims its range of the list with one
+// atomic on *count.
+__global__ __launch_bounds__(256) void k_sched_list(const uint2 *meta, const uint32_t *low_bits, uint64_t n_slots,
+                                                    uint32_t run, uint32_t *list, uint32_t *count) {
+    __shared__ uint32_t pre[256];
+    __shared__ uint32_t base;
+    const uint32_t t = threadIdx.x;
+    const uint64_t s0 = (uint64_t)blockIdx.x * 1024 + 4ull * t;
+    uint32_t flags = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint64_t s = s0 + k;
+        if (s < n_slots) {
+            const uint2 m = meta[s];
+            const bool low = (low_bits[s >> 5] >> (s & 31)) & 1u;
+            const bool tested = m.x != 0 && !(low && ((run + m.y) & 3u) != 0);
+            flags |= (tested ? 1u : 0u) << k;
+        }
+    }
+    const uint32_t mine = __builtin_popcount(flags);
+    pre[t] = mine;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {  // inclusive scan
+        const uint32_t v = t >= off ? pre[t - off] : 0u;
+        __syncthreads();
+        pre[t] += v;
+        __syncthreads();
+    }
+    if (t == 255) base = pre[255] ? atomicAdd(count, pre[255]) : 0u;
+    __syncthreads();
+    uint32_t pos = base + pre[t] - mine;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+        if ((flags >> k) & 1u) list[pos++] = (uint32_t)(s0 + k);
+}
+
 // summary[3] receives the verdict of the asynchronous updates queued before the
 // test.  The summary is also written straight into pinned host memory, followed by
 // the test's serial number: the host sees the test complete when the serial

@@ -83,6 +83,69 @@ struct Counts {
     uint32_t settled = 0;
 };
 
+// A tile as one lane sees it: wave-uniform code resource and stride, this lane's
+// byte offset of its clause's codes, its metadata (length, id) and its codes 0..3.
+struct TileRef {
+    __amdgpu_buffer_rsrc_t lits;
+    uint32_t s_log2;
+    uint32_t code_off;
+    uint2 meta;
+    uint4 c0;
+    uint32_t lowword;   // schedule bits of the slot's 32-slot group (0: no schedule)
+    uint32_t lowshift;  // this slot's bit in it
+};
+
+// Locates tile t of a store whose tiles hold T clauses (bi: bucket cursor, only
+// ever advanced) and issues the loads of the metadata and first four codes of
+// the tile's clause j.
+__device__ inline void open_tile(const BucketDesc *descs, uint32_t n_buckets, uint32_t &bi, uint32_t t, uint32_t j,
+                                 uint32_t T, TileRef &tl) {
+    while (bi + 1 < n_buckets && t >= descs[bi + 1].tile_begin) ++bi;
+    const BucketDesc &d = descs[bi];
+    const uint32_t slot = (t - d.tile_begin) * T + j;
+    tl.s_log2 = d.stride_log2;
+    tl.lits = make_rsrc(d.lits, d.lits_bytes);
+    // the tile's codes start at tile * T * S; this clause's first group at j * 16 B
+    tl.code_off = (((t - d.tile_begin) * T) << (d.stride_log2 + 2)) + j * 16u;
+    const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(d.meta, d.meta_bytes), slot * 8u, 0, kStream);
+    tl.meta = make_uint2(m[0], m[1]);
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(tl.lits, tl.code_off, 0, kStream);
+    tl.c0 = make_uint4(q[0], q[1], q[2], q[3]);
+    tl.lowshift = slot & 31u;
+    tl.lowword = d.low ? __builtin_amdgcn_raw_buffer_load_b32(make_rsrc(d.low, d.low_bytes), (slot >> 5) * 4u, 0, kStream)
+                       : 0u;
+}
+
+// The same for a scheduled test, whose wavefronts take the slots of a list
+// (only the clauses this run tests) T at a time: chunk c of the run's chunks,
+// chunk_begin[b] the first chunk of length class b, count[b] its listed slots.
+// Lane j takes list entry (c - chunk_begin[b]) * T + j; past the end it tests
+// nothing (length 0).  A listed slot's codes keep their tile layout: its group g
+// still lies T * 16 bytes after group g - 1.
+__device__ inline void open_listed(const BucketDesc *descs, uint32_t n_buckets, uint32_t &bi, uint32_t c,
+                                   const uint32_t *chunk_begin, const uint32_t *count, uint32_t j, uint32_t t_log2,
+                                   TileRef &tl) {
+    while (bi + 1 < n_buckets && c >= chunk_begin[bi + 1]) ++bi;
+    const BucketDesc &d = descs[bi];
+    const uint32_t e = ((c - chunk_begin[bi]) << t_log2) + j;
+    tl.s_log2 = d.stride_log2;
+    tl.lits = make_rsrc(d.lits, d.lits_bytes);
+    tl.lowword = 0;
+    tl.lowshift = 0;
+    tl.meta = make_uint2(0, 0);
+    tl.c0 = make_uint4(0, 0, 0, 0);
+    tl.code_off = 0;
+    if (e < count[bi]) {
+        const uint32_t slot = d.list[e];
+        const uint32_t tile = slot >> t_log2, jj = slot & ((1u << t_log2) - 1);
+        tl.code_off = ((tile << t_log2) << (d.stride_log2 + 2)) + jj * 16u;
+        const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(d.meta, d.meta_bytes), slot * 8u, 0, kStream);
+        tl.meta = make_uint2(m[0], m[1]);
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(tl.lits, tl.code_off, 0, kStream);
+        tl.c0 = make_uint4(q[0], q[1], q[2], q[3]);
+    }
+}
+
 // Plane words of one lane: WPL consecutive 64-slot words.
 template <int WPL>
 struct Words {
@@ -120,17 +183,7 @@ struct Tester {
     // a row's aggregate bits (one per word), as stored by the context
     using AggT = std::conditional_t<(RW <= 16), uint16_t, std::conditional_t<(RW <= 32), uint32_t, uint64_t>>;
 
-    // a tile: wave-uniform code resource and stride, this lane's byte offset of its
-    // clause's codes, its metadata (length, id) and its codes 0..3
-    struct Tile {
-        __amdgpu_buffer_rsrc_t lits;
-        uint32_t s_log2;
-        uint32_t code_off;
-        uint2 meta;
-        uint4 c0;
-        uint32_t lowword;   // schedule bits of the slot's 32-slot group (0: no schedule)
-        uint32_t lowshift;  // this slot's bit in it
-    };
+    using Tile = TileRef;
 
     uint32_t j;    // clause of this lane within the tile
     uint32_t w0;   // first word of this lane within a chunk
@@ -189,20 +242,7 @@ struct Tester {
     // Locates tile t (bi: bucket cursor, only ever advanced) and issues the loads
     // of this lane's metadata and first four codes.
     __device__ void open(const BucketDesc *descs, uint32_t n_buckets, uint32_t &bi, uint32_t t, Tile &tl) const {
-        while (bi + 1 < n_buckets && t >= descs[bi + 1].tile_begin) ++bi;
-        const BucketDesc &d = descs[bi];
-        const uint32_t slot = (t - d.tile_begin) * T + j;
-        tl.s_log2 = d.stride_log2;
-        tl.lits = make_rsrc(d.lits, d.lits_bytes);
-        // the tile's codes start at tile * T * S; this clause's first group at j * 16 B
-        tl.code_off = (((t - d.tile_begin) * T) << (d.stride_log2 + 2)) + j * 16u;
-        const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(d.meta, d.meta_bytes), slot * 8u, 0, kStream);
-        tl.meta = make_uint2(m[0], m[1]);
-        const auto q = __builtin_amdgcn_raw_buffer_load_b128(tl.lits, tl.code_off, 0, kStream);
-        tl.c0 = make_uint4(q[0], q[1], q[2], q[3]);
-        tl.lowshift = slot & 31u;
-        tl.lowword = d.low ? __builtin_amdgcn_raw_buffer_load_b32(make_rsrc(d.low, d.low_bytes), (slot >> 5) * 4u, 0, kStream)
-                           : 0u;
+        open_tile(descs, n_buckets, bi, t, j, T, tl);
     }
 
     // The top level of the aggregate test (G > 1): for this lane's clause, the

@@ -53,6 +53,26 @@ def _csv(directory: str, suffix: str):
         return list(csv.DictReader(fh))
 
 
+def steady(args) -> None:
+    """Per-kernel durations from the kernel trace, without each kernel's first
+    `skip` launches (cold caches, first-touch page mapping)."""
+    rows = _csv(args.dir, "kernel_trace.csv")
+    by = {}
+    for r in rows:
+        name = r["Kernel_Name"].removeprefix("void ").replace("(anonymous namespace)::", "").split("(")[0]
+        key = int(r.get("Dispatch_Id") or 0)
+        by.setdefault(name, []).append((key, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    print(f"\nSteady state (each kernel's first {args.skip_first} launches left out):\n")
+    print("| kernel | calls | left out | average us | min us | max us |")
+    print("|---|---:|---:|---:|---:|---:|")
+    order = sorted(by.items(), key=lambda kv: -sum(d for _, d in kv[1]))
+    for name, v in order[:args.top]:
+        d = [x for _, x in sorted(v)][args.skip_first:]
+        if not d:
+            continue
+        print(f"| `{name}` | {len(d)} | {len(v) - len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |")
+
+
 def stats(args) -> None:
     rows = _csv(args.dir, "kernel_stats.csv")
     print(f"# Kernel time: {args.title}\n")
@@ -64,6 +84,8 @@ def stats(args) -> None:
         print(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
               f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
               f"{float(r['Percentage']):.1f} |")
+    if args.skip_first:
+        steady(args)
 
 
 def _per_dispatch(directory: str, counter: str, match) -> list:
@@ -172,6 +194,8 @@ def main(argv=None) -> None:
     s.add_argument("--command", required=True)
     s.add_argument("--title", default="")
     s.add_argument("--top", type=int, default=12)
+    s.add_argument("--skip-first", type=int, default=0,
+                   help="also list averages without each kernel's first N launches (needs --kernel-trace output)")
     t = sub.add_parser("traffic")
     for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--bench-json", "--command", "--json"):
         t.add_argument(a, required=True)

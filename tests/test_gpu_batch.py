@@ -180,3 +180,41 @@ def test_batch_refuses_a_member_with_an_async_test_in_flight():
         counts = b.test(0)
         _check_all(items, counts)
 
+
+
+@pytest.mark.parametrize("mode", ["falsified", "trigger"])
+def test_batch_aggregate_pretest_with_graph_replays(mode):
+    """GSS_TEST_AGGREGATE in the batched kernel: Table 1 words (where the
+    aggregate bits are selective), per-store parity with the oracle, and graph
+    replays after bulk updates that leave the bits stale (refreshed before each
+    launch)."""
+    import torch
+    stream = torch.cuda.Stream()
+    rng = np.random.default_rng(21)
+    items = []
+    for i, (n, v, a) in enumerate(STORES[:5]):
+        lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, n), v)
+        vals = np.concatenate([gen.assignments_table1(rng, 64, v) for _ in range(a // 64)])
+        ctx = gss.Context(v, a, stream=stream, report_capacity=1 << 21)  # no regrowth: one capture
+        ctx.add_clauses(lits, offs)
+        ctx.set_assignments(0, vals)
+        items.append([lits, offs, ctx, vals])
+    flags = gss.GSS_TEST_AGGREGATE | (gss.GSS_TEST_TRIGGER if mode == "trigger" else 0)
+    with gss.Batch([it[2] for it in items]) as b:
+        b.set_schedule(gss.GSS_ORDER_INTERLEAVE, 16)
+        for rep in range(3):
+            print(f"batch aggregate mode={mode} replay {rep}", flush=True)
+            counts = b.test(flags | gss.GSS_TEST_GRAPH)
+            for (lits, offs, ctx, vals), cnt in zip(items, counts):
+                got = _dense(ctx, len(offs) - 1)
+                assert int(np.count_nonzero(got)) == int(cnt)
+                want = oracle.masks(lits, offs, vals, mode=mode)
+                assert np.array_equal(got, want), mismatch_summary(got, want)
+            for lits, offs, ctx, vals in items:  # a bulk update: the aggregate bits go stale
+                V = vals.shape[1]
+                flip = 1 + rng.choice(V, max(1, V // 10), replace=False).astype(np.uint32)
+                vals[:, flip - 1] = -vals[:, flip - 1]
+                ctx.set_var_values(0, flip, np.ascontiguousarray(vals[:, flip - 1].T))
+        assert b.info()["captures"] == 1
+    for it in items:
+        it[2].close()

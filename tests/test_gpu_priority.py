@@ -185,7 +185,8 @@ def test_trained_schedule_misses_at_most_one_percent():
         tau = float(pos[int(0.004 * len(pos))]) if len(pos) else 0.5
         n_low = ctx.priority_score(tau)
         assert n_low > n // 4, f"threshold {tau} marks only {n_low} clauses low"
-        hits_plain = hits_sched = 0
+        hits_plain = hits_sched = hits_random = 0
+        bits = lambda r: sum(bin(int(c)).count("1") for c in r["mask"])
         for r in range(16):  # evaluation: scheduled and plain on the same runs
             ctx.set_assignments(0, vals)
             m = ctx.test(gss.GSS_TEST_SCHEDULED)
@@ -196,14 +197,24 @@ def test_trained_schedule_misses_at_most_one_percent():
             ps = {(int(a), int(b)): int(c) for a, b, c in plain}
             for a, b, c in sched:  # the schedule only drops clauses, it never changes a record
                 assert ps[(int(a), int(b))] == int(c)
-            hits_plain += sum(bin(int(c)).count("1") for c in plain["mask"])
-            hits_sched += sum(bin(int(c)).count("1") for c in sched["mask"])
+            hits_plain += bits(plain)
+            hits_sched += bits(sched)
+            # a random schedule with the same budget on the same assignments
+            low = np.zeros(n, dtype=np.uint8)
+            low[rng.choice(n, size=n_low, replace=False)] = 1
+            ctx.priority_mark(low)
+            m = ctx.test(gss.GSS_TEST_SCHEDULED)
+            hits_random += bits(ctx.fetch_reports(m))
             _redraw(rng, vals, 0.05)
-            ctx.priority_score(tau)  # fresh scores for the next run
+            n_low = ctx.priority_score(tau)  # fresh scores for the next run
     missed = 1 - hits_sched / hits_plain
-    print(f"[learned] threshold {tau:.4f}, {n_low} of {n} clauses low, missed {missed:.4f} of {hits_plain} hits",
-          flush=True)
+    missed_random = 1 - hits_random / hits_plain
+    print(f"[learned] threshold {tau:.4f}, {n_low} of {n} clauses low, missed {missed:.4f} of {hits_plain} hits; "
+          f"a random schedule of the same budget missed {missed_random:.4f}", flush=True)
     assert hits_plain > 0 and missed <= 0.01, f"missed {missed:.4f} of {hits_plain} hits"
+    # what the network gains over the method without it: the same budget spent at
+    # random loses a large share of the hits
+    assert missed_random > 0.2 and missed < missed_random / 20
 
 
 def test_update_rescores_exactly_the_changed_clauses():
