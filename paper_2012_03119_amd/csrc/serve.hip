@@ -47,6 +47,7 @@ struct Mail {
     uint64_t free_after = 0;    // the test queued behind the kernel that read d
     bool busy = false;          // uploaded or applied, until that test completes
     bool queued = false;        // uploaded, plane update not queued yet
+    const char *hd = nullptr;   // h as kernels address it, when the device buffer could not be had (else null)
 
     static size_t vbytes(uint32_t cap) { return ((size_t)cap * 4 + 255) / 256 * 256; }
     static size_t bytes(uint32_t cap) { return vbytes(cap) + (size_t)cap * 16; }
@@ -137,16 +138,30 @@ __global__ void k_route_scan(const uint32_t *counts, uint32_t W, uint32_t *curso
     }
 }
 
-// Every kept record to its word's block (order inside a block unspecified).
+// Every kept record to its word's block (order inside a block unspecified).  A
+// workgroup counts its segments' records per word in LDS, claims one range per
+// word with one atomic each, then places its records with LDS cursors: the
+// global counters see one atomic per (workgroup, word), not one per record.
 __global__ __launch_bounds__(256) void k_route_place(const gss_report *reports, const uint32_t *seg_counts,
                                                      uint32_t seg_cap, uint32_t n_segments, uint32_t *cursor,
                                                      gss_report *out) {
+    __shared__ uint32_t h[kChunkWords];
+    if (threadIdx.x < kChunkWords) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t s = blockIdx.x; s < n_segments; s += gridDim.x) {
+        const uint32_t n = min(seg_counts[s], seg_cap);
+        const gss_report *seg = reports + (uint64_t)s * seg_cap;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&h[seg[i].word], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kChunkWords) h[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]) : 0u;
+    __syncthreads();
     for (uint32_t s = blockIdx.x; s < n_segments; s += gridDim.x) {
         const uint32_t n = min(seg_counts[s], seg_cap);
         const gss_report *seg = reports + (uint64_t)s * seg_cap;
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
             const gss_report r = seg[i];
-            out[atomicAdd(&cursor[r.word], 1u)] = r;
+            out[atomicAdd(&h[r.word], 1u)] = r;
         }
     }
 }
@@ -286,18 +301,31 @@ void gss_server::run() {
             res.dropped += snaps - 1 + (staged[p] >= 0 ? 1 : 0);
             staged[p] = arrival;
             if (m->n == 0) continue;
+            m->hd = nullptr;
             if (m->n > m->dcap) {  // the device mirror is idle: the mailbox was open
                 C.dfree(m->d);
                 m->d = nullptr;
                 m->dcap = 0;
-                m->d = (char *)C.dalloc(Mail::bytes(m->cap));
-                m->dcap = m->cap;
+                try {
+                    m->d = (char *)C.dalloc(Mail::bytes(m->cap));
+                    m->dcap = m->cap;
+                } catch (const Error &e) {
+                    if (e.code != GSS_ERR_CAPACITY) throw;
+                    // no room in the HBM budget: the plane update reads the mailbox
+                    // from pinned host memory over the bus instead (the delta must
+                    // be applied: the producer's next one builds on it)
+                    void *hd = nullptr;
+                    GSS_HIP(hipHostGetDevicePointer(&hd, m->h, 0));
+                    m->hd = (const char *)hd;
+                }
             }
-            const size_t vb = Mail::vbytes(m->dcap);
-            GSS_HIP(hipMemcpyAsync(m->d, m->h, (size_t)m->n * 4, hipMemcpyHostToDevice, copy_stream));
-            GSS_HIP(hipMemcpyAsync(m->d + vb, m->f(), (size_t)m->n * 8, hipMemcpyHostToDevice, copy_stream));
-            GSS_HIP(hipMemcpyAsync(m->d + vb + (size_t)m->dcap * 8, m->t(), (size_t)m->n * 8, hipMemcpyHostToDevice,
-                                   copy_stream));
+            if (!m->hd) {
+                const size_t vb = Mail::vbytes(m->dcap);
+                GSS_HIP(hipMemcpyAsync(m->d, m->h, (size_t)m->n * 4, hipMemcpyHostToDevice, copy_stream));
+                GSS_HIP(hipMemcpyAsync(m->d + vb, m->f(), (size_t)m->n * 8, hipMemcpyHostToDevice, copy_stream));
+                GSS_HIP(hipMemcpyAsync(m->d + vb + (size_t)m->dcap * 8, m->t(), (size_t)m->n * 8,
+                                       hipMemcpyHostToDevice, copy_stream));
+            }
             res.delta_bytes += (uint64_t)m->n * 20;
             m->busy = true;
             m->queued = true;
@@ -314,9 +342,15 @@ void gss_server::run() {
             GSS_HIP(hipStreamWaitEvent(C.stream, ev_copied, 0));
             for (const Taken &x : taken) {
                 Mail &m = *x.m;
-                const size_t vb = Mail::vbytes(m.dcap);
-                launch_set_words(C, x.p, (const uint32_t *)m.d, (const uint64_t *)(m.d + vb),
-                                 (const uint64_t *)(m.d + vb) + m.dcap, m.n);
+                if (m.hd) {  // read from pinned host memory (same layout, capacity m.cap)
+                    const size_t vb = Mail::vbytes(m.cap);
+                    launch_set_words(C, x.p, (const uint32_t *)m.hd, (const uint64_t *)(m.hd + vb),
+                                     (const uint64_t *)(m.hd + vb) + m.cap, m.n);
+                } else {
+                    const size_t vb = Mail::vbytes(m.dcap);
+                    launch_set_words(C, x.p, (const uint32_t *)m.d, (const uint64_t *)(m.d + vb),
+                                     (const uint64_t *)(m.d + vb) + m.dcap, m.n);
+                }
                 m.free_after = C.tests_launched + 1;  // the run launched right after this
                 m.queued = false;
                 if (log) {
@@ -530,13 +564,23 @@ void gss_server::run() {
             GSS_HIP(hipHostMalloc((void **)&rec[k], want * sizeof(gss_report), hipHostMallocDefault));
             rec_cap[k] = want;
         }
+        gss_report *place = nullptr;  // where the routing kernel writes the records
         if (n > fdev_cap[k]) {
             C.dfree(fdev[k]);
             fdev[k] = nullptr;
             fdev_cap[k] = 0;
             const uint64_t want = n + n / 4 + 1024;
-            fdev[k] = (gss_report *)C.dalloc(want * sizeof(gss_report));
-            fdev_cap[k] = want;
+            try {
+                fdev[k] = (gss_report *)C.dalloc(want * sizeof(gss_report));
+                fdev_cap[k] = want;
+            } catch (const Error &e) {
+                if (e.code != GSS_ERR_CAPACITY) throw;
+                // no room in the HBM budget: the records go straight into the pinned
+                // host buffer (written over the bus)
+                void *hd = nullptr;
+                GSS_HIP(hipHostGetDevicePointer(&hd, rec[k], 0));
+                place = (gss_report *)hd;
+            }
         }
         timed(res.fetch_ms, [&] {
             if (n) {  // the records sorted by word on the device, then to the host with the word offsets
@@ -550,11 +594,13 @@ void gss_server::run() {
                 hipLaunchKernelGGL(k_route_scan, dim3(1), dim3(64), 0, C.stream, counts, C.W, cursor, offs);
                 GSS_HIP(hipGetLastError());
                 hipLaunchKernelGGL(k_route_place, dim3(grid), dim3(256), 0, C.stream, C.reports, C.seg_counts,
-                                   C.seg_cap, C.last_waves, cursor, fdev[k]);
+                                   C.seg_cap, C.last_waves, cursor, place ? place : fdev[k]);
                 GSS_HIP(hipGetLastError());
                 GSS_HIP(hipEventRecord(ev_stitched, C.stream));
                 GSS_HIP(hipStreamWaitEvent(fetch_stream, ev_stitched, 0));
-                GSS_HIP(hipMemcpyAsync(rec[k], fdev[k], n * sizeof(gss_report), hipMemcpyDeviceToHost, fetch_stream));
+                if (!place)
+                    GSS_HIP(hipMemcpyAsync(rec[k], fdev[k], n * sizeof(gss_report), hipMemcpyDeviceToHost,
+                                           fetch_stream));
                 GSS_HIP(hipMemcpyAsync(roff[k], offs, (C.W + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                        fetch_stream));
             }
