@@ -267,28 +267,162 @@ __global__ void k_prio_gather_act(ProbeArgs a, const uint32_t *ids, uint32_t n, 
     if (i < n) out[i] = a.act[ids[i]];
 }
 
-// Scores every live clause and sets its low flag; counters[1] receives the
-// number of low clauses (one atomic per workgroup).
-__global__ __launch_bounds__(256) void k_prio_score(ProbeArgs a, const float *__restrict__ params, uint64_t n_ids,
-                                                    uint32_t run, float src_scale, float threshold,
-                                                    uint32_t *counters) {
-    uint32_t lows = 0;
-    for (uint64_t id = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; id < n_ids;
-         id += (uint64_t)gridDim.x * blockDim.x) {
-        if (!a.alive[id]) {
-            a.score[id] = 0.f;
-            a.low[id] = 0;
-            continue;
-        }
-        float x[kFeat];
-        load_features(a, id, run, src_scale, x);
-        const float p = sigmoidf_(mlp_logit(params, x));
-        a.score[id] = p;
-        a.low[id] = p < threshold;
-        a.dirty[id] = 0;
-        lows += p < threshold ? 1u : 0u;
+
+// Scoring on the matrix cores.  A wavefront scores 32 clauses per step with
+// fp32 MFMAs (32x32 outputs, K = 2 per instruction) on the transposed
+// activations: H1^T = W1^T X^T (K = the 12 features), then H2^T = W2^T H1^T
+// (K = the 64 hidden units).  In the 32x32 result a lane holds one clause (its
+// column, lane % 32) and 16 rows; those are exactly the values that lane must
+// supply as the B operand (one K row for one clause) of the next product, so
+// the activations never move between lanes: step s of the second product takes
+// its two K rows from register s % 16 of tile s / 16 of the two lane halves,
+// and the weights (the A operand) are loaded in that same row order.  The
+// output layer sums each lane's 32 rows and its partner lane's (lane ^ 32).
+// The weights stay in registers for all of a wavefront's steps.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Workgroups of 4 wavefronts for scoring n ids, 32 per wavefront step; at most
+// 4 workgroups per compute unit (the kernel holds its weights in registers).
+unsigned score_grid(const Ctx &c, uint64_t n) {
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 127) / 128, (uint64_t)c.n_cu * 4));
+}
+
+// row of the 32x32 result held in register v by a lane of half `half`
+__device__ constexpr uint32_t mfma_row(uint32_t v, uint32_t half) { return 8 * (v / 4) + 4 * half + (v % 4); }
+
+// The raw per-clause statistics the features are made of, loaded ahead of use.
+struct RawFeat {
+    uint32_t len, birth, src;
+    float lbd;
+    uint4 hist;
+};
+
+__device__ inline void raw_load(const ProbeArgs &a, uint32_t id, RawFeat &r) {
+    r.len = a.len[id];
+    r.birth = a.birth[id];
+    r.src = a.src[id];
+    r.lbd = a.lbd[id];
+    r.hist = a.hist[id];
+}
+
+// LIST: score the n ids of list[] (n = *list_n); else ids 0..n_ids-1 (removed
+// ones get score 0 and are not low).  The first weight matrix and the second
+// live in registers as MFMA operands; the biases and output weights in LDS; the
+// next step's clause statistics are loaded while the current step multiplies.
+template <bool LIST>
+__global__ __launch_bounds__(256) void k_prio_score_mfma(ProbeArgs a, const float *__restrict__ params,
+                                                         const uint32_t *list, const uint32_t *list_n, uint64_t n_ids,
+                                                         uint32_t run, float src_scale, float threshold,
+                                                         uint32_t *counters) {
+    __shared__ float b1s[kHid], b2s[kHid], w3s[kHid];
+    for (uint32_t t = threadIdx.x; t < kHid; t += blockDim.x) {
+        b1s[t] = params[kOffB1 + t];
+        b2s[t] = params[kOffB2 + t];
+        w3s[t] = params[kOffW3 + t];
     }
-    block_add((int32_t)lows, &counters[1]);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    float w1a[2][kFeat / 2], w2a[2][kHid / 2];
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+#pragma unroll
+        for (uint32_t st = 0; st < kFeat / 2; ++st) w1a[u][st] = params[kOffW1 + (2 * st + half) * kHid + 32 * u + col];
+#pragma unroll
+        for (uint32_t st = 0; st < kHid / 2; ++st) {
+            const uint32_t hid = 32 * (st / 16) + mfma_row(st % 16, half);
+            w2a[u][st] = params[kOffW2 + hid * kHid + 32 * u + col];
+        }
+    }
+    const float b3 = params[kOffB3];
+    const uint64_t n = LIST ? (uint64_t)*list_n : n_ids;
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / 64;
+    const uint64_t n_waves = (uint64_t)gridDim.x * blockDim.x / 64;
+    int32_t count = 0;  // LIST: change in the number of low clauses; else low clauses
+    // this lane's clause of a step starting at `base`
+    auto clause_of = [&](uint64_t base, uint32_t &id, bool &valid, bool &live, RawFeat &r) {
+        const uint64_t i = base + col;
+        valid = i < n;
+        id = valid ? (LIST ? list[i] : (uint32_t)i) : 0u;
+        live = valid && (LIST || a.alive[id]);
+        if (live) raw_load(a, id, r);
+    };
+    uint64_t base = wave * 32;
+    uint32_t id = 0;
+    bool valid = false, live = false;
+    RawFeat r{};
+    if (base < n) clause_of(base, id, valid, live, r);
+    for (; base < n; base += n_waves * 32) {  // uniform per wavefront
+        float x[kFeat];
+        if (live) {
+            uint32_t h[kHist];
+            const uint32_t c4[4] = {r.hist.x, r.hist.y, r.hist.z, r.hist.w};
+#pragma unroll
+            for (int k = 0; k < kHist; ++k) h[k] = (c4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+            clause_features(x, r.len, r.lbd, run - r.birth, r.src, src_scale, h);
+        } else {
+#pragma unroll
+            for (int f = 0; f < kFeat; ++f) x[f] = 0.f;
+        }
+        const uint32_t cur_id = id;
+        const bool cur_valid = valid, cur_live = live;
+        const uint64_t next = base + n_waves * 32;
+        if (next < n) clause_of(next, id, valid, live, r);  // in flight during the products
+        // an index the compiler cannot see through: the LDS reads stay in the
+        // loop instead of being hoisted into 96 more registers per lane
+        uint32_t lds_row = 4 * half;
+        asm volatile("" : "+v"(lds_row));
+        f32x16 acc1[2], acc2[2];
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u)
+#pragma unroll
+            for (uint32_t v = 0; v < 16; ++v) {
+                const uint32_t row = 32 * u + 8 * (v / 4) + (v % 4) + lds_row;  // mfma_row(v, half)
+                acc1[u][v] = b1s[row];
+                acc2[u][v] = b2s[row];
+            }
+#pragma unroll
+        for (uint32_t st = 0; st < kFeat / 2; ++st) {
+            const float bx = half ? x[2 * st + 1] : x[2 * st];
+#pragma unroll
+            for (uint32_t u = 0; u < 2; ++u)
+                acc1[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(w1a[u][st], bx, acc1[u], 0, 0, 0);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u)
+#pragma unroll
+            for (uint32_t v = 0; v < 16; ++v) acc1[u][v] = fmaxf(acc1[u][v], 0.f);
+#pragma unroll
+        for (uint32_t st = 0; st < kHid / 2; ++st) {
+            const float bh = acc1[st / 16][st % 16];
+#pragma unroll
+            for (uint32_t u = 0; u < 2; ++u)
+                acc2[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(w2a[u][st], bh, acc2[u], 0, 0, 0);
+        }
+        float part = 0.f;
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u)
+#pragma unroll
+            for (uint32_t v = 0; v < 16; ++v)
+                part = fmaf(fmaxf(acc2[u][v], 0.f), w3s[32 * u + 8 * (v / 4) + (v % 4) + lds_row], part);
+        const float z = part + __shfl_xor(part, 32) + b3;
+        if (half == 0 && cur_valid) {
+            if (!cur_live) {  // a removed clause: no score
+                a.score[cur_id] = 0.f;
+                a.low[cur_id] = 0;
+            } else {
+                const float prob = sigmoidf_(z);
+                const bool now = prob < threshold;
+                a.score[cur_id] = prob;
+                if (LIST)
+                    count += (int32_t)now - (int32_t)a.low[cur_id];
+                else
+                    count += now ? 1 : 0;
+                a.low[cur_id] = now;
+                a.dirty[cur_id] = 0;
+            }
+        }
+    }
+    block_add(count, &counters[1]);
 }
 
 // The dirty live clauses, compacted into a list (counters[2] = its length), so
@@ -310,24 +444,6 @@ __global__ __launch_bounds__(256) void k_prio_collect(ProbeArgs a, uint64_t n_id
     }
 }
 
-__global__ __launch_bounds__(256) void k_prio_score_list(ProbeArgs a, const float *__restrict__ params,
-                                                         const uint32_t *list, uint32_t run, float src_scale,
-                                                         float threshold, uint32_t *counters) {
-    const uint32_t n = counters[2];
-    int32_t delta = 0;  // change in the number of low clauses
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t id = list[i];
-        float x[kFeat];
-        load_features(a, id, run, src_scale, x);
-        const float p = sigmoidf_(mlp_logit(params, x));
-        a.score[id] = p;
-        const bool was = a.low[id], now = p < threshold;
-        a.low[id] = now;
-        a.dirty[id] = 0;
-        delta += (int32_t)now - (int32_t)was;
-    }
-    block_add(delta, &counters[1]);
-}
 
 // Schedule bits of one length class: bit s of word s / 32 set when slot s holds
 // a live low-priority clause.  Grid over 64-slot groups.
@@ -720,8 +836,8 @@ extern "C" gss_status gss_priority_score(gss_ctx *ctx, float threshold, uint64_t
     GSS_REQUIRE(!c.pending, GSS_ERR_STATE, "a test is in flight");
     launch_fill_u32(c, p.counters + 1, 1, 0);
     if (p.n_ids)
-        hipLaunchKernelGGL(k_prio_score, dim3(std::min<uint64_t>(grid_of(p.n_ids), (uint64_t)c.n_cu * 16)), dim3(256), 0,
-                           c.stream, args_of(p), p.params, p.n_ids, p.run, src_scale(p), threshold, p.counters);
+        hipLaunchKernelGGL(k_prio_score_mfma<false>, dim3(score_grid(c, p.n_ids)), dim3(256), 0, c.stream, args_of(p),
+                           p.params, nullptr, nullptr, p.n_ids, p.run, src_scale(p), threshold, p.counters);
     GSS_HIP(hipGetLastError());
     p.threshold = threshold;
     p.scored = true;
@@ -753,9 +869,9 @@ extern "C" gss_status gss_priority_update(gss_ctx *ctx, uint64_t *out_n_low) {
         hipLaunchKernelGGL(k_prio_collect, dim3(grid_of(p.n_ids, 256 * kPerThread)), dim3(256), 0, c.stream, args_of(p),
                            p.n_ids, p.list, p.counters);
         GSS_HIP(hipGetLastError());
-        const unsigned grid = (unsigned)std::min<uint64_t>(grid_of(p.n_ids), (uint64_t)c.n_cu * 16);
-        hipLaunchKernelGGL(k_prio_score_list, dim3(grid), dim3(256), 0, c.stream, args_of(p), p.params, p.list, p.run,
-                           src_scale(p), p.threshold, p.counters);
+        // the list's length is on the device: a grid for all ids, whose surplus wavefronts exit at once
+        hipLaunchKernelGGL(k_prio_score_mfma<true>, dim3(score_grid(c, p.n_ids)), dim3(256), 0, c.stream, args_of(p),
+                           p.params, p.list, p.counters + 2, 0ull, p.run, src_scale(p), p.threshold, p.counters);
         GSS_HIP(hipGetLastError());
     }
     p.score_epoch++;
