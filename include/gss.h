@@ -555,7 +555,10 @@ gss_status gss_server_insert(gss_server *srv, uint32_t producer, const int32_t *
 /* Moves up to cap of producer p's pending records into out (host) and sets
  * *out_n; out NULL discards them all (*out_n = the number discarded).  *out_run
  * (may be NULL) receives the last run whose records were routed to p (or
- * UINT64_MAX if none). */
+ * UINT64_MAX if none).  The records wait in the pinned buffers they were
+ * fetched into and are copied here, on the caller's thread; a producer that
+ * falls several runs behind is given copies, so that those buffers can be
+ * reused. */
 gss_status gss_server_poll(gss_server *srv, uint32_t producer, gss_report *out, uint64_t cap, uint64_t *out_n,
                            uint64_t *out_run);
 

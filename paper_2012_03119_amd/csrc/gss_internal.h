@@ -369,6 +369,7 @@ bool rank_vars(Ctx &c);
 // Writes the n records at src (device) into dst (device) ordered by (clause id,
 // word); synchronises the stream.
 void sort_records(Ctx &c, gss_report *src, uint64_t n, gss_report *dst);  // src is overwritten
+void launch_scan_u32(Ctx &c, uint32_t *x, uint64_t m);  // in place, exclusive, on c.stream
 uint32_t *deferred_flag(Ctx &c);
 uint32_t read_deferred(Ctx &c);
 void report_deferred(Ctx &c, uint32_t verdict);

@@ -14,7 +14,9 @@
 //     a fetch stream), then the plane update (behind the upload) and the next run
 //   next run: tests every word with a new snapshot; while the run after it
 //     executes, its records are routed by word to the producers' queues, which
-//     is when the snapshot is notified.
+//     is when the snapshot is notified.  A queue holds ranges of the pinned
+//     buffer the records came back in, not copies: each producer copies its own
+//     records when it polls, on its own thread.
 //
 // Runs are launched back to back (continuous batching): while run k executes,
 // the manager routes the records of run k-1 and admits snapshots, inserts and
@@ -27,6 +29,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -58,6 +61,31 @@ struct Mail {
 
 constexpr int kMails = 3;  // the open one, and up to two queued behind runs
 
+// The records of one run in pinned host memory, shared by the producers that
+// still hold a range of them; reused once none does.
+struct RecBlock {
+    gss_report *h = nullptr;
+    uint64_t cap = 0;
+    uint64_t used_run = 0;  // the last run fetched into it
+    RecBlock() = default;
+    RecBlock(const RecBlock &) = delete;
+    RecBlock &operator=(const RecBlock &) = delete;
+    ~RecBlock() {
+        if (h) (void)hipHostFree(h);
+    }
+};
+
+// Pending records of a producer: a range of a shared block, or (once the block
+// had to be reused before the producer polled) records of its own.
+struct OutChunk {
+    std::shared_ptr<RecBlock> blk;
+    std::vector<gss_report> own;
+    const gss_report *p = nullptr;
+    uint64_t n = 0;
+};
+
+constexpr size_t kMaxRecBlocks = 8;  // beyond this, a producer that does not poll gets copies
+
 struct Producer {
     std::mutex mu;
     Mail mail[kMails];
@@ -67,7 +95,8 @@ struct Producer {
     double arrival = -1.0;      // send time of the newest of them
 
     std::mutex omu;
-    std::vector<gss_report> outbox;
+    std::deque<OutChunk> outbox;
+    uint64_t out_n = 0;  // records in the outbox
     uint64_t last_run = UINT64_MAX;
 };
 
@@ -180,7 +209,7 @@ struct gss_server {
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_copied = nullptr;
     // records of a finished run travel to the host on their own stream while the
-    // next run executes: stitched into fdev[k], copied into pinned rec[k]
+    // next run executes: routed into fdev[k], copied into a pinned block
     hipStream_t fetch_stream = nullptr;
     hipEvent_t ev_stitched = nullptr;
     hipEvent_t ev_fetched[2] = {nullptr, nullptr};
@@ -226,10 +255,12 @@ void gss_server::run() {
         if (C.id_loc[id] != kNoLoc) live.push_back((uint32_t)id);
     uint64_t rng = cfg.seed * 0x2545F4914F6CDD1Dull + 11;
     std::vector<double> staged(P, -1.0), inflight(P, -1.0);  // arrival of the untested / tested snapshot
-    // two buffer pairs, used in turn: pinned records (they come back at full link
-    // speed) and the device list they are copied from
-    gss_report *rec[2] = {nullptr, nullptr}, *fdev[2] = {nullptr, nullptr};
-    uint64_t rec_cap[2] = {0, 0}, fdev_cap[2] = {0, 0};
+    // two device lists, used in turn, the records are routed into; pinned blocks
+    // they are copied to (they come back at full link speed), shared with the
+    // producers' outboxes
+    gss_report *fdev[2] = {nullptr, nullptr};
+    uint64_t fdev_cap[2] = {0, 0};
+    std::vector<std::shared_ptr<RecBlock>> pool;
     // routing by word: device counts, cursors and offsets; pinned copies of the offsets
     uint32_t *route_dev = nullptr;  // counts [64] | cursor [64] | offsets [65] (u64)
     unsigned long long *roff[2] = {nullptr, nullptr};
@@ -238,6 +269,7 @@ void gss_server::run() {
         bool active = false;
         uint64_t run = 0, n = 0;
         int k = 0;
+        std::shared_ptr<RecBlock> blk;
         std::vector<double> arrivals;  // per producer: the tested snapshot's send time, or -1
     } fq;
     std::vector<uint64_t> act(C.W, 0);
@@ -494,7 +526,7 @@ void gss_server::run() {
             GSS_HIP(e);
         }
         const double route_t0 = now();
-        const gss_report *r = rec[fq.k];
+        const gss_report *r = fq.blk->h;
         const unsigned long long *off = roff[fq.k];  // producer p's records: r[off[p] .. off[p + 1])
         const uint64_t got = fq.n;
         if (log) {
@@ -509,7 +541,15 @@ void gss_server::run() {
             {
                 Producer &pr = prod[p];
                 std::lock_guard<std::mutex> g(pr.omu);
-                if (got) pr.outbox.insert(pr.outbox.end(), r + off[p], r + off[p + 1]);
+                const uint64_t m = got ? off[p + 1] - off[p] : 0;
+                if (m) {
+                    OutChunk ch;
+                    ch.blk = fq.blk;
+                    ch.p = r + off[p];
+                    ch.n = m;
+                    pr.outbox.push_back(std::move(ch));
+                    pr.out_n += m;
+                }
                 pr.last_run = fq.run;
             }
             lat.push_back((t - fq.arrivals[p]) * 1e3);
@@ -518,7 +558,53 @@ void gss_server::run() {
         res.reports += got;
         res.route_ms += (now() - route_t0) * 1e3;
         fq.active = false;
+        fq.blk.reset();
         return true;
+    };
+
+    // A pinned block for a run's records: a free one (no producer holds a range of
+    // it; the smallest that fits, else the largest, grown), a new one while the
+    // pool is small, else the least recently used one, whose holders are given
+    // copies of their ranges first.
+    auto take_block = [&](uint64_t need) -> std::shared_ptr<RecBlock> {
+        auto better = [need](const RecBlock &a, const RecBlock &b) {
+            const bool fa = a.cap >= need, fb = b.cap >= need;
+            if (fa != fb) return fa;
+            return fa ? a.cap < b.cap : a.cap > b.cap;
+        };
+        std::shared_ptr<RecBlock> pick;
+        for (const auto &b : pool)
+            if (b.use_count() == 1 && (!pick || better(*b, *pick))) pick = b;
+        if (!pick && pool.size() >= kMaxRecBlocks) {
+            pick = *std::min_element(pool.begin(), pool.end(),
+                                     [](const auto &a, const auto &b) { return a->used_run < b->used_run; });
+            for (uint32_t p = 0; p < P; ++p) {
+                Producer &pr = prod[p];
+                std::lock_guard<std::mutex> g(pr.omu);
+                for (OutChunk &ch : pr.outbox)
+                    if (ch.blk == pick) {
+                        ch.own.assign(ch.p, ch.p + ch.n);
+                        ch.p = ch.own.data();
+                        ch.blk.reset();
+                    }
+            }
+        }
+        if (!pick) {
+            pool.push_back(std::make_shared<RecBlock>());
+            pick = pool.back();
+        }
+        // the last holder released it (a release decrement): its reads are over
+        std::atomic_thread_fence(std::memory_order_acquire);
+        if (pick->cap < need) {
+            if (pick->h) (void)hipHostFree(pick->h);
+            pick->h = nullptr;
+            pick->cap = 0;
+            const uint64_t want = need + need / 4 + 1024;
+            GSS_HIP(hipHostMalloc((void **)&pick->h, want * sizeof(gss_report), hipHostMallocDefault));
+            pick->cap = want;
+        }
+        pick->used_run = run_id;
+        return pick;
     };
 
     auto finish = [&]() {
@@ -556,14 +642,7 @@ void gss_server::run() {
         if (fq.active) route_fetch(true);
         const int k = next_k;
         next_k ^= 1;
-        if (n > rec_cap[k]) {
-            if (rec[k]) (void)hipHostFree(rec[k]);
-            rec[k] = nullptr;
-            rec_cap[k] = 0;
-            const uint64_t want = n + n / 4 + 1024;
-            GSS_HIP(hipHostMalloc((void **)&rec[k], want * sizeof(gss_report), hipHostMallocDefault));
-            rec_cap[k] = want;
-        }
+        std::shared_ptr<RecBlock> blk = take_block(n);
         gss_report *place = nullptr;  // where the routing kernel writes the records
         if (n > fdev_cap[k]) {
             C.dfree(fdev[k]);
@@ -578,7 +657,7 @@ void gss_server::run() {
                 // no room in the HBM budget: the records go straight into the pinned
                 // host buffer (written over the bus)
                 void *hd = nullptr;
-                GSS_HIP(hipHostGetDevicePointer(&hd, rec[k], 0));
+                GSS_HIP(hipHostGetDevicePointer(&hd, blk->h, 0));
                 place = (gss_report *)hd;
             }
         }
@@ -599,7 +678,7 @@ void gss_server::run() {
                 GSS_HIP(hipEventRecord(ev_stitched, C.stream));
                 GSS_HIP(hipStreamWaitEvent(fetch_stream, ev_stitched, 0));
                 if (!place)
-                    GSS_HIP(hipMemcpyAsync(rec[k], fdev[k], n * sizeof(gss_report), hipMemcpyDeviceToHost,
+                    GSS_HIP(hipMemcpyAsync(blk->h, fdev[k], n * sizeof(gss_report), hipMemcpyDeviceToHost,
                                            fetch_stream));
                 GSS_HIP(hipMemcpyAsync(roff[k], offs, (C.W + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                        fetch_stream));
@@ -610,6 +689,7 @@ void gss_server::run() {
         fq.run = this_run;
         fq.n = n;
         fq.k = k;
+        fq.blk = std::move(blk);
         fq.arrivals = inflight;
         std::fill(inflight.begin(), inflight.end(), -1.0);
     };
@@ -695,7 +775,6 @@ void gss_server::run() {
     (void)hipStreamSynchronize(C.stream);
     (void)hipStreamSynchronize(fetch_stream);
     for (int k = 0; k < 2; ++k) {
-        if (rec[k]) (void)hipHostFree(rec[k]);
         C.dfree(fdev[k]);
         if (roff[k]) (void)hipHostFree(roff[k]);
     }
@@ -856,13 +935,23 @@ extern "C" gss_status gss_server_poll(gss_server *s, uint32_t producer, gss_repo
     std::lock_guard<std::mutex> g(p.omu);
     if (out_run) *out_run = p.last_run;
     if (!out) {
-        *out_n = p.outbox.size();
+        *out_n = p.out_n;
         p.outbox.clear();
+        p.out_n = 0;
         return GSS_OK;
     }
-    const uint64_t k = std::min<uint64_t>(cap, p.outbox.size());
-    std::memcpy(out, p.outbox.data(), k * sizeof(gss_report));
-    p.outbox.erase(p.outbox.begin(), p.outbox.begin() + (ptrdiff_t)k);
+    // copied here, on the caller's thread, from the pinned blocks
+    uint64_t k = 0;
+    while (k < cap && !p.outbox.empty()) {
+        OutChunk &ch = p.outbox.front();
+        const uint64_t m = std::min<uint64_t>(cap - k, ch.n);
+        std::memcpy(out + k, ch.p, m * sizeof(gss_report));
+        k += m;
+        ch.p += m;
+        ch.n -= m;
+        if (ch.n == 0) p.outbox.pop_front();
+    }
+    p.out_n -= k;
     *out_n = k;
     GSS_SRV_END(s)
 }

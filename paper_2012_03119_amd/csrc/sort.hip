@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_tile_counts(const gss_rep
 }
 
 // In-place exclusive scan of m counts by one workgroup of 1024 threads, each
-// taking a contiguous share.
+// taking a contiguous share (also the store's compaction offsets).
 __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *x, uint64_t m) {
     __shared__ uint32_t part[1024];
     const uint32_t t = threadIdx.x;
@@ -135,6 +135,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const gss_report 
 unsigned grid_of(uint64_t n) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 16384)); }
 
 }  // namespace
+
+void launch_scan_u32(Ctx &c, uint32_t *x, uint64_t m) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, c.stream, x, m);
+    GSS_HIP(hipGetLastError());
+}
 
 void sort_records(Ctx &c, gss_report *src, uint64_t n, gss_report *dst) {
     if (n == 0) return;

@@ -67,6 +67,51 @@ __global__ void k_compact_meta(uint2 *dmeta, const uint2 *smeta, const uint64_t 
         dmeta[s] = smeta[old_slot[s]];
 }
 
+// Compaction map, K7 (a prefix sum over the live flags, length != 0): slot s of a
+// class is live when its length is nonzero; block b covers slots [1024 b, 1024 b
+// + 1024), four per thread.  First the live count of each block; then, after an
+// exclusive scan of the counts, every live slot's new place: the number of live
+// slots before it.  The map is in slot order, so the host mirror follows it
+// without reading it back.
+__global__ __launch_bounds__(256) void k_live_counts(const uint2 *meta, uint64_t n_slots, uint32_t *block_counts) {
+    __shared__ uint32_t part[4];
+    const uint64_t s0 = (uint64_t)blockIdx.x * 1024 + 4ull * threadIdx.x;
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) mine += (s0 + k < n_slots && meta[s0 + k].x != 0) ? 1u : 0u;
+    for (uint32_t off = 32; off; off >>= 1) mine += __shfl_xor(mine, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x / 64] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) block_counts[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// old_slot holds n_new entries (the host's live count; writes past it are dropped).
+__global__ __launch_bounds__(256) void k_live_place(const uint2 *meta, uint64_t n_slots, const uint32_t *block_base,
+                                                    uint64_t *old_slot, uint64_t n_new) {
+    __shared__ uint32_t pre[256];
+    const uint32_t t = threadIdx.x;
+    const uint64_t s0 = (uint64_t)blockIdx.x * 1024 + 4ull * t;
+    uint32_t flags = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) flags |= (s0 + k < n_slots && meta[s0 + k].x != 0 ? 1u : 0u) << k;
+    const uint32_t mine = __builtin_popcount(flags);
+    pre[t] = mine;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {  // inclusive scan
+        const uint32_t v = t >= off ? pre[t - off] : 0u;
+        __syncthreads();
+        pre[t] += v;
+        __syncthreads();
+    }
+    uint64_t pos = (uint64_t)block_base[blockIdx.x] + pre[t] - mine;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+        if ((flags >> k) & 1u) {
+            if (pos < n_new) old_slot[pos] = s0 + k;
+            ++pos;
+        }
+}
+
 static unsigned grid_for(uint64_t n, unsigned block = 256) {
     uint64_t g = (n + block - 1) / block;
     return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, 16384));
@@ -135,47 +180,57 @@ static void grow_bucket(Ctx &c, Bucket &b, uint64_t cap) {
 // (and changes nothing) when the HBM budget has no room for the new arrays.
 static bool compact_bucket(Ctx &c, int bi) {
     Bucket &b = c.buckets[bi];
-    std::vector<uint64_t> old_slot;
-    old_slot.reserve(b.n_slots - b.n_dead);
-    for (uint64_t s = 0; s < b.n_slots; ++s)
-        if (b.h_ids[s] != kDeadId) old_slot.push_back(s);
-    const uint64_t n_new = old_slot.size();
+    const uint64_t n_new = b.n_slots - b.n_dead;
     const uint64_t S = 1ull << b.stride_log2;
     const uint64_t cap = round_up(std::max<uint64_t>(n_new + n_new / 4, 256), c.T);
-    const uint64_t need = cap * S * 4 + cap * 8 + n_new * 8 + 4096;
+    const uint64_t n_blocks = (b.n_slots + 1023) / 1024;
+    const uint64_t need = cap * S * 4 + cap * 8 + n_new * 8 + n_blocks * 4 + 4096;
     if (!c.fits(need)) return false;
 
     uint32_t *lits = (uint32_t *)c.dalloc(cap * S * 4);
     uint2 *meta = (uint2 *)c.dalloc(cap * 8);
-    uint64_t *dmap = (uint64_t *)c.dalloc(std::max<uint64_t>(n_new, 1) * 8);
+    // the map (old slot of each new slot), then the per-block live counts
+    char *mbuf = (char *)c.dalloc(round_up(std::max<uint64_t>(n_new, 1) * 8, 256) + n_blocks * 4);
+    uint64_t *dmap = (uint64_t *)mbuf;
+    uint32_t *block_counts = (uint32_t *)(mbuf + round_up(std::max<uint64_t>(n_new, 1) * 8, 256));
     launch_fill_u32(c, lits, cap * S, 0);
     fill_meta(c, meta, cap);
     if (n_new) {
-        // the slot map goes up through a pinned ring slot (its host memory only:
-        // within the room checked above): nothing waits for the copy
-        const Ctx::Staged st = c.stage_upload(n_new * 8, true);
-        std::memcpy(st.h, old_slot.data(), n_new * 8);
-        GSS_HIP(hipMemcpyAsync(dmap, st.h, n_new * 8, hipMemcpyHostToDevice, c.stream));
-        c.stage_done(st);
+        // the map is built on the device from the lengths (the removals are queued
+        // before it on the same stream)
+        hipLaunchKernelGGL(k_live_counts, dim3((unsigned)n_blocks), dim3(256), 0, c.stream, b.meta, b.n_slots,
+                           block_counts);
+        GSS_HIP(hipGetLastError());
+        launch_scan_u32(c, block_counts, n_blocks);
+        hipLaunchKernelGGL(k_live_place, dim3((unsigned)n_blocks), dim3(256), 0, c.stream, b.meta, b.n_slots,
+                           block_counts, dmap, n_new);
+        GSS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_compact_lits, dim3(grid_for(n_new * S)), dim3(256), 0, c.stream, lits, b.lits,
                            b.stride_log2, tile_log2(c), dmap, n_new);
         GSS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_compact_meta, dim3(grid_for(n_new)), dim3(256), 0, c.stream, meta, b.meta, dmap, n_new);
         GSS_HIP(hipGetLastError());
     }
-    c.defer_free(dmap);  // read by the compaction kernels just queued
+    c.defer_free(mbuf);  // read by the compaction kernels just queued
     c.defer_free(b.lits);
     c.defer_free(b.meta);
     b.lits = lits;
     b.meta = meta;
     b.cap_slots = cap;
 
+    // the host mirror, in the same order: live slots keep their relative order
     std::vector<uint32_t> h_ids(n_new), h_len(n_new);
-    for (uint64_t s = 0; s < n_new; ++s) {
-        h_ids[s] = b.h_ids[old_slot[s]];
-        h_len[s] = b.h_len[old_slot[s]];
-        c.id_loc[h_ids[s]] = ((uint64_t)bi << 40) | s;
+    uint64_t s = 0;
+    for (uint64_t o = 0; o < b.n_slots; ++o) {
+        const uint32_t id = b.h_ids[o];
+        if (id == kDeadId) continue;
+        GSS_REQUIRE(s < n_new, GSS_ERR_DEVICE, "store mirror holds more live slots than counted");
+        h_ids[s] = id;
+        h_len[s] = b.h_len[o];
+        c.id_loc[id] = ((uint64_t)bi << 40) | s;
+        ++s;
     }
+    GSS_REQUIRE(s == n_new, GSS_ERR_DEVICE, "store mirror holds fewer live slots than counted");
     b.h_ids.swap(h_ids);
     b.h_len.swap(h_len);
     b.n_slots = n_new;
@@ -273,9 +328,13 @@ void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
     for (uint32_t i = 0; i < n; ++i) add[cls[i]]++;
     // ---- order the batch by bucket, and inside a bucket by lead code: clauses a
     //      wavefront (and an XCD) tests at the same time then share the plane row
-    //      of their first literal, the one every clause reads in full.  Then cut
-    //      the batch into upload chunks, each a run of clauses of one bucket; stage
-    //      buffers are sized for the largest chunk.
+    //      of their first literal, the one every clause reads in full.  The lead
+    //      is the smallest of about S codes out of 2 V, so two clauses of a class
+    //      share it with probability about S / 4V: a class that adds fewer than
+    //      V / 4S clauses (the small batches of a served store) would share almost
+    //      none, and keeps the arrival order.  Then cut the batch into upload
+    //      chunks, each a run of clauses of one bucket; stage buffers are sized
+    //      for the largest chunk.
     std::vector<uint32_t> order(n);
     {
         uint64_t pos[kMaxBuckets + 1] = {0};
@@ -284,8 +343,9 @@ void commit_clauses(Ctx &c, const Prepared &p, uint32_t *out_ids) {
         std::copy(pos, pos + kMaxBuckets + 1, start);
         for (uint32_t i = 0; i < n; ++i) order[pos[cls[i]]++] = i;
         for (int b = 0; b < kMaxBuckets; ++b)
-            std::stable_sort(order.begin() + start[b], order.begin() + start[b + 1],
-                             [&](uint32_t x, uint32_t y) { return lead[x] < lead[y]; });
+            if ((add[b] << c.buckets[b].stride_log2 << 2) >= (uint64_t)c.cfg.num_vars)
+                std::stable_sort(order.begin() + start[b], order.begin() + start[b + 1],
+                                 [&](uint32_t x, uint32_t y) { return lead[x] < lead[y]; });
     }
     const uint64_t kChunkLits = 1ull << 24, kChunkClauses = 1ull << 21;
     std::vector<uint32_t> cuts{0};

@@ -215,6 +215,59 @@ def test_add_remove_compact_sequence():
         assert e.value.code == gss.GSS_ERR_UNKNOWN_ID
 
 
+def test_compaction_over_many_blocks():
+    """A class of 300k slots compacted on the device (a prefix sum over the live
+    flags, 1024 slots per block): whole dead blocks, a dead last slot, a ragged
+    tail, then a second compaction after more inserts."""
+    n_vars, max_slots = 2000, 256
+    rng = np.random.default_rng(37)
+    vals_n = gen.assignments_bernoulli(rng, max_slots, n_vars, 0.8)
+    vals, active = full_values(vals_n, max_slots)
+    model = {}
+    with new_context(n_vars, max_slots) as ctx:
+        ctx.set_assignments(0, vals_n)
+        next_id = 0
+        for step, k in enumerate([300_001, 100_003]):
+            # lengths 3-4: one length class; the store orders a batch by its smallest code
+            lits, offsets = gen.random_clauses(rng, rng.integers(3, 5, k), n_vars)
+            ids = ctx.add_clauses(lits, offsets)
+            next_id += k
+            low = np.minimum.reduceat(np.abs(lits), offsets[:-1])
+            for i, cid in enumerate(ids.tolist()):
+                model[cid] = lits[offsets[i]:offsets[i + 1]]
+            kill = set(rng.choice(np.array(sorted(model), dtype=np.uint32), size=int(len(model) * 0.3),
+                                  replace=False).tolist())
+            # a contiguous run of slots (every clause whose smallest variable is in
+            # [10, 60]) and the batch's last slot (the largest smallest variable)
+            kill.update(ids[(low >= 10) & (low <= 60)].tolist())
+            kill.add(int(ids[np.argmax(low)]))
+            kill = np.array(sorted(kill), dtype=np.uint32)
+            before = ctx.stats()["compactions"]
+            ctx.remove_clauses(kill)
+            for cid in kill.tolist():
+                del model[cid]
+            print(f"compaction step {step}: live {len(model)}", flush=True)
+            assert ctx.stats()["compactions"] > before
+            assert ctx.store_info()["live_clauses"] == len(model)
+            got = gpu_dense(ctx, next_id)
+            ids_live = np.array(sorted(model), dtype=np.int64)
+            l2, o2 = csr([model[i] for i in ids_live.tolist()])
+            want = np.zeros_like(got)
+            want[ids_live] = oracle_dense(l2, o2, vals, active)
+            _check(got, want)
+        # removals after the compaction find the moved clauses
+        rest = np.array(sorted(model), dtype=np.uint32)[::3]
+        ctx.remove_clauses(rest)
+        for cid in rest.tolist():
+            del model[cid]
+        got = gpu_dense(ctx, next_id)
+        ids_live = np.array(sorted(model), dtype=np.int64)
+        l2, o2 = csr([model[i] for i in ids_live.tolist()])
+        want = np.zeros_like(got)
+        want[ids_live] = oracle_dense(l2, o2, vals, active)
+        _check(got, want)
+
+
 def test_var_value_deltas_and_flips():
     w = gen.paper(3, n_clauses=30_000, n_vars=5_000, n_slots=512)
     vals = w.values.copy()

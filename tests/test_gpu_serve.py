@@ -177,6 +177,54 @@ def _collect(srv, p, after, timeout=20.0):
     raise AssertionError("no run tested the snapshot in time")
 
 
+def test_late_pollers_receive_every_routed_record(tmp_path):
+    """Producers that do not poll for many runs: their records wait in the pinned
+    blocks they were fetched into until the block pool runs out, then are copied
+    out for them; polls with a small cap resume where they stopped.  What each
+    producer collects equals the records the log shows routed to its word."""
+    V, W = 2000, 4
+    lits, offs = _store(47, 15_000, V)
+    ctx = gss.Context(V, W * 64)
+    ctx.add_clauses(lits, offs)
+    var_ids = np.arange(1, V + 1, dtype=np.uint32)
+    log = tmp_path / "late.log"
+    srv = gss.Server(ctx, W, log_path=str(log))
+    got = {p: [] for p in range(W)}
+    seen = {p: None for p in range(W)}
+    try:
+        for k in range(16):  # more runs than the pool has blocks; nobody polls
+            for p in range(W):
+                _, f, t = _snapshot(1000 + 16 * p + k, V)
+                srv.send(p, var_ids, f, t)
+            time.sleep(0.03)
+        time.sleep(0.5)
+        for p in range(W):
+            while True:
+                r, run = srv.poll(p, cap=777)
+                got[p].append(r)
+                seen[p] = run
+                if len(r) == 0:
+                    break
+    finally:
+        res = srv.stop()
+    runs = set()
+    want = {p: [] for p in range(W)}
+    with open(log) as fh:
+        for line in fh:
+            q = line.split()
+            if q and q[0] == "P":
+                run, cid, w, m = int(q[1]), int(q[2]), int(q[3]), int(q[4], 16)
+                runs.add(run)
+                if seen[w] is not None and run <= seen[w]:
+                    want[w].append((cid, w, m))
+    print(f"[serve] late pollers: {res['runs']} runs, {len(runs)} with records", flush=True)
+    assert len(runs) > 10
+    for p in range(W):
+        g = np.sort(np.concatenate(got[p]).astype(REC), order=["clause_id", "word", "mask"])
+        e = np.sort(np.array(want[p], dtype=REC), order=["clause_id", "word", "mask"])
+        assert len(e) > 0 and len(g) == len(e) and (g == e).all(), f"producer {p}: {len(g)} vs {len(e)}"
+
+
 def test_snapshot_alone_equals_snapshot_in_mix():
     V, W = 2000, 8
     lits, offs = _store(43, 15_000, V)
