@@ -87,7 +87,9 @@ typedef struct gss_config {
     void *alloc_user;
     uint32_t hot_vars;          /* LDS staging of the rows of the hot_vars most frequent variables (0 = off);
                                    see gss_rank_vars */
-    uint32_t reserved;
+    uint32_t timing_interval;   /* the test kernel is timed with HIP events on every timing_interval-th
+                                   launch (0 or 1: every launch); the events cost the stream a few
+                                   microseconds per launch.  See gss_stats.timed_launches */
 } gss_config;
 
 /* Creates a context on the current HIP device.  Planes start all-Undef and no slot
@@ -296,9 +298,9 @@ typedef struct gss_stats {
     uint64_t compactions;
     uint64_t regrows;           /* report-buffer regrowths */
     uint64_t kernel_launches;   /* test kernel launches (reruns included) */
-    double last_kernel_ms;      /* duration of the last test kernel, from HIP events on the context stream */
-    double total_kernel_ms;     /* sum over test kernel launches since the last reset */
-    uint64_t timed_launches;    /* launches summed in total_kernel_ms */
+    double last_kernel_ms;      /* duration of the last timed test kernel, from HIP events on the context stream */
+    double total_kernel_ms;     /* sum over the timed test kernel launches since the last reset */
+    uint64_t timed_launches;    /* launches summed in total_kernel_ms (every gss_config.timing_interval-th) */
     /* the last test, when it ran with GSS_TEST_COUNT (else 0): */
     uint64_t last_gathers;      /* plane-row reads of the kernel's lanes: a lane reads its (up to 4) words of the
                                    row of each literal it tests (with GSS_TEST_AGGREGATE, of each literal of a

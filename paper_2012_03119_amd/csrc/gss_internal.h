@@ -207,7 +207,7 @@ struct Ctx {
     uint32_t *dsmall = nullptr;              // 256 B device scratch for flags
     uint32_t *hsmall = nullptr;              // 256 B pinned host
     void *d_desc = nullptr;                  // device copy of the test kernel's bucket descriptors
-    uint64_t desc_version = ~0ull;           // store version the device copy describes
+    std::vector<BucketDesc> desc_shadow;     // what the device copy holds (uploaded again only when it differs)
     void *hsmall_desc = nullptr;             // pinned host staging of the same
     uint64_t test_serial = 0;  // tests completed by this context
     uint64_t n_reports = 0;  // records found by the last test
@@ -243,6 +243,7 @@ struct Ctx {
     size_t hstage_bytes = 0;
 
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    bool timed = false;  // the last launched test kernel has timing events
     hipEvent_t ev_stage = nullptr;  // recorded after the last queued use of the staging buffers
     // queued deltas: their variable lists go up on a copy stream of their own while
     // the test ahead of them runs (created by the first gss_set_var_values_async)

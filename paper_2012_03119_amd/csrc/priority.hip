@@ -445,21 +445,36 @@ __global__ __launch_bounds__(256) void k_prio_collect(ProbeArgs a, uint64_t n_id
 }
 
 
-// Schedule bits of one length class: bit s of word s / 32 set when slot s holds
-// a live low-priority clause.  Grid over 64-slot groups.
-__global__ void k_sched_bits(const uint2 *meta, uint64_t n_slots, const uint8_t *low, uint32_t *bits,
-                             uint64_t n_words) {
-    const uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+// Schedule bits of every length class in one launch: bit s of word s / 32 of a
+// class is set when slot s holds a live low-priority clause.  Workgroup g takes
+// 256 slots of the class whose block range holds g.
+struct SchedBitsClass {
+    const uint2 *meta;
+    uint32_t *bits;
+    uint64_t n_slots, n_words;
+    uint32_t block_begin;
+};
+
+struct SchedBitsTable {
+    SchedBitsClass cls[kMaxBuckets];
+    uint32_t n;
+};
+
+__global__ __launch_bounds__(256) void k_sched_bits(const SchedBitsTable tab, const uint8_t *low) {
+    uint32_t c = 0;
+    while (c + 1 < tab.n && blockIdx.x >= tab.cls[c + 1].block_begin) ++c;
+    const SchedBitsClass &C = tab.cls[c];
+    const uint64_t s = (uint64_t)(blockIdx.x - C.block_begin) * 256 + threadIdx.x;
     bool b = false;
-    if (s < n_slots) {
-        const uint2 m = meta[s];
+    if (s < C.n_slots) {
+        const uint2 m = C.meta[s];
         b = m.x != 0 && low[m.y];
     }
     const uint64_t bal = __ballot(b);
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t w = (s - lane) / 32;
-    if (lane == 0 && w < n_words) bits[w] = (uint32_t)bal;
-    if (lane == 32 && w + 1 < n_words) bits[w + 1] = (uint32_t)(bal >> 32);
+    if (lane == 0 && w < C.n_words) C.bits[w] = (uint32_t)bal;
+    if (lane == 32 && w + 1 < C.n_words) C.bits[w + 1] = (uint32_t)(bal >> 32);
 }
 
 __global__ __launch_bounds__(256) void k_prio_mark(ProbeArgs a, const uint8_t *low, uint64_t n, uint32_t *counters) {
@@ -621,6 +636,8 @@ uint32_t priority_schedule(Ctx &c) {
     for (int b = 0; b < kMaxBuckets && fresh; ++b)
         fresh = c.buckets[b].low_words >= (c.buckets[b].cap_slots + 31) / 32;
     if (!fresh) {
+        SchedBitsTable tab{};
+        uint32_t blocks = 0;
         for (int b = 0; b < kMaxBuckets; ++b) {
             Bucket &B = c.buckets[b];
             if (B.cap_slots == 0) continue;
@@ -633,8 +650,11 @@ uint32_t priority_schedule(Ctx &c) {
                 B.low = (uint32_t *)c.dalloc(words * 4);
                 B.low_words = words;
             }
-            hipLaunchKernelGGL(k_sched_bits, dim3(grid_of(B.low_words * 32)), dim3(256), 0, c.stream, B.meta,
-                               B.n_slots, p.low, B.low, B.low_words);
+            tab.cls[tab.n++] = SchedBitsClass{B.meta, B.low, B.n_slots, B.low_words, blocks};
+            blocks += (uint32_t)((B.low_words * 32 + 255) / 256);
+        }
+        if (blocks) {  // every class in one launch
+            hipLaunchKernelGGL(k_sched_bits, dim3(blocks), dim3(256), 0, c.stream, tab, (const uint8_t *)p.low);
             GSS_HIP(hipGetLastError());
         }
         p.built_version = c.version;

@@ -99,6 +99,8 @@ static Launch prepare(Ctx &c, uint32_t flags) {
         if (!c.sched_counts) c.sched_counts = (uint32_t *)c.dalloc(kMaxBuckets * 4);
         launch_fill_u32(c, c.sched_counts, kMaxBuckets, 0);
     }
+    SchedTable st{};
+    uint32_t sched_blocks = 0;
     for (int b = 0; b < kMaxBuckets; ++b) {
         const Bucket &B = c.buckets[b];
         if (B.n_slots == 0 || B.n_dead == B.n_slots) continue;
@@ -116,14 +118,17 @@ static Launch prepare(Ctx &c, uint32_t flags) {
         if (listed) {
             d.list = c.sched_list + list_off;
             d.list_count = c.sched_counts + nb;
-            const unsigned grid = (unsigned)((B.n_slots + 1023) / 1024);
-            hipLaunchKernelGGL(k_sched_list, dim3(grid), dim3(256), 0, c.stream, B.meta, B.low, B.n_slots, a.sched_run,
-                               c.sched_list + list_off, c.sched_counts + nb);
-            GSS_HIP(hipGetLastError());
+            st.cls[st.n++] = SchedClass{B.meta, B.low, c.sched_list + list_off, c.sched_counts + nb, (uint32_t)B.n_slots,
+                                        sched_blocks};
+            sched_blocks += (uint32_t)((B.n_slots + kSchedSlots - 1) / kSchedSlots);
             list_off += B.n_slots;
         }
         h[nb++] = d;
         tiles += (uint32_t)((B.n_slots + c.T - 1) / c.T);
+    }
+    if (listed && sched_blocks) {  // every class's list in one launch
+        hipLaunchKernelGGL(k_sched_list, dim3(sched_blocks), dim3(kSchedThreads), 0, c.stream, st, a.sched_run);
+        GSS_HIP(hipGetLastError());
     }
     a.n_buckets = nb;
     a.n_tiles = tiles;
@@ -163,10 +168,11 @@ static Launch prepare(Ctx &c, uint32_t flags) {
             a.saggu = c.saggu;
         }
     }
-    // the device copy stays valid while the store is unchanged (schedule bits and lists may move: always upload then)
-    if (nb && (sched || c.desc_version != c.version)) {
+    // the device copy is uploaded again only when the descriptors changed (a
+    // growth, compaction or new schedule arrays; not a removal or a delta)
+    if (nb && (c.desc_shadow.size() != nb || std::memcmp(c.desc_shadow.data(), h, nb * sizeof(BucketDesc)) != 0)) {
         GSS_HIP(hipMemcpyAsync(c.d_desc, h, nb * sizeof(BucketDesc), hipMemcpyHostToDevice, c.stream));
-        c.desc_version = sched ? ~0ull : c.version;
+        c.desc_shadow.assign(h, h + nb);
     }
     L.descs = (const BucketDesc *)c.d_desc;
     L.fn = pick_kernel(c.RWc, (flags & GSS_TEST_TRIGGER) ? 1 : 0, hot, a.agg != nullptr, c.G > 1, listed);
@@ -199,16 +205,18 @@ static Segments context_segments(Ctx &c) { return Segments{c.reports, c.seg_coun
 // Queues the test kernel and the finalize kernel, which writes the summary and
 // the test's serial into pinned host memory.
 static void launch(Ctx &c, const Launch &L, uint32_t flags, const Segments &sg) {
-    // timing events around the kernel (attaching them to the dispatch instead,
-    // with hipExtLaunchKernel, measured slower: 24 against 10 us of host time per
-    // launch, on the path between two tests)
-    GSS_HIP(hipEventRecord(c.ev_start, c.stream));
+    const uint64_t serial = c.tests_launched + 1;
+    // timing events around the kernel on every timing_interval-th launch (each
+    // event leaves the stream idle for a few microseconds; attaching them to the
+    // dispatch instead, with hipExtLaunchKernel, measured slower: 24 against 10 us
+    // of host time per launch, on the path between two tests)
+    c.timed = serial % std::max<uint32_t>(1u, c.cfg.timing_interval) == 0;
+    if (c.timed) GSS_HIP(hipEventRecord(c.ev_start, c.stream));
     hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(kTestWavesPerBlock * 64), L.lds, c.stream, L.descs, L.args,
                        (flags & GSS_TEST_NO_EARLY_EXIT) ? 0u : 1u, (flags & GSS_TEST_DENSE) ? 1u : 0u);
     GSS_HIP(hipGetLastError());
-    GSS_HIP(hipEventRecord(c.ev_stop, c.stream));
+    if (c.timed) GSS_HIP(hipEventRecord(c.ev_stop, c.stream));
     const uint32_t n_waves = L.grid * kTestWavesPerBlock;
-    const uint64_t serial = c.tests_launched + 1;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, c.stream, sg.counts, n_waves, sg.cap, sg.offsets,
                        c.d_summary, deferred_flag(c), c.hd_summary, (unsigned long long)serial);
     GSS_HIP(hipGetLastError());
@@ -247,13 +255,14 @@ static void complete(Ctx &c) {
     }
     c.tests_completed = c.tests_launched;
     c.release_deferred();
+    c.stats.kernel_launches++;
+    if (!c.timed) return;
     GSS_HIP(hipEventSynchronize(c.ev_stop));  // recorded before the finalize kernel: already complete
     float ms = 0.f;
     GSS_HIP(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
     c.stats.last_kernel_ms = ms;
     c.stats.total_kernel_ms += ms;
     c.stats.timed_launches++;
-    c.stats.kernel_launches++;
 }
 
 // Checks flags and prepares a test; returns false when there is nothing to launch.

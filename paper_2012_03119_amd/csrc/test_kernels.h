@@ -129,42 +129,81 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test_list(const Buc
     }
 }
 
-// The slots of one length class that a scheduled run tests (alive, and not a
-// low-priority clause off its turn: (run + id) % 4 != 0), in slot order within
-// each workgroup's 1024 slots; a workgroup claims its range of the list with one
-// atomic on *count.
-__global__ __launch_bounds__(256) void k_sched_list(const uint2 *meta, const uint32_t *low_bits, uint64_t n_slots,
-                                                    uint32_t run, uint32_t *list, uint32_t *count) {
-    __shared__ uint32_t pre[256];
+// The slots that a scheduled run tests (alive, and not a low-priority clause off
+// its turn: (run + id) % 4 != 0), one list per length class, built by one launch
+// over every class: workgroup g takes kSchedSlots consecutive slots of the class
+// whose block range holds g, 32 per thread (one word of schedule bits; their 256
+// bytes of metadata are loaded at once), and claims its range of the class's
+// list with one atomic on its count (one per 8192 slots: the counters see few
+// atomics).  In slot order within a workgroup.
+constexpr uint32_t kSchedThreads = 256, kSchedSlots = 32 * kSchedThreads;
+
+struct SchedClass {
+    const uint2 *meta;
+    const uint32_t *low;  // one bit per slot
+    uint32_t *list;
+    uint32_t *count;
+    uint32_t n_slots;
+    uint32_t block_begin;  // first workgroup of the class
+};
+
+struct SchedTable {
+    SchedClass cls[kMaxBuckets];
+    uint32_t n;
+};
+
+__global__ __launch_bounds__(kSchedThreads) void k_sched_list(const SchedTable tab, uint32_t run) {
+    __shared__ uint32_t wave_sum[kSchedThreads / 64];
     __shared__ uint32_t base;
-    const uint32_t t = threadIdx.x;
-    const uint64_t s0 = (uint64_t)blockIdx.x * 1024 + 4ull * t;
+    uint32_t b = 0;
+    while (b + 1 < tab.n && blockIdx.x >= tab.cls[b + 1].block_begin) ++b;
+    const SchedClass &C = tab.cls[b];
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t s0 = (blockIdx.x - C.block_begin) * kSchedSlots + 32u * t;  // one low word
     uint32_t flags = 0;
+    if (s0 < C.n_slots) {
+        const uint32_t lw = C.low[s0 >> 5];
+        if (s0 + 32 <= C.n_slots) {
+            // 32 slots' metadata in sixteen 16-byte loads, all in flight together
+            const uint4 *mp = reinterpret_cast<const uint4 *>(C.meta + s0);
+            uint4 q[16];
 #pragma unroll
-    for (uint32_t k = 0; k < 4; ++k) {
-        const uint64_t s = s0 + k;
-        if (s < n_slots) {
-            const uint2 m = meta[s];
-            const bool low = (low_bits[s >> 5] >> (s & 31)) & 1u;
-            const bool tested = m.x != 0 && !(low && ((run + m.y) & 3u) != 0);
-            flags |= (tested ? 1u : 0u) << k;
+            for (uint32_t k = 0; k < 16; ++k) q[k] = mp[k];
+#pragma unroll
+            for (uint32_t k = 0; k < 16; ++k) {
+                const bool t0 = q[k].x != 0 && !(((lw >> (2 * k)) & 1u) && ((run + q[k].y) & 3u) != 0);
+                const bool t1 = q[k].z != 0 && !(((lw >> (2 * k + 1)) & 1u) && ((run + q[k].w) & 3u) != 0);
+                flags |= (t0 ? 1u : 0u) << (2 * k) | (t1 ? 1u : 0u) << (2 * k + 1);
+            }
+        } else {
+            for (uint32_t k = 0; s0 + k < C.n_slots; ++k) {
+                const uint2 m = C.meta[s0 + k];
+                const bool tested = m.x != 0 && !(((lw >> k) & 1u) && ((run + m.y) & 3u) != 0);
+                flags |= (tested ? 1u : 0u) << k;
+            }
         }
     }
     const uint32_t mine = __builtin_popcount(flags);
-    pre[t] = mine;
-    __syncthreads();
-    for (uint32_t off = 1; off < 256; off <<= 1) {  // inclusive scan
-        const uint32_t v = t >= off ? pre[t - off] : 0u;
-        __syncthreads();
-        pre[t] += v;
-        __syncthreads();
-    }
-    if (t == 255) base = pre[255] ? atomicAdd(count, pre[255]) : 0u;
-    __syncthreads();
-    uint32_t pos = base + pre[t] - mine;
+    uint32_t x = mine;  // inclusive scan: within the wavefront, then across
 #pragma unroll
-    for (uint32_t k = 0; k < 4; ++k)
-        if ((flags >> k) & 1u) list[pos++] = (uint32_t)(s0 + k);
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wave_sum[wave] = x;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (uint32_t w = 0; w < kSchedThreads / 64; ++w) {
+            const uint32_t v = wave_sum[w];
+            wave_sum[w] = acc;
+            acc += v;
+        }
+        base = acc ? atomicAdd(C.count, acc) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = base + wave_sum[wave] + x - mine;
+    for (uint32_t f = flags; f; f &= f - 1) C.list[pos++] = s0 + (uint32_t)__builtin_ctz(f);
 }
 
 // summary[3] receives the verdict of the asynchronous updates queued before the

@@ -73,7 +73,7 @@ class gss_config(ctypes.Structure):
         ("dev_free", FREE_FN),
         ("alloc_user", ctypes.c_void_p),
         ("hot_vars", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("timing_interval", ctypes.c_uint32),
     ]
 
 
@@ -571,7 +571,8 @@ class Context:
     """One clause store plus one set of assignment slots on the current GPU."""
 
     def __init__(self, num_vars: int, max_slots: int = 64, *, hbm_budget_bytes: int = 0,
-                 report_capacity: int = 1 << 16, hot_vars: int = 0, use_torch: bool = True, stream=None):
+                 report_capacity: int = 1 << 16, hot_vars: int = 0, use_torch: bool = True, stream=None,
+                 timing_interval: int = 0):
         self.num_vars = int(num_vars)
         self.max_slots = int(max_slots)
         self.n_words = self.max_slots // 64
@@ -582,6 +583,7 @@ class Context:
         cfg.hbm_budget_bytes = hbm_budget_bytes
         cfg.report_capacity = report_capacity
         cfg.hot_vars = hot_vars
+        cfg.timing_interval = timing_interval
         self.torch_stream = None
         self._held, self._held_by_test = [], []  # device inputs of queued updates, kept alive
         if use_torch:

@@ -47,7 +47,7 @@ def test_binding_declares_every_symbol(lib_path):
 
 def test_config_struct_layout_matches_header():
     from paper_2012_03119_amd import gss
-    # num_vars, max_slots (2x4) + budget, capacity (2x8) + 4 pointers + hot_vars, reserved (2x4)
+    # num_vars, max_slots (2x4) + budget, capacity (2x8) + 4 pointers + hot_vars, timing_interval (2x4)
     assert ctypes.sizeof(gss.gss_config) == 8 + 16 + 4 * 8 + 8
     assert gss.REPORT_DTYPE.itemsize == 16
 

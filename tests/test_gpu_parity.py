@@ -829,6 +829,26 @@ def _uniform_word(value, n_vars):
     return np.full((64, n_vars), value, dtype=np.int8)
 
 
+def test_timing_interval_times_every_nth_launch():
+    """timing_interval = 3: of seven tests, launches 3 and 6 carry timing events;
+    every launch is counted and every result is unchanged."""
+    w = gen.tiny(5)
+    with new_context(w.n_vars, 64, timing_interval=3) as ctx:
+        ctx.add_clauses(w.lits, w.offsets)
+        ctx.set_assignments(0, w.values)
+        want = oracle.masks(w.lits, w.offsets, w.values)
+        _check(gpu_dense(ctx, w.n_clauses), want)  # sizes the report segments (may run twice)
+        first = ctx.stats()["kernel_launches"]
+        ctx.reset_stats()
+        for k in range(7):
+            _check(gpu_dense(ctx, w.n_clauses), want)
+            st = ctx.stats()
+            assert st["kernel_launches"] == k + 1
+            # launch serials first + 1 .. first + k + 1; the multiples of 3 are timed
+            assert st["timed_launches"] == (first + k + 1) // 3 - first // 3
+        assert st["last_kernel_ms"] > 0 and st["total_kernel_ms"] >= st["last_kernel_ms"]
+
+
 @pytest.mark.parametrize("max_slots", [128, 1024])
 def test_kernel_counts_in_closed_form(max_slots):
     """GSS_TEST_COUNT: the plane rows the lanes read and the words the aggregate
