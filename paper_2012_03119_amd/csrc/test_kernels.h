@@ -220,8 +220,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const uint32_t *counts, uint3
 #pragma unroll
         for (int k = 0; k < 4; ++k) host_summary[k] = summary[k];
         __threadfence_system();  // the summary reaches the host before the serial
-        host_summary[4] = serial;
-        __threadfence_system();
+        host_summary[4] = serial;  // made visible by the kernel's end
     }
 }
 

@@ -430,49 +430,59 @@ struct Tester {
 
 // Called by one workgroup of 1024 threads: exclusive prefix of the records each
 // segment kept (min(count, cap)) into offsets[0..n], and summary = {total count,
-// largest count, records kept}.
+// largest count, records kept}.  Thread t takes a contiguous share of the
+// segments; the shares are combined within each wavefront by shuffles and across
+// the 16 wavefronts through LDS (two barriers).
 __device__ inline void finalize_segments(const uint32_t *counts, uint32_t n, uint32_t cap, uint64_t *offsets,
                                          unsigned long long *summary) {
-    __shared__ unsigned long long part[1024];
-    __shared__ unsigned long long tot[1024];
-    __shared__ unsigned int mx[1024];
-    const uint32_t tid = threadIdx.x;
+    __shared__ unsigned long long wkept[16], wall[16];
+    __shared__ unsigned int wmax[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t per = (n + 1023) / 1024;
-    const uint32_t lo = tid * per, hi = min(n, lo + per);
+    const uint32_t lo = min(n, tid * per), hi = min(n, lo + per);
     unsigned long long kept = 0, all = 0;
     unsigned int m = 0;
     for (uint32_t i = lo; i < hi; ++i) {
-        kept += min(counts[i], cap);
-        all += counts[i];
-        m = max(m, counts[i]);
+        const uint32_t v = counts[i];
+        kept += min(v, cap);
+        all += v;
+        m = max(m, v);
     }
-    part[tid] = kept;
-    tot[tid] = all;
-    mx[tid] = m;
+    // inclusive scan of kept within the wavefront; sum and max over it
+    unsigned long long x = kept, a = all;
+    unsigned int mm = m;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const unsigned long long y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+        a += __shfl_xor(a, d);
+        mm = max(mm, (unsigned int)__shfl_xor(mm, d));
+    }
+    if (lane == 63) wkept[wave] = x;
+    if (lane == 0) {
+        wall[wave] = a;
+        wmax[wave] = mm;
+    }
     __syncthreads();
-    // inclusive Hillis-Steele scan of part[]; tree reductions of tot[] and mx[]
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        const unsigned long long p = tid >= off ? part[tid - off] : 0ull;
-        const unsigned long long q = (tid + off < 1024) ? tot[tid + off] : 0ull;
-        const unsigned int r = (tid + off < 1024) ? mx[tid + off] : 0u;
-        __syncthreads();
-        part[tid] += p;
-        if ((tid & (2 * off - 1)) == 0) {
-            tot[tid] += q;
-            mx[tid] = max(mx[tid], r);
-        }
-        __syncthreads();
+    unsigned long long before = 0, total_kept = 0, total = 0;
+    unsigned int mx = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < 16; ++w) {
+        before += w < wave ? wkept[w] : 0ull;
+        total_kept += wkept[w];
+        total += wall[w];
+        mx = max(mx, wmax[w]);
     }
-    unsigned long long base = tid ? part[tid - 1] : 0ull;
+    unsigned long long base = before + x - kept;
     for (uint32_t i = lo; i < hi; ++i) {
         offsets[i] = base;
         base += min(counts[i], cap);
     }
-    if (tid == 1023) offsets[n] = part[1023];
     if (tid == 0) {
-        summary[0] = tot[0];
-        summary[1] = mx[0];
-        summary[2] = part[1023];
+        offsets[n] = total_kept;
+        summary[0] = total;
+        summary[1] = mx;
+        summary[2] = total_kept;
     }
 }
 
