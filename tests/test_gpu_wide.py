@@ -58,6 +58,22 @@ def test_wide_rows_all_modes(max_slots):
         _check_all(ctx, lits, offsets, vals, active, n)
 
 
+def test_maximum_width():
+    """262144 slots, the largest max_slots: 4096 words in 64 chunks, so the
+    super-group mask uses all 64 bits; the last word's slots are left inactive."""
+    n_vars, n, max_slots = 200, 400, 262144
+    print("wide max_slots=262144", flush=True)
+    lits, offsets = _clauses(77, n, n_vars)
+    vals = _values(78, max_slots, n_vars)
+    vals[-64:] = 0
+    with gss.Context(n_vars, max_slots, report_capacity=1 << 22) as ctx:
+        ctx.add_clauses(lits, offsets)
+        ctx.set_assignments(0, vals[:-64])
+        active = np.zeros(max_slots, dtype=bool)
+        active[:-64] = True
+        _check_all(ctx, lits, offsets, vals, active, n)
+
+
 @pytest.mark.parametrize("max_slots,first,count", [(4160, 0, 4160), (12288, 64, 8000), (8192, 4096, 4096)])
 def test_wide_rows_partial_chunks(max_slots, first, count):
     """The last chunk partly used (4160 slots: a chunk of one word), unused chunks
