@@ -32,12 +32,52 @@ def _hipcc() -> str:
 
 def build(verbose: bool = False, extra_flags=()) -> str:
     """Compiles every source (always) and links libgss.so next to this file."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+    return _build_library(OUT, BUILD_DIR, HIPCC_FLAGS + list(extra_flags), verbose)
+
+
+# The host sanitizer run (tests/test_gpu_host_sanitized.py): the library with its
+# host code under AddressSanitizer and UndefinedBehaviorSanitizer (each option
+# applies to the host pass only; the device code is built as usual), and a driver
+# built with the same sanitizers that exercises it through the C ABI.
+SAN_DIR = os.path.join(ROOT, "tests", "sanitize")
+SAN_LIB = os.path.join(SAN_DIR, "libgss_host_san.so")
+SAN_DRIVER = os.path.join(SAN_DIR, "host_driver")
+HOST_SANITIZERS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                   "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+DRIVER_SANITIZERS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """Builds the sanitized library and its driver into tests/sanitize."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    clang = os.path.join(rocm, "lib", "llvm", "bin", "clang")
+    obj_dir = os.path.join(BUILD_DIR, "host_san")
+    _build_library(SAN_LIB, obj_dir, HIPCC_FLAGS + ["-g"] + HOST_SANITIZERS, verbose)
+    oracle_obj = os.path.join(obj_dir, "oracle.o")
+    steps = [
+        [clang, "-O1", "-g", *DRIVER_SANITIZERS, "-c", os.path.join(ROOT, "oracle", "oracle.c"), "-o", oracle_obj],
+        [clang + "++", "-O1", "-g", "-std=c++17", *DRIVER_SANITIZERS, "-D__HIP_PLATFORM_AMD__",
+         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(rocm, "include"),
+         os.path.join(SAN_DIR, "host_driver.cpp"), oracle_obj, "-o", SAN_DRIVER + ".tmp",
+         "-L", SAN_DIR, "-lgss_host_san", "-Wl,-rpath,$ORIGIN",
+         "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(rocm, "lib")],
+    ]
+    for cmd in steps:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"sanitized driver build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(SAN_DRIVER + ".tmp", SAN_DRIVER)
+    return SAN_DRIVER
+
+
+def _build_library(out: str, obj_dir: str, flags, verbose: bool) -> str:
+    os.makedirs(obj_dir, exist_ok=True)
     hipcc = _hipcc()
-    flags = HIPCC_FLAGS + list(extra_flags)
 
     def compile_one(src):
-        obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
+        obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
         cmd = [hipcc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -50,13 +90,13 @@ def build(verbose: bool = False, extra_flags=()) -> str:
 
     with ThreadPoolExecutor(len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

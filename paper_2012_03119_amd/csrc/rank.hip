@@ -131,8 +131,10 @@ bool rank_vars(Ctx &c) {
     uint64_t *d_tmp = (uint64_t *)(d + remap_pad + 2 * list_bytes);
     char *h = (char *)c.host_stage(2 * remap_pad + 2 * list_bytes);  // the map, the lists, then the new perm
     std::memcpy(h, remap.data(), remap_bytes);
-    std::memcpy(h + remap_pad, moved_from.data(), (size_t)n_mv * 4);
-    std::memcpy(h + remap_pad + list_bytes, moved_to.data(), (size_t)n_mv * 4);
+    if (n_mv) {  // (empty lists may hold no storage at all)
+        std::memcpy(h + remap_pad, moved_from.data(), (size_t)n_mv * 4);
+        std::memcpy(h + remap_pad + list_bytes, moved_to.data(), (size_t)n_mv * 4);
+    }
     GSS_HIP(hipMemcpyAsync(d, h, remap_pad + 2 * list_bytes, hipMemcpyHostToDevice, c.stream));
     for (Bucket &B : c.buckets) {
         if (B.cap_slots == 0) continue;

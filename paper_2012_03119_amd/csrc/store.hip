@@ -545,6 +545,7 @@ extern "C" gss_status gss_remove_clauses(gss_ctx *ctx, const uint32_t *ids, uint
         for (int b = 0; b < kMaxBuckets; ++b) total += per[b].size();
         size_t off = 0;
         for (int b = 0; b < kMaxBuckets; ++b) {
+            if (per[b].empty()) continue;  // (an empty vector may hold no storage at all)
             std::memcpy(st.h + off * 8, per[b].data(), per[b].size() * 8);
             off += per[b].size();
         }
