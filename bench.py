@@ -132,7 +132,7 @@ def bench_batched(args, torch, gss):
     t0 = time.perf_counter()
     stream = torch.cuda.Stream()
     stores = []
-    n_rounds = min(max(args.warmup, 8) + args.steps, 19)
+    n_rounds = min(max(args.warmup, 8) + 2 * args.steps + 1, 40)
     for i, (n, v, a) in enumerate(BATCHED_STORES):
         w = gen.paper(300 + i, n_clauses=n, n_vars=v, n_slots=a)
         ctx = gss.Context(v, a, stream=stream, report_capacity=1 << 22)
@@ -157,34 +157,60 @@ def bench_batched(args, torch, gss):
     # the size of a store's delta on first use
     warm = max(args.warmup, 8)
 
-    def run(step_fn):
+    def store_delta(s, i):
+        _, ctx, rounds = stores[s]
+        vs, delta = rounds[i % len(rounds)]
+        ctx.set_var_values_async(0, vs, delta)
+
+    # A round is every store's delta and test.  Both forms pipeline the rounds the
+    # same way: the next round's deltas are queued behind the test in flight, so
+    # their host work overlaps the kernels (batched: gss_batch_test_async, the 8
+    # deltas, gss_batch_wait; plain: per store gss_test_async, its next delta,
+    # gss_test_wait).
+    def round_batched(i, last):
+        batch.test_async(gss.GSS_TEST_GRAPH)
+        if not last:
+            deltas(i + 1)
+        batch.wait()
+
+    def round_plain(i, last):
+        for s, (_, ctx, _) in enumerate(stores):
+            ctx.test_async()
+            if not last:
+                store_delta(s, i + 1)
+            ctx.test_wait()
+
+    def run(round_fn, tests_fn):
         """(ms per round with the deltas, ms per round of the tests alone)"""
+        deltas(0)
         for i in range(warm):
-            deltas(i)
-            step_fn()
+            round_fn(i, False)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        t_test = 0.0
+        for i in range(warm, warm + args.steps):
+            round_fn(i, i == warm + args.steps - 1)
+        torch.cuda.synchronize()
+        t_round = (time.perf_counter() - t) / args.steps
+        t_test = 0.0  # the tests alone: each round's deltas applied, untimed, first
         for i in range(args.steps):
-            deltas(warm + i)
+            deltas(warm + args.steps + i)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            step_fn()
+            tests_fn()
             torch.cuda.synchronize()
             t_test += time.perf_counter() - t1
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / args.steps, t_test / args.steps
+        return t_round, t_test / args.steps
 
-    def batched_step():
+    def batched_tests():
         batch.test(gss.GSS_TEST_GRAPH)
 
-    def plain_step():
+    def plain_tests():
         for _, ctx, _ in stores:
             ctx.test()
 
-    t_batch, t_batch_test = run(batched_step)
+    t_batch, t_batch_test = run(round_batched, batched_tests)
     graph_ms = batch.info()["last_ms"]
-    t_plain, t_plain_test = run(plain_step)
+    t_plain, t_plain_test = run(round_plain, plain_tests)
     pairs = sum(ctx.stats()["last_pairs"] for _, ctx, _ in stores)
     out = {
         "metric": "clause x assignment tests/sec (batched: 8 databases, one persistent launch)",
@@ -197,7 +223,9 @@ def bench_batched(args, torch, gss):
                    ("order", "chunk_tiles", "blocks_per_cu")}, "graph_launch_ms": graph_ms},
         "tests_ms_per_round": t_batch_test * 1e3,
         "plain": {"value": pairs / t_plain, "ms_per_step": t_plain * 1e3, "tests_ms_per_round": t_plain_test * 1e3,
-                  "how": "the same rounds, one gss_test per database"},
+                  "how": "the same rounds, one gss_test_async/gss_test_wait per database, each database's next "
+                         "delta queued behind its test"},
+        "how": "rounds pipelined: gss_batch_test_async, the next round's 8 queued deltas, gss_batch_wait",
         "speedup_vs_plain": t_plain / t_batch,
         "tests_speedup_vs_plain": t_plain_test / t_batch_test,
     }

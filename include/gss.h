@@ -363,6 +363,18 @@ gss_status gss_batch_set_schedule(gss_batch *batch, const gss_schedule *schedule
  * GSS_ERR_REPORT_OVERFLOW, with exact counts). */
 gss_status gss_batch_test(gss_batch *batch, uint32_t flags, uint64_t *out_n_reports);
 
+/* The same test queued without waiting, so that the next round's updates
+ * (gss_set_var_values_async on the members) can be queued while it runs: the
+ * host work of those calls then overlaps the batched kernel.  Until
+ * gss_batch_wait, the members count as having a test in flight (gss_test on them,
+ * gss_fetch_reports and the like: GSS_ERR_STATE; gss_test_wait on a member: STATE,
+ * naming gss_batch_wait).  gss_batch_wait returns what gss_batch_test would; a
+ * store that overflowed is grown, and the batch repeated only when no member has
+ * changed since the launch (else GSS_ERR_REPORT_OVERFLOW with exact counts, and
+ * the next test fits). */
+gss_status gss_batch_test_async(gss_batch *batch, uint32_t flags);
+gss_status gss_batch_wait(gss_batch *batch, uint64_t *out_n_reports);
+
 /* Duration of the last batched launch sequence in ms (HIP events around it),
  * launches and graph captures so far, and the tiles of the last plan. */
 gss_status gss_batch_info(const gss_batch *batch, double *last_ms, uint64_t *launches, uint64_t *captures,

@@ -153,6 +153,10 @@ struct gss_batch {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
     std::string last_error;
+    // gss_batch_test_async issued, gss_batch_wait not yet called
+    bool pending = false;
+    uint32_t pending_flags = 0;
+    std::vector<uint64_t> launch_mutations;  // each member's change count when the test was queued
 };
 
 namespace {
@@ -168,6 +172,12 @@ void free_graph(gss_batch &b) {
 void destroy_batch(gss_batch *b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->pending)  // destroyed with a test in flight: the members are usable again
+        for (Ctx *c : b->ctxs) {
+            c->pending = false;
+            c->batch_pending = false;
+            c->mark_idle();
+        }
     free_graph(*b);
     Ctx &c0 = *b->ctxs[0];
     c0.dfree(b->d_stores);
@@ -344,10 +354,10 @@ bool same_schedule(const gss_schedule &x, const gss_schedule &y) {
     return x.order == y.order && x.chunk_tiles == y.chunk_tiles && x.blocks_per_cu == y.blocks_per_cu;
 }
 
-// One batched test: plans (unless a valid graph is replayed), launches, and
-// publishes every store's counts into its context.  Returns true when some store
-// overflowed its report segments.
-bool run_once(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
+// Queues one batched test: plans (unless a valid graph is replayed) and
+// launches.  Every member counts it as a test of its own: its serial releases
+// the upload slots and deferred frees queued before it once it has completed.
+void launch_batch(gss_batch &b, uint32_t flags) {
     const uint32_t n = (uint32_t)b.ctxs.size();
     const bool use_graph = flags & GSS_TEST_GRAPH;
     const bool moved = refresh_aggregates(b, flags);
@@ -376,7 +386,20 @@ bool run_once(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
     else
         enqueue(b, flags);
     GSS_HIP(hipEventRecord(b.ev1, b.stream));
-    GSS_HIP(hipStreamSynchronize(b.stream));
+    b.launch_mutations.resize(n);
+    for (uint32_t s = 0; s < n; ++s) {
+        Ctx &c = *b.ctxs[s];
+        c.tests_launched++;
+        b.launch_mutations[s] = c.mutations;
+    }
+}
+
+// Waits for the queued batched test (work queued after it may still run) and
+// publishes every store's counts into its context.  Returns true when some store
+// overflowed its report segments.
+bool complete_batch(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
+    const uint32_t n = (uint32_t)b.ctxs.size();
+    GSS_HIP(hipEventSynchronize(b.ev1));
     float ms = 0.f;
     GSS_HIP(hipEventElapsedTime(&ms, b.ev0, b.ev1));
     b.last_ms = ms;
@@ -387,7 +410,8 @@ bool run_once(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
     uint64_t act = 0;
     for (uint32_t s = 0; s < n; ++s) {
         Ctx &c = *b.ctxs[s];
-        c.mark_idle();  // the shared stream was synchronised above
+        c.tests_completed = c.tests_launched;  // the batch was the member's last queued test
+        c.release_deferred();
         const unsigned long long *sum = b.h_summary + 4 * s;
         c.last_waves = b.grid * kTestWavesPerBlock;
         c.n_reports = sum[0];
@@ -435,6 +459,22 @@ bool run_once(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
     }
     GSS_REQUIRE(bad == GSS_OK, bad, why);
     return overflow;
+}
+
+// One batched test, waited for.
+bool run_once(gss_batch &b, uint32_t flags, bool &any_overflow_growable) {
+    launch_batch(b, flags);
+    return complete_batch(b, flags, any_overflow_growable);
+}
+
+void check_batch_flags(const gss_batch &b, uint32_t flags) {
+    const uint32_t known =
+        GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_REGROW | GSS_TEST_GRAPH | GSS_TEST_AGGREGATE;
+    GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "flag not supported by gss_batch_test");
+    GSS_REQUIRE(!b.pending, GSS_ERR_STATE, "the batch has a test in flight (call gss_batch_wait)");
+    // a member's asynchronous test would have its report segments overwritten
+    for (const Ctx *c : b.ctxs)
+        GSS_REQUIRE(!c->pending, GSS_ERR_STATE, "a member context has a test in flight (call gss_test_wait)");
 }
 
 }  // namespace
@@ -514,12 +554,7 @@ extern "C" gss_status gss_batch_set_schedule(gss_batch *b, const gss_schedule *s
 
 extern "C" gss_status gss_batch_test(gss_batch *b, uint32_t flags, uint64_t *out_n_reports) {
     GSS_BATCH_BEGIN(b)
-    const uint32_t known =
-        GSS_TEST_TRIGGER | GSS_TEST_NO_EARLY_EXIT | GSS_TEST_NO_REGROW | GSS_TEST_GRAPH | GSS_TEST_AGGREGATE;
-    GSS_REQUIRE((flags & ~known) == 0, GSS_ERR_INVALID_ARG, "flag not supported by gss_batch_test");
-    // a member's asynchronous test would have its report segments overwritten
-    for (const Ctx *c : b_->ctxs)
-        GSS_REQUIRE(!c->pending, GSS_ERR_STATE, "a member context has a test in flight (call gss_test_wait)");
+    check_batch_flags(*b_, flags);
     bool grown = false;
     bool overflow = run_once(*b_, flags, grown);
     if (overflow && grown) overflow = run_once(*b_, flags, grown);
@@ -527,6 +562,50 @@ extern "C" gss_status gss_batch_test(gss_batch *b, uint32_t flags, uint64_t *out
     if (out_n_reports)
         for (uint32_t s = 0; s < n; ++s) out_n_reports[s] = b_->ctxs[s]->n_reports;
     GSS_REQUIRE(!overflow, GSS_ERR_REPORT_OVERFLOW, "a store's report segments overflowed; its counts are exact");
+    GSS_BATCH_END
+}
+
+extern "C" gss_status gss_batch_test_async(gss_batch *b, uint32_t flags) {
+    GSS_BATCH_BEGIN(b)
+    check_batch_flags(*b_, flags);
+    launch_batch(*b_, flags);
+    b_->pending = true;
+    b_->pending_flags = flags;
+    for (Ctx *c : b_->ctxs) {
+        c->pending = true;
+        c->batch_pending = true;
+    }
+    GSS_BATCH_END
+}
+
+extern "C" gss_status gss_batch_wait(gss_batch *b, uint64_t *out_n_reports) {
+    GSS_BATCH_BEGIN(b)
+    GSS_REQUIRE(b_->pending, GSS_ERR_STATE, "no batched test in flight");
+    b_->pending = false;
+    for (Ctx *c : b_->ctxs) {
+        c->pending = false;
+        c->batch_pending = false;
+    }
+    const uint32_t flags = b_->pending_flags;
+    const uint32_t n = (uint32_t)b_->ctxs.size();
+    bool grown = false;
+    bool overflow = false;
+    try {
+        overflow = complete_batch(*b_, flags, grown);
+        // repeated at once only when no member has changed since the launch (a
+        // change queued behind the test would be read by the repeat)
+        bool unchanged = true;
+        for (uint32_t s = 0; s < n; ++s) unchanged = unchanged && b_->ctxs[s]->mutations == b_->launch_mutations[s];
+        if (overflow && grown && unchanged) overflow = run_once(*b_, flags, grown);
+    } catch (...) {
+        if (out_n_reports)
+            for (uint32_t s = 0; s < n; ++s) out_n_reports[s] = b_->ctxs[s]->n_reports;
+        throw;
+    }
+    if (out_n_reports)
+        for (uint32_t s = 0; s < n; ++s) out_n_reports[s] = b_->ctxs[s]->n_reports;
+    GSS_REQUIRE(!overflow, GSS_ERR_REPORT_OVERFLOW,
+                "a store's report segments overflowed (now grown); its counts are exact: test again");
     GSS_BATCH_END
 }
 

@@ -251,7 +251,9 @@ struct Ctx {
     hipEvent_t ev_copy = nullptr;
     uint64_t tests_launched = 0;    // serial of the last queued test (its finalize kernel writes it to h_summary[4])
     uint64_t tests_completed = 0;   // serial of the last test seen complete (or of all, after a sync)
-    bool pending = false;           // gss_test_async issued, gss_test_wait not yet called
+    bool pending = false;           // gss_test_async issued, gss_test_wait not yet called (or a batched test
+                                    // of which the context is a member, gss_batch_wait not yet called)
+    bool batch_pending = false;     // the test in flight is a batch's
     bool pending_launched = false;
     uint32_t pending_flags = 0;
     bool stage_pending = false;

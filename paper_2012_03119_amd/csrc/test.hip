@@ -415,6 +415,7 @@ extern "C" gss_status gss_test_wait(gss_ctx *ctx, uint64_t *out_n_reports) {
     GSS_API_BEGIN(ctx)
     Ctx &c = *c_;
     GSS_REQUIRE(c.pending, GSS_ERR_STATE, "no test in flight");
+    GSS_REQUIRE(!c.batch_pending, GSS_ERR_STATE, "the test in flight is a batch's (call gss_batch_wait)");
     c.pending = false;
     if (out_n_reports) *out_n_reports = 0;
     try {
@@ -440,6 +441,7 @@ extern "C" gss_status gss_test_query(gss_ctx *ctx, int *done) {
     Ctx &c = *c_;
     GSS_REQUIRE(done != nullptr, GSS_ERR_INVALID_ARG, "null argument");
     GSS_REQUIRE(c.pending, GSS_ERR_STATE, "no test in flight");
+    GSS_REQUIRE(!c.batch_pending, GSS_ERR_STATE, "the test in flight is a batch's (call gss_batch_wait)");
     if (!c.pending_launched) {
         *done = 1;
     } else {

@@ -183,6 +183,8 @@ def load_library(path: Optional[str] = None):
         "gss_batch_last_error": ([P], ctypes.c_char_p),
         "gss_batch_set_schedule": ([P, ctypes.POINTER(gss_schedule)], ctypes.c_int32),
         "gss_batch_test": ([P, u32, P], ctypes.c_int32),
+        "gss_batch_test_async": ([P, u32], ctypes.c_int32),
+        "gss_batch_wait": ([P, P], ctypes.c_int32),
         "gss_batch_info": ([P, P, P, P, P], ctypes.c_int32),
         "gss_mlp_forward": ([P, P, P, u32, P], ctypes.c_int32),
         "gss_mlp_loss_grad": ([P, P, P, P, u32, P, P], ctypes.c_int32),
@@ -448,6 +450,16 @@ def gss_batch_set_schedule(b, order: int, chunk_tiles: int = 0, blocks_per_cu: i
 def gss_batch_test(b, n: int, flags: int = 0) -> np.ndarray:
     out = np.zeros(n, dtype=np.uint64)
     _check_batch(b, load_library().gss_batch_test(b, flags, _np_ptr(out)))
+    return out
+
+
+def gss_batch_test_async(b, flags: int = 0) -> None:
+    _check_batch(b, load_library().gss_batch_test_async(b, flags))
+
+
+def gss_batch_wait(b, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.uint64)
+    _check_batch(b, load_library().gss_batch_wait(b, _np_ptr(out)))
     return out
 
 
@@ -868,6 +880,20 @@ class Batch:
         for c in self.contexts:  # their queued updates have been read
             c._held = []
         return counts
+
+    def test_async(self, flags: int = 0) -> None:
+        """Queues the batched test; updates queued on the members afterwards stay
+        held until the next test."""
+        gss_batch_test_async(self.b, flags)
+        for c in self.contexts:
+            c._held_by_test, c._held = c._held, []
+
+    def wait(self) -> np.ndarray:
+        try:
+            return gss_batch_wait(self.b, len(self.contexts))
+        finally:
+            for c in self.contexts:
+                c._held_by_test = []
 
     def info(self) -> dict:
         return gss_batch_info(self.b)

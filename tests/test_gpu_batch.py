@@ -161,6 +161,90 @@ def test_batch_with_queued_deltas_and_their_errors():
         it[1].close()
 
 
+def test_batch_async_with_the_next_round_queued_behind_it():
+    """gss_batch_test_async, then the next round's deltas queued while it runs,
+    then gss_batch_wait: each round equals the oracle on the values queued before
+    its launch.  While the batch is in flight its members refuse direct tests and
+    waits, and the batch refuses a second launch."""
+    import torch
+    _, items = _make(8)
+    rng = np.random.default_rng(10)
+
+    def queue_round():
+        for it in items:
+            w, ctx, vals = it
+            vs = np.sort(rng.choice(w.n_vars, max(1, w.n_vars // 20), replace=False)).astype(np.uint32) + 1
+            vals[:, vs - 1] = -vals[:, vs - 1]
+            ctx.set_var_values_async(0, vs, torch.from_numpy(np.ascontiguousarray(vals[:, vs - 1].T)).cuda())
+
+    with gss.Batch([it[1] for it in items]) as b:
+        b.test(0)  # sizes the report segments
+        queue_round()
+        for rep in range(4):
+            at_launch = [it[2].copy() for it in items]
+            b.test_async(gss.GSS_TEST_GRAPH)
+            if rep == 0:
+                ctx = items[2][1]
+                for call in (lambda: ctx.test(0), ctx.test_wait, ctx.fetch_reports,
+                             lambda: b.test(0), lambda: b.test_async(0)):
+                    with pytest.raises(gss.GssError) as e:
+                        call()
+                    assert e.value.code == gss.GSS_ERR_STATE
+            queue_round()  # the next round, behind the test in flight
+            counts = b.wait()
+            print(f"async batch, round {rep}", flush=True)
+            for (w, ctx, _), vals, n in zip(items, at_launch, counts):
+                got = _dense(ctx, w.n_clauses)
+                assert int(np.count_nonzero(got)) == int(n)
+                want = oracle.masks(w.lits, w.offsets, vals)
+                assert np.array_equal(got, want), mismatch_summary(got, want)
+        with pytest.raises(gss.GssError) as e:
+            b.wait()
+        assert e.value.code == gss.GSS_ERR_STATE
+        counts = b.test(0)  # the last queued round
+        _check_all(items, counts)
+    for it in items:
+        it[1].close()
+
+
+def test_batch_async_overflow():
+    """Stores that overflow in an asynchronous batched test: with nothing changed
+    since the launch the wait repeats the batch (exact records); with a change
+    queued behind the launch the wait reports the overflow (the segments are
+    grown), and the next test fits."""
+    import torch
+    stream = torch.cuda.Stream()
+    items = []
+    for i, (n, v, a) in enumerate([(20000, 300, 256), (3000, 900, 64)]):
+        w = gen.paper(900 + i, n_clauses=n, n_vars=v, n_slots=a, planted_rate=0.0)
+        ctx = gss.Context(v, a, stream=stream, report_capacity=64)
+        ctx.add_clauses(w.lits, w.offsets)
+        vals = w.values.copy() if i == 0 else np.zeros_like(w.values)  # store 1: all U, no records
+        ctx.set_assignments(0, vals)
+        items.append([w, ctx, vals])
+    with gss.Batch([it[1] for it in items]) as b:
+        b.test_async(0)
+        counts = b.wait()  # store 0 overflowed, grown and repeated inside the wait
+        _check_all(items, counts)
+        assert counts[1] == 0
+        # store 1 takes its real values (records far beyond its minimal segments),
+        # and one variable is queued again behind the launch
+        w, ctx, vals = items[1]
+        vs = np.arange(1, w.n_vars + 1, dtype=np.uint32)
+        new = w.values.copy()
+        ctx.set_var_values_async(0, vs, torch.from_numpy(np.ascontiguousarray(new.T)).cuda())
+        b.test_async(0)
+        ctx.set_var_values_async(0, vs[:1], torch.from_numpy(np.ascontiguousarray(new[:, :1].T)).cuda())
+        vals[:] = new
+        with pytest.raises(gss.GssError) as e:
+            b.wait()
+        assert e.value.code == gss.GSS_ERR_REPORT_OVERFLOW
+        counts = b.test(0)  # fits now
+        _check_all(items, counts)
+    for it in items:
+        it[1].close()
+
+
 def test_batch_refuses_a_member_with_an_async_test_in_flight():
     """The batched test would overwrite the report segments of a member whose own
     asynchronous test is still pending: it is refused before anything is queued,
