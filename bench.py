@@ -575,12 +575,12 @@ def main():
     ap.add_argument("--learn-clauses", type=int, default=8_000_000)
     ap.add_argument("--learn-vars", type=int, default=2_000_000)
     ap.add_argument("--learn-train-runs", type=int, default=24)
-    ap.add_argument("--learn-eval-runs", type=int, default=32)
+    ap.add_argument("--learn-eval-runs", type=int, default=128)
     ap.add_argument("--learn-epochs", type=int, default=2)
     ap.add_argument("--learn-sample-period", type=int, default=64)
-    ap.add_argument("--learn-rescore", type=int, default=32,
+    ap.add_argument("--learn-rescore", type=int, default=128,
                     help="score every clause every K runs (only the changed ones in between)")
-    ap.add_argument("--learn-update", type=int, default=4, help="rescore the changed clauses every U runs")
+    ap.add_argument("--learn-update", type=int, default=16, help="rescore the changed clauses every U runs")
     ap.add_argument("--learn-lr", type=float, default=3e-3)
     ap.add_argument("--learn-quantile", type=float, default=0.004,
                     help="threshold: the score under which this fraction of the training positives fall")
