@@ -341,6 +341,89 @@ def table1_words(rng, n):
     return f, t
 
 
+def bench_wide(args, torch, gss):
+    """Rows wider than 4096 slots and the aggregate of aggregates (Section 7): a
+    store tested against 16384 assignments (256 words in 4 super-groups of 4096
+    slots).  Assignments are hierarchical: per super-group each variable draws a
+    Table 1 value subset, each word keeps part of it, each slot draws inside its
+    word's subset.  Times the test kernel without and with the aggregate pre-test
+    (super-groups, then words, then slots), in both modes, and reports how many
+    (clause, super-group) and (clause, word) aggregate tests are negative (numpy,
+    from the definition, on a sample of clauses) and what the kernel's pre-test
+    settled (GSS_TEST_COUNT)."""
+    from paper_2012_03119_amd import gen
+    V, N, S = args.wide_vars, args.wide_clauses, args.wide_slots
+    n_super, n_words = S // 4096, S // 64
+    rng = np.random.default_rng(args.seed + 700)
+    t0 = time.perf_counter()
+    lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, N), V)
+    vals = gen.assignments_hierarchical(rng, n_super, V)
+    log(f"wide workload ready in {time.perf_counter() - t0:.1f} s: {N} clauses over {V} variables, {S} slots")
+    ctx = gss.Context(V, S, report_capacity=1 << 22)
+    ctx.add_clauses(lits, offs)
+    ctx.set_assignments(0, vals)
+    AGG, TRIG = gss.GSS_TEST_AGGREGATE, gss.GSS_TEST_TRIGGER
+    forms = {}
+    for name, flags in (("falsified", 0), ("falsified_aggregate", AGG), ("trigger", TRIG),
+                        ("trigger_aggregate", TRIG | AGG)):
+        for _ in range(2):
+            ctx.test(flags)
+        torch.cuda.synchronize()
+        ctx.reset_stats()
+        for _ in range(args.steps):
+            n = ctx.test(flags)
+        st = ctx.stats()
+        forms[name] = {"kernel_ms": st["total_kernel_ms"] / max(1, st["timed_launches"]), "reports": int(n)}
+    settled = {}
+    for name, flags in (("falsified", AGG), ("trigger", TRIG | AGG)):
+        ctx.test(flags | gss.GSS_TEST_COUNT)
+        st = ctx.stats()
+        settled[name] = st["last_agg_settled"] / (st["live_clauses"] * n_words)
+    pairs = ctx.stats()["last_pairs"]
+    ctx.close()
+    # Definition 7, falsified: an aggregate test is negative when some literal of the
+    # clause is F in no slot of the group.  F-anywhere per (variable, group, sign).
+    slots_f, slots_t = (vals == -1), (vals == 1)
+    f_word = slots_f.reshape(n_words, 64, V).any(axis=1)    # [word][var]: v is F in some slot
+    t_word = slots_t.reshape(n_words, 64, V).any(axis=1)
+    f_sup = f_word.reshape(n_super, 64, V).any(axis=1)      # [super-group][var]
+    t_sup = t_word.reshape(n_super, 64, V).any(axis=1)
+    n_s = min(N, 20_000)
+    neg_sup = neg_word = neg_word_in_pos_sup = pos_sup = 0
+    for c in range(n_s):
+        cl = lits[offs[c]:offs[c + 1]]
+        v = np.abs(cl) - 1
+        pos = cl > 0  # a positive literal is F where its variable is F
+        sup_ok = np.where(pos[None, :], f_sup[:, v], t_sup[:, v]).all(axis=1)     # [n_super]
+        word_ok = np.where(pos[None, :], f_word[:, v], t_word[:, v]).all(axis=1)  # [n_words]
+        neg_sup += int((~sup_ok).sum())
+        neg_word += int((~word_ok).sum())
+        ok_rows = np.repeat(sup_ok, 64)
+        pos_sup += int(ok_rows.sum())
+        neg_word_in_pos_sup += int((~word_ok & ok_rows).sum())
+    ratios = {"super_group_negative": neg_sup / (n_s * n_super), "word_negative": neg_word / (n_s * n_words),
+              "word_negative_where_super_group_positive": neg_word_in_pos_sup / max(pos_sup, 1),
+              "sample_clauses": n_s}
+    plain_ms = forms["falsified"]["kernel_ms"]
+    agg_ms = forms["falsified_aggregate"]["kernel_ms"]
+    out = {
+        "metric": "clause x assignment tests/sec (wide rows: aggregate of aggregates, falsified)",
+        "value": pairs / (agg_ms * 1e-3), "unit": "tests/s", "n_gpus": 1, "steps": args.steps, "warmup": 2,
+        "ms_per_step": agg_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"wide rows: {N} clauses (length mix) over {V} variables x {S} hierarchical "
+                               f"assignments ({n_super} super-groups of 64 words, Table 1 subsets, each word "
+                               f"keeping 70% of its super-group's values)"},
+        "forms": forms, "aggregate_speedup": plain_ms / agg_ms,
+        "aggregate_speedup_trigger": forms["trigger"]["kernel_ms"] / forms["trigger_aggregate"]["kernel_ms"],
+        "negative_ratios": ratios, "kernel_pretest_settled_ratio": settled,
+    }
+    log(f"wide: plain {plain_ms:.3f} ms, aggregate {agg_ms:.3f} ms ({plain_ms / agg_ms:.2f}x); trigger "
+        f"{forms['trigger']['kernel_ms']:.3f} / {forms['trigger_aggregate']['kernel_ms']:.3f} ms; negative: super "
+        f"{ratios['super_group_negative']:.4f}, word {ratios['word_negative']:.4f}; settled {settled}")
+    print(json.dumps(out), flush=True)
+
+
 def recency_params():
     """Hit recency as a network: any hit in the last 8 tested runs scores ~1, none
     scores 0.27 (weights set by hand)."""
@@ -571,7 +654,10 @@ def main():
                     help="plain workloads: time every n-th test kernel launch with HIP events (1: every one)")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["paper", "tiny", "batched", "served", "learned"], default="paper")
+    ap.add_argument("--workload", choices=["paper", "tiny", "batched", "served", "learned", "wide"], default="paper")
+    ap.add_argument("--wide-clauses", type=int, default=1_000_000)
+    ap.add_argument("--wide-vars", type=int, default=50_000)
+    ap.add_argument("--wide-slots", type=int, default=16384, help="a multiple of 4096")
     ap.add_argument("--learn-clauses", type=int, default=8_000_000)
     ap.add_argument("--learn-vars", type=int, default=2_000_000)
     ap.add_argument("--learn-train-runs", type=int, default=24)
@@ -642,6 +728,9 @@ def main():
         return
     if args.workload == "served":
         bench_served(args, torch, gss)
+        return
+    if args.workload == "wide":
+        bench_wide(args, torch, gss)
         return
     if args.workload == "learned":
         bench_learned(args, torch, gss)
