@@ -59,7 +59,9 @@ def test_oracle_under_asan_and_ubsan(tmp_path):
     lib = os.path.join(OUT_DIR, "liboracle_sanitized.so")
     subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fopenmp", "-shared", "-fPIC",
                            "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-o", lib, SRC])
-    env = dict(os.environ, ORACLE_LIBRARY=lib, LD_PRELOAD=asan,
+    # The sanitizer runtime must come first; whatever the environment already preloads stays after it.
+    preload = ":".join(p for p in (asan, os.environ.get("LD_PRELOAD", "")) if p)
+    env = dict(os.environ, ORACLE_LIBRARY=lib, LD_PRELOAD=preload,
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1",
                PYTHONPATH=ROOT)
     r = subprocess.run([sys.executable, "-c", CHILD], env=env, capture_output=True, text=True, timeout=300)
