@@ -11,7 +11,10 @@
 //
 // State is kept per clause id (structure of arrays, grown with the id space):
 // length, LBD, birth run, source thread, alive flag, 8 hit counts (16 bits each,
-// one 16-byte word), this run's hit count, score and low flag.  The schedule bits the test kernel reads are
+// one 16-byte word), this run's hit count, score and low flag, and two flag
+// bytes (the history is nonzero; the test being observed reported the clause), so
+// that the observation after a run reads the history and the hit count only where
+// they can be nonzero.  The schedule bits the test kernel reads are
 // per slot of each length class, rebuilt from the low flags when the store or
 // the scores changed.
 #include "mlp.h"
@@ -34,6 +37,8 @@ struct Priority {
     float *act = nullptr;  // activity (Section 3.7)
     uint8_t *alive = nullptr, *low = nullptr;
     uint8_t *dirty = nullptr;  // features changed (beyond age) since the clause was last scored
+    uint8_t *hnz = nullptr;    // the history holds a nonzero count
+    uint8_t *rec = nullptr;    // the test being observed reported the clause (its hit count is nonzero)
     float *sx = nullptr, *sy = nullptr;  // samples [sample_cap][kFeat], [sample_cap]
     uint32_t *counters = nullptr;        // [0] samples taken, [1] low clauses of the last scoring
     uint32_t *h_counters = nullptr;      // pinned copy
@@ -67,12 +72,13 @@ struct ProbeArgs {  // per-id arrays as the kernels see them
     uint32_t *len, *birth, *src, *hits;
     uint4 *hist;
     float *lbd, *score, *act;
-    uint8_t *alive, *low, *dirty;
+    uint8_t *alive, *low, *dirty, *hnz, *rec;
     uint64_t cap;
 };
 
 ProbeArgs args_of(const Priority &p) {
-    return ProbeArgs{p.len, p.birth, p.src, p.hits, p.hist, p.lbd, p.score, p.act, p.alive, p.low, p.dirty, p.cap};
+    return ProbeArgs{p.len, p.birth, p.src,   p.hits,  p.hist, p.lbd, p.score,
+                     p.act, p.alive, p.low,   p.dirty, p.hnz,  p.rec, p.cap};
 }
 
 __device__ inline void load_features(const ProbeArgs &a, uint64_t id, uint32_t run, float src_scale,
@@ -98,6 +104,8 @@ __global__ void k_prio_init(ProbeArgs a, uint64_t first, uint32_t n, const uint3
     a.alive[id] = 1;
     a.low[id] = 0;
     a.dirty[id] = 1;
+    a.hnz[id] = 0;
+    a.rec[id] = 0;
     a.score[id] = 1.f;
     a.act[id] = 0.f;
 }
@@ -155,49 +163,89 @@ __device__ inline void block_add(int32_t v, uint32_t *counter) {
     if (threadIdx.x == 0 && total) atomicAdd(counter, total);  // wraps for negative sums
 }
 
-// Hit counts of the last run: one workgroup per report segment.
+// Hit counts of the last run: one workgroup per report segment.  A clause's
+// records may sit in several segments; the threads that flag it all store 1.
 __global__ void k_prio_hits(ProbeArgs a, const gss_report *reports, const uint32_t *counts, uint32_t seg_cap,
                             uint32_t n_segments) {
     for (uint32_t s = blockIdx.x; s < n_segments; s += gridDim.x) {
         const uint32_t n = min(counts[s], seg_cap);
         const gss_report *seg = reports + (uint64_t)s * seg_cap;
-        for (uint32_t r = threadIdx.x; r < n; r += blockDim.x)
-            atomicAdd(&a.hits[seg[r].clause_id], (uint32_t)__popcll(seg[r].mask));
+        for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
+            const uint32_t id = seg[r].clause_id;
+            atomicAdd(&a.hits[id], (uint32_t)__popcll(seg[r].mask));
+            a.rec[id] = 1;
+        }
     }
 }
 
 // After a run: samples, history shift, hit counter reset.  Each lane takes
-// kObserve ids (strided by the workgroup size) and issues all their loads before
-// it uses any, so that a lane waits for memory once per phase rather than once
-// per id; the workgroup claims its sample rows with one atomic.
+// kObserve ids (strided by the workgroup size) and moves them through three
+// phases: their flag bytes (alive, low, history nonzero, reported); then the hit counts, the
+// histories and the activities the flags call for; then the stores.  Within a
+// phase every load is issued before any is used, and no load sits under a branch
+// (a lane that needs no value reads the workgroup's first element instead, a line
+// all such lanes share), so that a lane waits for memory once per phase rather than
+// once per id.  Most clauses neither hit nor carry a nonzero history, so their
+// lanes read four bytes per id.  The arrays are addressed from the workgroup's
+// first id (a uniform base) with 32-bit lane offsets.  The workgroup claims its
+// sample rows with one atomic.  SAMPLE is false when no samples are taken (period 0).
 constexpr uint32_t kObserve = 8;
 
+template <bool SAMPLE>
 __global__ __launch_bounds__(256) void k_prio_observe(ProbeArgs a, uint64_t n_ids, uint32_t run, uint32_t scheduled,
                                                       float src_scale, uint32_t period, uint64_t seed, float *sx,
                                                       float *sy, uint64_t sample_cap, uint32_t *counters, float bump) {
     __shared__ uint32_t base_s;
-    const uint64_t first = (uint64_t)blockIdx.x * 256 * kObserve + threadIdx.x;
-    uint32_t h[kObserve];
-    uint32_t live = 0, low = 0, tested = 0, sample = 0;  // bit k: id first + 256 k
+    const uint64_t base = (uint64_t)blockIdx.x * 256 * kObserve;  // below n_ids: the grid covers n_ids
+    const uint8_t *alive = a.alive + base, *lowf = a.low + base;
+    uint8_t *hnzf = a.hnz + base, *recf = a.rec + base, *dirty = a.dirty + base;
+    uint32_t *hits = a.hits + base;
+    uint4 *hist = a.hist + base;
+    float *act = a.act + base;
+    // lane offset of the k-th id (below 256 kObserve, so 32 bits hold every byte offset)
+    auto off = [](uint32_t k) { return threadIdx.x + k * 256u; };
+    auto at = [&](uint32_t k, uint32_t need) { return ((need >> k) & 1u) ? off(k) : 0u; };
+    uint32_t in = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kObserve; ++k) in |= (base + off(k) < n_ids ? 1u : 0u) << k;
+    uint32_t al[kObserve], lo[kObserve], hz[kObserve], rc[kObserve];
 #pragma unroll
     for (uint32_t k = 0; k < kObserve; ++k) {
-        const uint64_t id = first + (uint64_t)k * 256;
-        const bool in = id < n_ids;
-        const uint32_t al = in ? a.alive[id] : 0u, lo = in ? a.low[id] : 0u;
-        h[k] = in ? a.hits[id] : 0u;
-        live |= (al ? 1u : 0u) << k;
-        low |= (lo ? 1u : 0u) << k;
+        al[k] = alive[at(k, in)];
+        lo[k] = lowf[at(k, in)];
+        hz[k] = hnzf[at(k, in)];
+        rc[k] = recf[at(k, in)];
+    }
+    uint32_t live = 0, low = 0, nz = 0, hit = 0, tested = 0, sample = 0;  // bit k: id base + off(k)
+#pragma unroll
+    for (uint32_t k = 0; k < kObserve; ++k) {
+        const bool i = (in >> k) & 1u;
+        live |= (i && al[k] ? 1u : 0u) << k;
+        low |= (i && lo[k] ? 1u : 0u) << k;
+        nz |= (i && hz[k] ? 1u : 0u) << k;
+        hit |= (i && rc[k] ? 1u : 0u) << k;
     }
 #pragma unroll
     for (uint32_t k = 0; k < kObserve; ++k) {
-        const uint64_t id = first + (uint64_t)k * 256;
+        const uint64_t id = base + off(k);
         const bool skipped = scheduled && ((low >> k) & 1u) && ((run + (uint32_t)id) & 3u) != 0;
         const bool t = ((live >> k) & 1u) && !skipped;
         tested |= (t ? 1u : 0u) << k;
-        if (period) sample |= (t && mix64(seed ^ (id << 32) ^ run) % period == 0 ? 1u : 0u) << k;
+        if (SAMPLE) sample |= (t && mix64(seed ^ (id << 32) ^ run) % period == 0 ? 1u : 0u) << k;
     }
+    // a clause without records has a zero count, one with a zero history a zero word
+    const uint32_t need_hist = tested & nz, bumped = live & hit;
+    uint32_t h[kObserve];
+    float ac[kObserve];
+#pragma unroll
+    for (uint32_t k = 0; k < kObserve; ++k) {
+        h[k] = hits[at(k, hit)];
+        ac[k] = act[at(k, bumped)];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kObserve; ++k) h[k] = ((hit >> k) & 1u) ? h[k] : 0u;
     uint32_t pos = 0;
-    if (period) {  // uniform: sample rows are claimed only while samples are taken
+    if (SAMPLE) {  // sample rows are claimed only while samples are taken
         const uint32_t mine = __popc(sample);
         uint32_t total = 0;
         pos = block_inclusive_sum(mine, total) - mine;
@@ -206,12 +254,11 @@ __global__ __launch_bounds__(256) void k_prio_observe(ProbeArgs a, uint64_t n_id
         pos += base_s;
     }
     // samples take the features as they were before this run, labelled by its hits
-    for (uint32_t k = 0; k < kObserve && sample; ++k) {
+    for (uint32_t k = 0; SAMPLE && k < kObserve && sample; ++k) {
         if (!((sample >> k) & 1u)) continue;
-        const uint64_t id = first + (uint64_t)k * 256;
         if (pos < sample_cap) {
             float x[kFeat];
-            load_features(a, id, run, src_scale, x);
+            load_features(a, base + off(k), run, src_scale, x);
 #pragma unroll
             for (int q = 0; q < kFeat; ++q) sx[(uint64_t)pos * kFeat + q] = x[q];
             sy[pos] = h[k] ? 1.f : 0.f;
@@ -220,24 +267,28 @@ __global__ __launch_bounds__(256) void k_prio_observe(ProbeArgs a, uint64_t n_id
     }
     uint4 v[kObserve];
 #pragma unroll
-    for (uint32_t k = 0; k < kObserve; ++k)
-        v[k] = ((tested >> k) & 1u) ? a.hist[first + (uint64_t)k * 256] : make_uint4(0, 0, 0, 0);
+    for (uint32_t k = 0; k < kObserve; ++k) v[k] = hist[at(k, need_hist)];
 #pragma unroll
     for (uint32_t k = 0; k < kObserve; ++k) {
-        const uint64_t id = first + (uint64_t)k * 256;
+        const uint32_t nzk = (nz >> k) & 1u;
         // a tested clause shifts in this run's count (a history of zeros stays as it is)
-        if (((tested >> k) & 1u) && (h[k] || (v[k].x | v[k].y | v[k].z | v[k].w))) {
+        if (((tested >> k) & 1u) && (h[k] || nzk)) {
+            const uint4 o = nzk ? v[k] : make_uint4(0, 0, 0, 0);
             const uint32_t hc = min(h[k], 0xFFFFu);  // at most 64 x 64 slots: never clipped
-            a.hist[id] = make_uint4((v[k].x << 16) | hc, (v[k].y << 16) | (v[k].x >> 16),
-                                    (v[k].z << 16) | (v[k].y >> 16), (v[k].w << 16) | (v[k].z >> 16));
+            const uint4 w = make_uint4((o.x << 16) | hc, (o.y << 16) | (o.x >> 16), (o.z << 16) | (o.y >> 16),
+                                       (o.w << 16) | (o.z >> 16));
+            hist[off(k)] = w;
+            const uint32_t now = (w.x | w.y | w.z | w.w) ? 1u : 0u;
+            if (now != nzk) hnzf[off(k)] = (uint8_t)now;
             // rescored by the next update only where its side of the threshold may
             // change: a low clause that hit, a high one that did not (the next full
             // scoring catches everything else)
-            if (((low >> k) & 1u) ? h[k] != 0 : h[k] == 0) a.dirty[id] = 1;
+            if (((low >> k) & 1u) ? h[k] != 0 : h[k] == 0) dirty[off(k)] = 1;
         }
-        if (((live >> k) & 1u) && h[k]) {
-            a.act[id] += bump;  // Section 3.7: bumped whenever the clause triggers
-            a.hits[id] = 0;
+        if (((live >> k) & 1u) && h[k]) {  // the count and its flag are cleared together (a dead clause keeps both)
+            act[off(k)] = ac[k] + bump;  // Section 3.7: bumped whenever the clause triggers
+            hits[off(k)] = 0;
+            recf[off(k)] = 0;
         }
     }
 }
@@ -253,6 +304,7 @@ __global__ void k_prio_bump(ProbeArgs a, const gss_report *reports, const uint32
         for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
             const uint32_t id = seg[r].clause_id;
             if (atomicExch(&a.hits[id], 0u) != 0u) a.act[id] += bump;  // the first record of the clause
+            a.rec[id] = 0;
         }
     }
 }
@@ -426,22 +478,32 @@ __global__ __launch_bounds__(256) void k_prio_score_mfma(ProbeArgs a, const floa
 }
 
 // The dirty live clauses, compacted into a list (counters[2] = its length), so
-// that the network runs on dense wavefronts rather than on scattered lanes.
+// that the network runs on dense wavefronts rather than on scattered lanes.  The
+// flag bytes are loaded once, all in flight together (an id past the end reads
+// the workgroup's first byte instead, and is not counted).
 __global__ __launch_bounds__(256) void k_prio_collect(ProbeArgs a, uint64_t n_ids, uint32_t *list, uint32_t *counters) {
     __shared__ uint32_t base_s;
-    const uint64_t first = (uint64_t)blockIdx.x * 256 * kPerThread + threadIdx.x;
-    auto is_dirty = [&](uint64_t id) { return id < n_ids && a.alive[id] && a.dirty[id]; };
-    uint32_t mine = 0;
-    for (uint32_t k = 0; k < kPerThread; ++k) mine += is_dirty(first + (uint64_t)k * 256) ? 1u : 0u;
+    const uint64_t base = (uint64_t)blockIdx.x * 256 * kPerThread;  // below n_ids: the grid covers n_ids
+    const uint8_t *alive = a.alive + base, *dirty = a.dirty + base;
+    uint32_t al[kPerThread], di[kPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kPerThread; ++k) {
+        const uint32_t o = base + threadIdx.x + k * 256u < n_ids ? threadIdx.x + k * 256u : 0u;
+        al[k] = alive[o];
+        di[k] = dirty[o];
+    }
+    uint32_t flags = 0;  // bit k: id base + threadIdx.x + 256 k is live and dirty
+#pragma unroll
+    for (uint32_t k = 0; k < kPerThread; ++k)
+        flags |= (base + threadIdx.x + k * 256u < n_ids && al[k] && di[k] ? 1u : 0u) << k;
+    const uint32_t mine = __popc(flags);
     uint32_t total = 0;
     uint32_t pos = block_inclusive_sum(mine, total) - mine;
     if (threadIdx.x == 0) base_s = total ? atomicAdd(&counters[2], total) : 0u;
     __syncthreads();
     pos += base_s;
-    for (uint32_t k = 0; k < kPerThread; ++k) {
-        const uint64_t id = first + (uint64_t)k * 256;
-        if (is_dirty(id)) list[pos++] = (uint32_t)id;
-    }
+    for (uint32_t f = flags; f; f &= f - 1)
+        list[pos++] = (uint32_t)(base + threadIdx.x + 256u * (uint32_t)__builtin_ctz(f));
 }
 
 
@@ -536,6 +598,8 @@ void grow(Ctx &c, Priority &p, uint64_t need) {
     move(p.alive, 1, 1);
     move(p.low, 1, 1);
     move(p.dirty, 1, 1);
+    move(p.hnz, 1, 1);
+    move(p.rec, 1, 1);
     p.cap = cap;
 }
 
@@ -667,7 +731,7 @@ void priority_release(Ctx &c) {
     Priority *p = c.prio;
     if (!p) return;
     for (void *q : {(void *)p->len, (void *)p->birth, (void *)p->src, (void *)p->hits, (void *)p->hist, (void *)p->lbd,
-                    (void *)p->score, (void *)p->act, (void *)p->alive, (void *)p->low, (void *)p->dirty, (void *)p->sx, (void *)p->sy,
+                    (void *)p->score, (void *)p->act, (void *)p->alive, (void *)p->low, (void *)p->dirty, (void *)p->hnz, (void *)p->rec, (void *)p->sx, (void *)p->sy,
                     (void *)p->counters, (void *)p->params, (void *)p->list})
         c.dfree(q);
     if (p->h_counters) (void)hipHostFree(p->h_counters);
@@ -781,8 +845,8 @@ extern "C" gss_status gss_priority_observe(gss_ctx *ctx) {
                            args_of(p), c.reports, c.seg_counts, c.seg_cap, c.last_waves);
     GSS_HIP(hipGetLastError());
     if (p.n_ids)
-        hipLaunchKernelGGL(k_prio_observe, dim3(grid_of(p.n_ids, 256 * kObserve)), dim3(256), 0, c.stream, args_of(p),
-                           p.n_ids, p.run,
+        hipLaunchKernelGGL(p.cfg.sample_period ? k_prio_observe<true> : k_prio_observe<false>,
+                           dim3(grid_of(p.n_ids, 256 * kObserve)), dim3(256), 0, c.stream, args_of(p), p.n_ids, p.run,
                            (c.last_flags & GSS_TEST_SCHEDULED) ? 1u : 0u, src_scale(p), p.cfg.sample_period,
                            p.cfg.seed, p.sx, p.sy, p.cfg.sample_capacity, p.counters, (float)p.bump);
     GSS_HIP(hipGetLastError());

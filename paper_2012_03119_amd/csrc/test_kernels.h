@@ -135,7 +135,8 @@ __global__ __launch_bounds__(kTestWavesPerBlock * 64) void k_test_list(const Buc
 // whose block range holds g, 32 per thread (one word of schedule bits; their 256
 // bytes of metadata are loaded at once), and claims its range of the class's
 // list with one atomic on its count (one per 8192 slots: the counters see few
-// atomics).  In slot order within a workgroup.
+// atomics).  In slot order within a workgroup: the workgroup's part of the list is
+// assembled in LDS and written out in whole lines.
 constexpr uint32_t kSchedThreads = 256, kSchedSlots = 32 * kSchedThreads;
 
 struct SchedClass {
@@ -154,7 +155,8 @@ struct SchedTable {
 
 __global__ __launch_bounds__(kSchedThreads) void k_sched_list(const SchedTable tab, uint32_t run) {
     __shared__ uint32_t wave_sum[kSchedThreads / 64];
-    __shared__ uint32_t base;
+    __shared__ uint32_t base, total;
+    __shared__ uint32_t stage[kSchedSlots];
     uint32_t b = 0;
     while (b + 1 < tab.n && blockIdx.x >= tab.cls[b + 1].block_begin) ++b;
     const SchedClass &C = tab.cls[b];
@@ -200,10 +202,13 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched_list(const SchedTable t
             acc += v;
         }
         base = acc ? atomicAdd(C.count, acc) : 0u;
+        total = acc;
     }
     __syncthreads();
-    uint32_t pos = base + wave_sum[wave] + x - mine;
-    for (uint32_t f = flags; f; f &= f - 1) C.list[pos++] = s0 + (uint32_t)__builtin_ctz(f);
+    uint32_t pos = wave_sum[wave] + x - mine;  // below kSchedSlots: at most 32 per thread
+    for (uint32_t f = flags; f; f &= f - 1) stage[pos++] = s0 + (uint32_t)__builtin_ctz(f);
+    __syncthreads();
+    for (uint32_t i = t; i < total; i += kSchedThreads) C.list[base + i] = stage[i];
 }
 
 // summary[3] receives the verdict of the asynchronous updates queued before the
