@@ -440,13 +440,31 @@ __device__ inline void finalize_segments(const uint32_t *counts, uint32_t n, uin
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t per = (n + 1023) / 1024;
     const uint32_t lo = min(n, tid * per), hi = min(n, lo + per);
+    // Up to kHeld counts a thread (16384 segments) are loaded all at once, from
+    // addresses clamped into the array, and kept for the second pass; beyond that
+    // the thread walks its range twice.
+    constexpr uint32_t kHeld = 16;
+    const bool held = per <= kHeld;
+    uint32_t v[kHeld];
+#pragma unroll
+    for (uint32_t k = 0; k < kHeld; ++k) v[k] = (held && n) ? counts[min(lo + k, n - 1)] : 0u;
     unsigned long long kept = 0, all = 0;
     unsigned int m = 0;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t v = counts[i];
-        kept += min(v, cap);
-        all += v;
-        m = max(m, v);
+    if (held) {
+#pragma unroll
+        for (uint32_t k = 0; k < kHeld; ++k) {
+            const uint32_t c = lo + k < hi ? v[k] : 0u;
+            kept += min(c, cap);
+            all += c;
+            m = max(m, c);
+        }
+    } else {
+        for (uint32_t i = lo; i < hi; ++i) {
+            const uint32_t c = counts[i];
+            kept += min(c, cap);
+            all += c;
+            m = max(m, c);
+        }
     }
     // inclusive scan of kept within the wavefront; sum and max over it
     unsigned long long x = kept, a = all;
@@ -474,9 +492,17 @@ __device__ inline void finalize_segments(const uint32_t *counts, uint32_t n, uin
         mx = max(mx, wmax[w]);
     }
     unsigned long long base = before + x - kept;
-    for (uint32_t i = lo; i < hi; ++i) {
-        offsets[i] = base;
-        base += min(counts[i], cap);
+    if (held) {
+#pragma unroll
+        for (uint32_t k = 0; k < kHeld; ++k) {
+            if (lo + k < hi) offsets[lo + k] = base;
+            base += lo + k < hi ? min(v[k], cap) : 0u;
+        }
+    } else {
+        for (uint32_t i = lo; i < hi; ++i) {
+            offsets[i] = base;
+            base += min(counts[i], cap);
+        }
     }
     if (tid == 0) {
         offsets[n] = total_kept;
