@@ -157,6 +157,65 @@ def test_scheduled_test_equals_oracle_on_scheduled_clauses():
             ctx.priority_observe()
 
 
+def test_scheduled_runs_follow_new_marks_and_store_changes():
+    """The slots a scheduled run tests follow the store, the schedule bits and the
+    run number mod 4: twelve runs in a row, then a new marking, then removals and
+    insertions, and a marking again; every run equals the oracle on the clauses
+    the schedule tests."""
+    rng = np.random.default_rng(17)
+    V, n_words, n = 3000, 4, 20_000
+    lits, offs = gen.random_clauses(rng, gen.lengths_mix(rng, n), V)
+    vals = _stream_values(rng, n_words, V)
+    clauses = {}  # live id -> literals
+    with new_context(V, 64 * n_words) as ctx:
+        ids = ctx.add_clauses(lits, offs)
+        assert (ids == np.arange(n)).all()
+        for k, i in enumerate(ids):
+            clauses[int(i)] = lits[offs[k]:offs[k + 1]]
+        ctx.priority_enable(n_sources=1, seed=1)
+        ctx.set_assignments(0, vals)
+        low = (rng.random(n) < 0.6).astype(np.uint8)  # one flag per issued id
+        ctx.priority_mark(low)
+
+        def check(tag):
+            run = ctx.priority_info()["run"]
+            print(f"[scheduled] {tag}: run {run}", flush=True)
+            m = ctx.test(gss.GSS_TEST_SCHEDULED)
+            got = np.sort(ctx.fetch_reports(m), order=["clause_id", "word"])
+            live = np.array(sorted(clauses), dtype=np.int64)
+            l_lits = np.concatenate([clauses[i] for i in live])
+            l_offs = np.concatenate([[0], np.cumsum([len(clauses[i]) for i in live])]).astype(np.int64)
+            full = oracle.masks(l_lits, l_offs, vals)
+            keep = P.tested(live, low[live], run)
+            want = oracle.report_set(np.where(keep[:, None], full, np.uint64(0)), live.astype(np.uint32))
+            assert len(got) == len(want) and (got == want).all(), f"{tag}: run {run}"
+            ctx.priority_observe()
+
+        for _ in range(12):
+            check("same store and marks")
+        low = (rng.random(n) < 0.3).astype(np.uint8)
+        ctx.priority_mark(low)
+        for _ in range(6):
+            check("new marks")
+        gone = rng.choice(n, size=3000, replace=False)
+        ctx.remove_clauses(gone.astype(np.uint32))
+        for i in gone:
+            del clauses[int(i)]
+        m2 = 2000
+        lits2, offs2 = gen.random_clauses(rng, gen.lengths_mix(rng, m2), V)
+        ids2 = ctx.add_clauses(lits2, offs2)
+        assert (ids2 == np.arange(n, n + m2)).all()
+        for k, i in enumerate(ids2):
+            clauses[int(i)] = lits2[offs2[k]:offs2[k + 1]]
+        low = np.concatenate([low, np.zeros(m2, np.uint8)])  # new clauses start high
+        for _ in range(5):
+            check("removals and insertions")
+        low = (rng.random(n + m2) < 0.5).astype(np.uint8)
+        ctx.priority_mark(low)
+        for _ in range(5):
+            check("changed store, new marks")
+
+
 def test_trained_schedule_misses_at_most_one_percent():
     """Train on the hit logs of a stream, pick the threshold on the training
     samples, then run scheduled and plain tests side by side on later runs of the
