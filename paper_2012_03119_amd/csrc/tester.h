@@ -267,15 +267,20 @@ struct Tester {
                 cn = make_uint4(q[0], q[1], q[2], q[3]);
             }
             const uint32_t cs[4] = {c.x, c.y, c.z, c.w};
+            // the group's four bit sets are loaded together (past the clause's end,
+            // code 0's); once af and ou are zero, further steps keep them zero
+            uint64_t cf[4], cu[4];
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u) {
-                if (k + u < len && (af | ou) != 0) {
-                    const uint64_t cf = sagg[cs[u]];
-                    if constexpr (MODE == 1) {
-                        const uint64_t cu = saggu[cs[u] >> 1];
-                        ou = (af & cu) | (ou & cf);
-                    }
-                    af &= cf;
+                const uint32_t code = k + u < len ? cs[u] : 0u;
+                cf[u] = sagg[code];
+                if constexpr (MODE == 1) cu[u] = saggu[code >> 1];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                if (k + u < len) {
+                    if constexpr (MODE == 1) ou = (af & cu[u]) | (ou & cf[u]);
+                    af &= cf[u];
                 }
             }
             c = cn;
